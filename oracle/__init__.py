@@ -1,0 +1,26 @@
+"""CPU FP64 oracle for FCG-NO.  TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path never routes through
+it, and it shares no code with the HIP library; the two meet only through the
+seeded generators in ``synth``.
+
+Every function is written from the paper (Rudikov et al., "Neural operators
+meet conjugate gradients: the FCG-NO method", ICML 2024) and cites the passage
+it follows.  Plain definitions are written out; library primitives (FFT,
+sparse direct solve, autograd) serve as single steps.
+
+Parity status of each function (what pins it, see tests/test_oracle_*.py):
+  stencil_apply / assemble     pinned: sine-mode eigenpairs, Dirichlet energy
+  fcg                          pinned: FCG(I) == textbook CG, PCG(Jacobi),
+                               one-step convergence with A^-1, A-orthogonality,
+                               energy identity, finite termination, Table 1
+  no_apply                     pinned: explicit-sum DFT on tiny grids, identity
+                               and homogeneity special cases, linearity in R
+  notay_loss / l2_loss         pinned: closed-form values on eigenvectors
+  loss gradients (autograd)    pinned: central finite differences
+  jacobi / sgs                 pinned: Table 1 iteration counts (statistical)
+  adamw_step                   pinned: hand-computed first steps
+  Theorem 1's gamma            not used; parity unpinned (not computed)
+"""
+from .fcgno_ref import *  # noqa: F401,F403
