@@ -1,0 +1,158 @@
+/*
+ * fcgno.h -- C ABI of the FCG-NO hot path on AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the linear systems A u = f that the 5-point finite
+ * difference discretisation of -div(k grad u) = f on the unit square with zero
+ * Dirichlet boundary values produces (Sec. 2.1, the general elliptic equation
+ * and the linear system it yields), by flexible conjugate gradients
+ * (Algorithm 1) preconditioned by a Fourier neural operator B(r; theta)
+ * (Sec. 2.4.2), and trains that operator on the energy-norm loss (Sec. 3.1,
+ * the error form of the Notay loss).
+ *
+ * Conventions shared by every entry point
+ *   - N interior points per side, h = 1/(N+1).  Interior fields (f, u, r, w,
+ *     e) are float64 [batch][N][N], row-major, index [i][j] with j (x2)
+ *     contiguous.  Coefficients k are nodal float64 [batch][N+2][N+2]
+ *     including the boundary nodes; node (i+1, j+1) is interior point (i, j).
+ *   - A is applied as h^-2 [(kE+kW+kN+kS) u_ij - kE u_{i+1,j} - kW u_{i-1,j}
+ *     - kN u_{i,j+1} - kS u_{i,j-1}] with face values the mean of the two
+ *     nodal values and u = 0 off the interior.
+ *   - "device" pointers are HIP device memory of the current device, 8-byte
+ *     aligned at least; "host" pointers are ordinary host memory.  The caller
+ *     owns every buffer it passes.  Workspaces are caller-allocated device
+ *     memory of at least the queried size, 256-byte aligned; the library does
+ *     not allocate per call.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Nothing throws across the ABI and nothing aborts.  A negative status
+ *     means the call did nothing useful and outputs are undefined; the text of
+ *     the last error is available from fcgno_last_error().
+ *
+ * Operator weight blob (float64, the order every entry point uses):
+ *   W_L[C][Cin], b_L[C],
+ *   for each of the L layers: Re R[C][C][2M][M], Im R[C][C][2M][M], W[C][C], b[C],
+ *   W_P[C], b_P[1].
+ * R[c][o][a][ky] mixes input channel c into output channel o at mode
+ * (kx, ky) with kx = a for a < M and kx = N - 2M + a otherwise; W[o][c] is the
+ * 1x1 bypass.  The operator is B(r) = s * P(layers(lift(phi))) with
+ * s = ||r||_2 / N, features phi = [r/s, log k, x1, x2], GELU(z) = z/2
+ * (1 + erf(z/sqrt 2)) after every layer; B(0) = 0.
+ */
+#ifndef FCGNO_H
+#define FCGNO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FCGNO_OK = 0,
+    FCGNO_NOT_CONVERGED = 1,   /* non-fatal: some system stopped at max_iter or broke down */
+    FCGNO_E_INVALID = -1,      /* null pointer, bad size, unsupported architecture */
+    FCGNO_E_NOMEM = -2,        /* workspace smaller than required, or device allocation failed */
+    FCGNO_E_HIP = -3,          /* a HIP runtime call failed */
+} fcgno_status;
+
+/* per-system status of a solve */
+enum {
+    FCGNO_SYS_OK = 0,            /* ||r_i|| / ||r_0|| <= rtol reached at iteration iters */
+    FCGNO_SYS_NOT_CONVERGED = 1, /* max_iter reached */
+    FCGNO_SYS_BREAKDOWN = 2,     /* (p_i, A p_i) <= 0 or not finite; the system froze at u_i */
+    FCGNO_SYS_NONFINITE = 3,     /* NaN/Inf in k, f or u0, or k <= 0 at a node; nothing done */
+};
+
+/* arithmetic precision of the operator B; the Krylov part is always float64 */
+enum {
+    FCGNO_OP_FP64 = 0,      /* float64 matrix cores */
+    FCGNO_OP_FP32 = 1,      /* float32 matrix cores */
+    FCGNO_OP_BF16 = 2,      /* bfloat16 inputs on matrix cores, float32 accumulation */
+    FCGNO_OP_IDENTITY = 3,  /* B = I: FCG is then conjugate gradients (Fig. 2a) */
+};
+
+typedef struct {
+    int32_t layers;       /* L >= 1 */
+    int32_t width;        /* C in {16, 32} */
+    int32_t modes;        /* M, 1 <= M <= 16; every solve needs 2M <= N */
+    int32_t in_channels;  /* must be 4: [r/s, log k, x1, x2] */
+} fcgno_arch;
+
+typedef struct fcgno_model fcgno_model;
+
+/* Number of float64 values in a weight blob of this architecture. */
+size_t fcgno_weight_count(const fcgno_arch* arch);
+
+/* Create a model from a host float64 blob (Sec. 2.4.2, the spectral layers
+ * u <- S L A u).  The library copies the weights to the current device in
+ * float64, float32 and bfloat16 and owns those copies.  Errors: E_INVALID
+ * (null pointer, n_weights mismatch, unsupported width or modes), E_HIP. */
+fcgno_status fcgno_model_create(const fcgno_arch* arch, const double* weights_host,
+                                size_t n_weights, fcgno_model** out);
+
+/* Copy the current float64 weights (updated by training) to a host blob. */
+fcgno_status fcgno_model_get_weights(const fcgno_model* m, double* weights_host, size_t n);
+
+/* Replace the weights from a host blob (same layout); not concurrent with use. */
+fcgno_status fcgno_model_set_weights(fcgno_model* m, const double* weights_host, size_t n);
+
+void fcgno_model_destroy(fcgno_model* m);
+
+/* ------------------------------------------------------------------------ */
+/* fcgno_solve: Algorithm 1 ("Input: A, B, f, m_max, iter.  Ensure: u_iter,   */
+/* r_iter") for a batch of independent systems of the same size.              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t n;          /* N, interior points per side, >= 1 (>= 2*modes unless IDENTITY) */
+    int32_t batch;      /* number of systems, >= 1 */
+    int32_t m_max;      /* truncation parameter of Algorithm 1, 1..32 */
+    int32_t max_iter;   /* iteration limit ("iter"), >= 1 */
+    double rtol;        /* stop at the first i with ||r_i||_2/||r_0||_2 <= rtol, > 0 */
+    int32_t op;         /* FCGNO_OP_* */
+    int32_t check_every;/* host polls convergence every this many iterations (0 = auto) */
+} fcgno_solve_desc;
+
+/* Workspace bytes fcgno_solve needs for this model and descriptor
+ * (model may be NULL when op is IDENTITY); 0 on invalid input. */
+size_t fcgno_solve_workspace_bytes(const fcgno_model* m, const fcgno_solve_desc* d);
+
+/* Solve, per system b, A_b u_b = f_b from u_b = u0_b.
+ *   k       device [batch][N+2][N+2] float64, nodal coefficients (> 0)
+ *   f       device [batch][N][N] float64, right-hand sides
+ *   u       device [batch][N][N] float64, in: u_0, out: u at the stopping iteration
+ *   r_out   device [batch][N][N] float64 or NULL; out: the recurrence residual r_iter
+ *   iters   host [batch] int32 out: the stopping iteration i (0 if ||r_0|| = 0)
+ *   sys_status host [batch] int32 out: FCGNO_SYS_*
+ *   rel_hist host [batch][max_iter+1] float64 or NULL; out: ||r_i||/||r_0||,
+ *           i = 0..iters, the rest of each row untouched
+ *   true_rel_res host [batch] float64 or NULL; out: ||f - A u||_2 / ||r_0||_2
+ *           recomputed from the returned u
+ * The call enqueues on stream, polls convergence from the host and returns
+ * when every system has stopped; the outputs are then final.  Returns
+ * FCGNO_OK if every system converged, FCGNO_NOT_CONVERGED otherwise. */
+fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc* d,
+                         const double* k, const double* f, double* u, double* r_out,
+                         int32_t* iters, int32_t* sys_status, double* rel_hist,
+                         double* true_rel_res, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* fcgno_precond_apply: w = B(r; theta) (the preconditioner of Sec. 2.4.2).   */
+/* ------------------------------------------------------------------------ */
+
+size_t fcgno_precond_workspace_bytes(const fcgno_model* m, int32_t n, int32_t batch, int32_t op);
+
+/* k device [batch][N+2][N+2], r device [batch][N][N] (read only), w device
+ * [batch][N][N] out.  op is FP64, FP32 or BF16.  Asynchronous on stream. */
+fcgno_status fcgno_precond_apply(const fcgno_model* m, int32_t n, int32_t batch, int32_t op,
+                                 const double* k, const double* r, double* w,
+                                 void* ws, size_t ws_bytes, void* stream);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char* fcgno_last_error(void);
+const char* fcgno_status_string(fcgno_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FCGNO_H */

@@ -1,0 +1,192 @@
+"""ctypes binding of libfcgno.so.  Argument marshalling only: every step of the
+solve and of the operator runs in the HIP library.  Tensors are torch device
+tensors (float64, contiguous); torch supplies device memory and the stream."""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_size_t, c_void_p, c_char_p
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfcgno.so")
+
+OP = {"fp64": 0, "fp32": 1, "bf16": 2, "identity": 3}
+SYS_OK, SYS_NOT_CONVERGED, SYS_BREAKDOWN, SYS_NONFINITE = 0, 1, 2, 3
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "BREAKDOWN", 3: "NONFINITE"}
+
+
+class Arch(ctypes.Structure):
+    _fields_ = [("layers", c_int32), ("width", c_int32), ("modes", c_int32), ("in_channels", c_int32)]
+
+
+class SolveDesc(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("batch", c_int32), ("m_max", c_int32), ("max_iter", c_int32),
+                ("rtol", c_double), ("op", c_int32), ("check_every", c_int32)]
+
+
+class FcgnoError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; fail loudly if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FcgnoError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                         "(hipcc for gfx950); there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = c_void_p
+    L.fcgno_weight_count.argtypes = [POINTER(Arch)]
+    L.fcgno_weight_count.restype = c_size_t
+    L.fcgno_model_create.argtypes = [POINTER(Arch), POINTER(c_double), c_size_t, POINTER(vp)]
+    L.fcgno_model_create.restype = c_int32
+    L.fcgno_model_get_weights.argtypes = [vp, POINTER(c_double), c_size_t]
+    L.fcgno_model_get_weights.restype = c_int32
+    L.fcgno_model_set_weights.argtypes = [vp, POINTER(c_double), c_size_t]
+    L.fcgno_model_set_weights.restype = c_int32
+    L.fcgno_model_destroy.argtypes = [vp]
+    L.fcgno_model_destroy.restype = None
+    L.fcgno_solve_workspace_bytes.argtypes = [vp, POINTER(SolveDesc)]
+    L.fcgno_solve_workspace_bytes.restype = c_size_t
+    L.fcgno_solve.argtypes = [vp, POINTER(SolveDesc), vp, vp, vp, vp, POINTER(c_int32), POINTER(c_int32),
+                              POINTER(c_double), POINTER(c_double), vp, c_size_t, vp]
+    L.fcgno_solve.restype = c_int32
+    L.fcgno_precond_workspace_bytes.argtypes = [vp, c_int32, c_int32, c_int32]
+    L.fcgno_precond_workspace_bytes.restype = c_size_t
+    L.fcgno_precond_apply.argtypes = [vp, c_int32, c_int32, c_int32, vp, vp, vp, vp, c_size_t, vp]
+    L.fcgno_precond_apply.restype = c_int32
+    L.fcgno_last_error.argtypes = []
+    L.fcgno_last_error.restype = c_char_p
+    _lib = L
+    return L
+
+
+def _check(status, what):
+    if status < 0:
+        msg = lib().fcgno_last_error().decode(errors="replace")
+        raise FcgnoError(f"{what} failed with status {status}: {msg}")
+    return status
+
+
+def _dev_f64(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise FcgnoError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise FcgnoError(f"{name} must be contiguous float64")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _workspace(nbytes, device, workspace):
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < nbytes:
+            raise FcgnoError("workspace too small")
+        return workspace
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def weight_count(C, M, L=4, Cin=4):
+    a = Arch(L, C, M, Cin)
+    return int(lib().fcgno_weight_count(ctypes.byref(a)))
+
+
+class Model:
+    """Operator weights resident on the current device (library-owned)."""
+
+    def __init__(self, weights, C, M, L=4, Cin=4):
+        self.arch = Arch(L, C, M, Cin)
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        self.n_weights = w.size
+        h = ctypes.c_void_p()
+        _check(lib().fcgno_model_create(ctypes.byref(self.arch),
+                                        w.ctypes.data_as(POINTER(c_double)), w.size, ctypes.byref(h)),
+               "fcgno_model_create")
+        self.handle = h
+        self.C, self.M, self.L = C, M, L
+
+    def get_weights(self):
+        out = np.empty(self.n_weights, dtype=np.float64)
+        _check(lib().fcgno_model_get_weights(self.handle, out.ctypes.data_as(POINTER(c_double)), out.size),
+               "fcgno_model_get_weights")
+        return out
+
+    def set_weights(self, weights):
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        _check(lib().fcgno_model_set_weights(self.handle, w.ctypes.data_as(POINTER(c_double)), w.size),
+               "fcgno_model_set_weights")
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().fcgno_model_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_workspace_bytes(model, n, batch, op="bf16", m_max=5, max_iter=300, rtol=1e-6):
+    d = SolveDesc(n, batch, m_max, max_iter, rtol, OP[op], 0)
+    return int(lib().fcgno_solve_workspace_bytes(model.handle if model else None, ctypes.byref(d)))
+
+
+def solve(model, k, f, u, op="bf16", m_max=5, max_iter=300, rtol=1e-6, r_out=None, hist=True,
+          check_every=0, workspace=None, stream=None):
+    """Run Algorithm 1 on a batch: k [B][N+2][N+2], f [B][N][N], u [B][N][N]
+    (in: u0, out: u_iter), all float64 device tensors.  Returns a dict with
+    numpy arrays iters, status, true_rel_res and (if hist) hist [B][max_iter+1]."""
+    B, N = f.shape[0], f.shape[-1]
+    if tuple(k.shape) != (B, N + 2, N + 2) or tuple(u.shape) != (B, N, N):
+        raise FcgnoError("shape mismatch: k [B][N+2][N+2], f and u [B][N][N]")
+    d = SolveDesc(N, B, m_max, max_iter, rtol, OP[op], check_every)
+    h = model.handle if (model is not None and op != "identity") else None
+    nbytes = lib().fcgno_solve_workspace_bytes(h, ctypes.byref(d))
+    if nbytes == 0:
+        raise FcgnoError("invalid solve descriptor: " + lib().fcgno_last_error().decode(errors="replace"))
+    ws = _workspace(nbytes, f.device, workspace)
+    iters = np.zeros(B, dtype=np.int32)
+    status = np.zeros(B, dtype=np.int32)
+    tres = np.zeros(B, dtype=np.float64)
+    hh = np.full((B, max_iter + 1), np.nan) if hist else None
+    rc = lib().fcgno_solve(
+        h, ctypes.byref(d), _dev_f64(k, "k"), _dev_f64(f, "f"), _dev_f64(u, "u"),
+        _dev_f64(r_out, "r_out") if r_out is not None else None,
+        iters.ctypes.data_as(POINTER(c_int32)), status.ctypes.data_as(POINTER(c_int32)),
+        hh.ctypes.data_as(POINTER(c_double)) if hist else None,
+        tres.ctypes.data_as(POINTER(c_double)), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+    _check(rc, "fcgno_solve")
+    out = {"iters": iters, "status": status, "true_rel_res": tres, "rc": rc}
+    if hist:
+        out["hist"] = hh
+    return out
+
+
+def precond_apply(model, k, r, op="bf16", w=None, workspace=None, stream=None):
+    """w = B(r; theta) for a batch (asynchronous on the stream)."""
+    B, N = r.shape[0], r.shape[-1]
+    if tuple(k.shape) != (B, N + 2, N + 2):
+        raise FcgnoError("shape mismatch: k [B][N+2][N+2], r [B][N][N]")
+    if w is None:
+        w = torch.empty_like(r)
+    nbytes = lib().fcgno_precond_workspace_bytes(model.handle, N, B, OP[op])
+    if nbytes == 0:
+        raise FcgnoError("invalid operator application (need 2*modes <= N and a matrix precision)")
+    ws = _workspace(nbytes, r.device, workspace)
+    _check(lib().fcgno_precond_apply(model.handle, N, B, OP[op], _dev_f64(k, "k"), _dev_f64(r, "r"),
+                                     _dev_f64(w, "w"), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                     _stream(stream)), "fcgno_precond_apply")
+    return w

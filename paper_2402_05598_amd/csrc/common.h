@@ -1,0 +1,187 @@
+// Internal declarations shared by the HIP translation units of libfcgno.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fcgno {
+
+constexpr int MAXW = 32;        // largest truncation window m_max
+constexpr int NQ = MAXW + 4;    // partial-sum slots per block
+constexpr int FLAT_PTS = 2048;  // points per workgroup in the flat Krylov kernels
+constexpr int TILE_I = 16;      // stencil tile rows (x1)
+constexpr int TILE_J = 64;      // stencil tile columns (x2, contiguous)
+constexpr int TPW = 32;         // 16-point column tiles per wave in the layer kernel
+
+enum Prec { P64 = 0, P32 = 1, PBF = 2, PID = 3 };
+
+enum SysStatus { S_OK = 0, S_NOTCONV = 1, S_BREAK = 2, S_NONFINITE = 3 };
+
+// Scalar state of one system, resident on the device.
+struct SysState {
+  int i;          // next iteration index
+  int active;     // 1 while iterating
+  int status;     // SysStatus
+  int iters;      // iteration count reported
+  unsigned tick[4];
+  int m;          // window size m_i of the current iteration
+  int max_iter;
+  int m_max;
+  int pad0;
+  double rr0;     // ||r_0||^2
+  double rr;      // ||r_i||^2
+  double alpha;
+  double snorm;   // ||r_i||_2 / N, the operator's input scale
+  double tres;    // ||f - A u||_2 / ||r_0||_2 (final check)
+  double rtol;
+  double ps_ring[MAXW + 1];   // (p_k, A p_k) by ring slot k mod (m_max+1)
+  double coef[MAXW];          // (w_i, s_k)/(p_k, s_k) of the current window
+};
+
+// Per-system device pointers.  All systems of one launch share N.
+struct SysDev {
+  const double* k;   // [(N+2)^2]
+  const double* f;   // [N^2]
+  double* u;
+  double* r;
+  double* w;         // == r for the identity operator
+  double* P;         // ring [(m_max+1)][N^2]
+  double* S;         // ring
+  SysState* st;
+  double* hist;      // [max_iter+1]
+  double* part;      // [blocks][NQ]
+  int* n_active;     // batch counter of active systems
+  // operator buffers (op precision unless noted)
+  void* act;         // [slots][N^2][C]
+  size_t act_stride; // elements per activation slot
+  void* logk;        // [N^2]
+  double* Gr;        // [N][MP] row DFT partials of r, float64
+  void* Gp;          // [N][S][MP][C] row DFT partials of activations, accumulate precision
+  void* Hc;          // [N][C][MP] synthesis rows for the layer kernel
+  void* Vc;          // [C][2M][M] complex, accumulate precision: constant part of layer-0 spectrum
+};
+
+// Per-N tables shared by the systems of one launch.
+struct Tables {
+  const double* E64;  // [N] (cos, sin)(2 pi m / N), float64 interleaved
+  const void* Eacc;   // same in accumulate precision
+  const void* T;      // [N][MP] op precision: T[y][2q] = cos(2 pi q y/N), T[y][2q+1] = sin(...)
+  const void* TT;     // [MP][N] transpose of T
+};
+
+__device__ __forceinline__ int window_size(int i, int m_max) {
+  int r = i % (m_max + 1);
+  int a = r > 1 ? r : 1;
+  return i < a ? i : a;
+}
+
+// ---- deterministic reductions ------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over a 256-thread block in a fixed order; result valid in every thread.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* lds /* >= 4 */) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  T s = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  return s;
+}
+
+// After every block of a system has written its partials, exactly one block
+// (the last to arrive) returns true; it then sees all partials.  The ticket
+// is reset by that block.
+__device__ __forceinline__ bool arrive_last(unsigned* tick, unsigned nblocks) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned t = atomicAdd(tick, 1u);
+    s_last = (t == nblocks - 1u);
+    if (s_last) atomicExch(tick, 0u);
+  }
+  __syncthreads();
+  if (s_last) __threadfence();
+  return s_last != 0;
+}
+
+// Fixed-order sum of part[b*NQ + q] over b < nb, in the calling block.
+__device__ __forceinline__ double reduce_partials(const double* part, int nb, int q, double* lds) {
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) v += __builtin_nontemporal_load(part + (size_t)b * NQ + q);
+  return block_sum(v, lds);
+}
+
+__device__ __forceinline__ void deactivate(SysState* st, int* n_active, int status, int iters) {
+  st->status = status;
+  st->iters = iters;
+  st->active = 0;
+  atomicSub(n_active, 1);
+}
+
+// ---- bfloat16 helpers ----------------------------------------------------
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  // round to nearest even; NaN stays NaN
+  uint32_t b = __float_as_uint(f);
+  if ((b & 0x7f800000u) == 0x7f800000u) return (uint16_t)((b >> 16) | ((b & 0xffffu) ? 0x40u : 0u));
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// ---- exact GELU ----------------------------------------------------------
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ double gelu(double z) { return 0.5 * z * (1.0 + erf(z * 0.70710678118654752440)); }
+
+// ---- host-side launchers (defined in the .hip files) ---------------------
+
+struct KrylovLaunch {
+  const SysDev* sys;   // device table
+  int nsys;
+  int N;
+  int m_max;
+  hipStream_t stream;
+};
+
+void launch_init_state(const KrylovLaunch& L, int max_iter, double rtol);
+void launch_residual(const KrylovLaunch& L, int mode);   // 0: r0 setup, 1: final true residual
+void launch_rnorm(const KrylovLaunch& L);                 // snorm from r (operator only)
+void launch_wdots(const KrylovLaunch& L);
+void launch_dir(const KrylovLaunch& L);
+void launch_update(const KrylovLaunch& L);
+
+struct NOLaunch {
+  const SysDev* sys;
+  int nsys;
+  int N, C, M, MP, L;   // MP = 2M rounded up to 16
+  int S;                // column segments per row in the layer kernel
+  int prec;             // P64, P32, PBF
+  Tables tab;
+  // model weights in the op / accumulate precisions
+  const void* const* Wfrag;   // [L] op precision [C][KWP_l]
+  const void* const* bias;    // [L] accumulate precision [C]
+  const void* const* Rmix;    // [L] accumulate precision [M][2M][C][C] complex
+  const void* WP;             // accumulate precision [C]
+  double bP;
+  const void* WL0;            // accumulate precision [C]: lift weights of the r/s feature
+  const double* WL;           // float64 [C][4]
+  const double* bL;           // float64 [C]
+  hipStream_t stream;
+};
+
+void launch_tables(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT);
+void launch_no_setup(const NOLaunch& L, double* scratch);   // logk, Vc
+void launch_no_apply(const NOLaunch& L);                    // w = B(r) for active systems
+
+}  // namespace fcgno
