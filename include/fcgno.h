@@ -148,6 +148,17 @@ fcgno_status fcgno_precond_apply(const fcgno_model* m, int32_t n, int32_t batch,
                                  const double* k, const double* r, double* w,
                                  void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Kernel timing: HIP event pairs recorded on the launch stream around each   */
+/* launch of a kernel family while enabled; read after the work completed.    */
+/* kernel ids: 0 operator layer kernel (matrix cores), 1 operator spectral    */
+/* kernel, 2 direction+stencil, 3 window dots, 4 update, 5 row DFT of r,      */
+/* 6 training forward, 7 training backward.                                   */
+/* ------------------------------------------------------------------------ */
+void fcgno_profile_enable(int32_t on);
+void fcgno_profile_reset(void);
+fcgno_status fcgno_profile_read(int32_t kernel, int64_t* launches, double* total_ms);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char* fcgno_last_error(void);
 const char* fcgno_status_string(fcgno_status s);

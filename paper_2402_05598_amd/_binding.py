@@ -63,6 +63,12 @@ def lib():
     L.fcgno_precond_workspace_bytes.restype = c_size_t
     L.fcgno_precond_apply.argtypes = [vp, c_int32, c_int32, c_int32, vp, vp, vp, vp, c_size_t, vp]
     L.fcgno_precond_apply.restype = c_int32
+    L.fcgno_profile_enable.argtypes = [c_int32]
+    L.fcgno_profile_enable.restype = None
+    L.fcgno_profile_reset.argtypes = []
+    L.fcgno_profile_reset.restype = None
+    L.fcgno_profile_read.argtypes = [c_int32, POINTER(ctypes.c_int64), POINTER(c_double)]
+    L.fcgno_profile_read.restype = c_int32
     L.fcgno_last_error.argtypes = []
     L.fcgno_last_error.restype = c_char_p
     _lib = L
@@ -190,3 +196,24 @@ def precond_apply(model, k, r, op="bf16", w=None, workspace=None, stream=None):
                                      _dev_f64(w, "w"), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                      _stream(stream)), "fcgno_precond_apply")
     return w
+
+
+PROFILE_KERNELS = {"layer": 0, "spectral": 1, "dir": 2, "wdots": 3, "update": 4, "rowdft": 5,
+                   "train_fwd": 6, "train_bwd": 7}
+
+
+def profile_enable(on=True):
+    lib().fcgno_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    lib().fcgno_profile_reset()
+
+
+def profile_read(kernel):
+    """(launches, total milliseconds) of a kernel family since the last reset."""
+    n = ctypes.c_int64(0)
+    ms = c_double(0.0)
+    _check(lib().fcgno_profile_read(PROFILE_KERNELS[kernel], ctypes.byref(n), ctypes.byref(ms)),
+           "fcgno_profile_read")
+    return int(n.value), float(ms.value)

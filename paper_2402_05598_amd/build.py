@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfcgno.so")
-SOURCES = ["krylov.hip", "no_fwd.hip", "train.hip", "api.hip", "train_api.hip", "serve.hip"]
+SOURCES = ["krylov.hip", "no_fwd.hip", "prof.hip", "train.hip", "api.hip", "train_api.hip", "serve.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
          # no packed-FP32 instructions in device code

@@ -8,6 +8,7 @@
 
 #include "common.h"
 #include "fcgno.h"
+#include "prof.h"
 
 using namespace fcgno;
 
@@ -134,8 +135,13 @@ static fcgno_status upload_weights(fcgno_model* m) {
       for (int oc = 0; oc < C; ++oc) {
         for (int kw = 0; kw < KWP; ++kw) {
           double v = 0.0;
-          if (l == 0) v = kw < 4 ? W0L[oc * 4 + kw] : 0.0;
-          else v = W[l][oc * C + kw];
+          if (l == 0) {
+            v = kw < 4 ? W0L[oc * 4 + kw] : 0.0;
+          } else {
+            // input K index kw = ks*KSTEP + g*KPL + e carries channel g*(C/4) + ks*KPL + e
+            const int kpl = ks / 4, kss = kw / ks, rem = kw % ks, g = rem / kpl, e = rem % kpl;
+            v = W[l][oc * C + g * (C / 4) + kss * kpl + e];
+          }
           put(hb, off[p].Wf[l] + ((size_t)oc * KWP + kw) * esz, esz, v);
         }
         put(hb, off[p].bias[l] + (size_t)oc * asz, asz, l == 0 ? b0c[oc] : b[l][oc]);
@@ -240,7 +246,8 @@ struct Plan {
   size_t total = 0;
   size_t sysdev, state, counter, hist, part;
   size_t r, w, P, S;
-  size_t act, logk, Gr, Gp, Hc, Vc;
+  size_t act, logk, Gr, Gp, Hc, Vc, Wh, Vp;
+  size_t vp_bytes_per_sys;
   size_t E64, Eacc, T, TT;
   size_t n_part_blocks;
   size_t gp_bytes_per_sys;
@@ -285,6 +292,10 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
     p.Gp = cv.take((size_t)B * p.gp_bytes_per_sys);
     p.Hc = cv.take((size_t)B * N * C * MP * esz);
     p.Vc = cv.take((size_t)B * C * 2 * M * M * 2 * asz);
+    p.Wh = cv.take((size_t)B * C * MP * M * 2 * asz);
+    const int XS = (N + 63) / 64;
+    p.vp_bytes_per_sys = (size_t)M * XS * C * 2 * M * 2 * asz;
+    p.Vp = cv.take((size_t)B * p.vp_bytes_per_sys);
     p.E64 = cv.take((size_t)N * 2 * 8);
     p.Eacc = cv.take((size_t)N * 2 * asz);
     p.T = cv.take((size_t)NP * MP * esz);
@@ -310,6 +321,8 @@ void fill_no(const fcgno_model* m, const Plan& p, char* base, int N, int B, int 
     h[b].Gp = base + p.Gp + (size_t)b * p.gp_bytes_per_sys;
     h[b].Hc = base + p.Hc + (size_t)b * N * C * MP * esz;
     h[b].Vc = base + p.Vc + (size_t)b * C * 2 * M * M * 2 * asz;
+    h[b].Wh = base + p.Wh + (size_t)b * C * MP * M * 2 * asz;
+    h[b].Vp = base + p.Vp + (size_t)b * p.vp_bytes_per_sys;
   }
 }
 
@@ -404,6 +417,7 @@ extern "C" fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc
   if (op != PID) {
     NL = make_no(m, p, base, sysdev, N, B, op, s);
     HIPCHK(hipMemsetAsync(base + p.Hc, 0, (size_t)B * N * m->arch.width * p.MP * op_esize(op), s));
+    HIPCHK(hipMemsetAsync(base + p.Wh, 0, (size_t)B * m->arch.width * p.MP * m->arch.modes * 2 * acc_esize(op), s));
     launch_tables(NL, (double*)(base + p.E64), base + p.Eacc, base + p.T, base + p.TT);
     launch_no_setup(NL, (double*)(base + p.Gp));
   }
@@ -434,6 +448,7 @@ extern "C" fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc
     HIPCHK(hipMemcpyAsync(hh.data(), base + p.hist, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   }
   HIPCHK(hipStreamSynchronize(s));
+  if (prof_on()) prof_collect();
   bool all_ok = true;
   for (int b = 0; b < B; ++b) {
     iters[b] = hs[b].iters;
@@ -486,6 +501,7 @@ extern "C" fcgno_status fcgno_precond_apply(const fcgno_model* m, int32_t N, int
   launch_init_state(KL, 1, 1.0);
   NOLaunch NL = make_no(m, p, base, sysdev, N, B, op, s);
   HIPCHK(hipMemsetAsync(base + p.Hc, 0, (size_t)B * N * m->arch.width * p.MP * op_esize(op), s));
+  HIPCHK(hipMemsetAsync(base + p.Wh, 0, (size_t)B * m->arch.width * p.MP * m->arch.modes * 2 * acc_esize(op), s));
   launch_tables(NL, (double*)(base + p.E64), base + p.Eacc, base + p.T, base + p.TT);
   launch_no_setup(NL, (double*)(base + p.Gp));
   launch_rnorm(KL);

@@ -60,6 +60,8 @@ struct SysDev {
   void* Gp;          // [N][S][MP][C] row DFT partials of activations, accumulate precision
   void* Hc;          // [N][C][MP] synthesis rows for the layer kernel
   void* Vc;          // [C][2M][M] complex, accumulate precision: constant part of layer-0 spectrum
+  void* Wh;          // [M][C][MP] complex, accumulate precision: mixed spectrum of the current layer (zero past 2M)
+  void* Vp;          // [M][XS][C][2M] complex, accumulate precision: per-chunk forward spectra
 };
 
 // Per-N tables shared by the systems of one launch.
@@ -97,30 +99,6 @@ __device__ __forceinline__ T block_sum(T v, T* lds /* >= 4 */) {
   return s;
 }
 
-// After every block of a system has written its partials, exactly one block
-// (the last to arrive) returns true; it then sees all partials.  The ticket
-// is reset by that block.
-__device__ __forceinline__ bool arrive_last(unsigned* tick, unsigned nblocks) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned t = atomicAdd(tick, 1u);
-    s_last = (t == nblocks - 1u);
-    if (s_last) atomicExch(tick, 0u);
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last != 0;
-}
-
-// Fixed-order sum of part[b*NQ + q] over b < nb, in the calling block.
-__device__ __forceinline__ double reduce_partials(const double* part, int nb, int q, double* lds) {
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) v += __builtin_nontemporal_load(part + (size_t)b * NQ + q);
-  return block_sum(v, lds);
-}
-
 __device__ __forceinline__ void deactivate(SysState* st, int* n_active, int status, int iters) {
   st->status = status;
   st->iters = iters;
@@ -130,18 +108,37 @@ __device__ __forceinline__ void deactivate(SysState* st, int* n_active, int stat
 
 // ---- bfloat16 helpers ----------------------------------------------------
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  // round to nearest even; NaN stays NaN
-  uint32_t b = __float_as_uint(f);
-  if ((b & 0x7f800000u) == 0x7f800000u) return (uint16_t)((b >> 16) | ((b & 0xffffu) ? 0x40u : 0u));
-  b += 0x7fffu + ((b >> 16) & 1u);
-  return (uint16_t)(b >> 16);
-}
+// float -> bfloat16 bits, round to nearest even (one hardware conversion)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+// two floats -> packed bfloat16 pair (a in the low half)
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+  bf2_t v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
+}
 
-// ---- exact GELU ----------------------------------------------------------
+// ---- GELU ----------------------------------------------------------------
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf(x) by Abramowitz & Stegun, Handbook of Mathematical Functions, formula
+// 7.1.26: 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1/(1 + p|x|), odd in x,
+// absolute error <= 1.5e-7.  Branch-free; used by the float32 and bfloat16
+// operators (below float32 resolution of GELU's output scale).
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+  float q = 1.061405429f;
+  q = fmaf(q, t, -1.453152027f);
+  q = fmaf(q, t, 1.421413741f);
+  q = fmaf(q, t, -0.284496736f);
+  q = fmaf(q, t, 0.254829592f);
+  q *= t;
+  const float r = 1.0f - q * __expf(-ax * ax);
+  return copysignf(r, x);
+}
+
+// GELU(z) = z/2 (1 + erf(z / sqrt 2))
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
 __device__ __forceinline__ double gelu(double z) { return 0.5 * z * (1.0 + erf(z * 0.70710678118654752440)); }
 
 // ---- host-side launchers (defined in the .hip files) ---------------------

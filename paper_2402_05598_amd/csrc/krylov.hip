@@ -1,29 +1,29 @@
 // Krylov part of flexible conjugate gradients (Algorithm 1), float64.
 //
 // Per iteration i and system b (after w_i = B(r_i) is available):
-//   k_wdots   c_k = (w_i, s_k) / (p_k, s_k) over the window k = i-m_i .. i-1
+//   k_wdots   partial (w_i, s_k) over the window k = i-m_i .. i-1
+//   k_fin(0)  c_k = (w_i, s_k) / (p_k, s_k)
 //   k_dir     p_i = w_i - sum_k c_k p_k (recomputed on a halo in LDS),
-//             s_i = A p_i, partial (p_i, r_i), (p_i, s_i)  -> alpha_i
-//   k_update  u += alpha p_i, r -= alpha s_i, ||r_{i+1}||^2 -> stop test
-// Reductions are two-level and deterministic: each block writes its partial
-// sums to a fixed slot, and the last block of the system to finish sums the
-// slots in block order.  The block -> points mapping depends only on N, so a
+//             s_i = A p_i, partial (p_i, r_i), (p_i, s_i)
+//   k_fin(1)  alpha_i = (p_i, r_i)/(p_i, s_i), or breakdown
+//   k_update  u += alpha p_i, r -= alpha s_i, partial ||r_{i+1}||^2
+//   k_fin(2)  ||r_{i+1}|| / ||r_0||, stopping test, i <- i+1
+// Reductions are two-level and deterministic: every block writes its partial
+// sums to a fixed slot and a one-block-per-system kernel sums the slots in
+// block order (the kernel boundary makes the slots visible, so no device-wide
+// fences are needed).  The block -> points mapping depends only on N, so a
 // system gives the same bits alone and inside any batch.
 #include "common.h"
+#include "prof.h"
 
 namespace fcgno {
 
-__device__ __forceinline__ double ld_coherent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ double final_sum(const double* part, int nb, int q, double* lds) {
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) v += ld_coherent(part + (size_t)b * NQ + q);
-  return block_sum(v, lds);
-}
+constexpr int PPT = FLAT_PTS / 256;   // points per thread in the flat kernels
 
 __device__ __forceinline__ int flat_blocks(int n) { return (n + FLAT_PTS - 1) / FLAT_PTS; }
+__device__ __forceinline__ int tile_blocks(int N) {
+  return ((N + TILE_I - 1) / TILE_I) * ((N + TILE_J - 1) / TILE_J);
+}
 
 // 5-point operator at interior point (i, j) with neighbour values supplied.
 __device__ __forceinline__ double stencil_at(const double* __restrict__ k, int N, int i, int j,
@@ -62,39 +62,40 @@ __global__ __launch_bounds__(64) void k_init_state(const SysDev* sys, int nsys, 
   if (b == 0) *sys[0].n_active = nsys;
 }
 
-// mode 0: r = f - A u, ||r_0||, input checks (k > 0 and finite, f and u finite).
-// mode 1: ||f - A u|| / ||r_0|| into st->tres, r untouched, every system.
+// mode 0: r = f - A u, partial ||r_0||^2 and input checks (k > 0 and finite,
+//         f and u finite).  mode 1: partial ||f - A u||^2 only, every system.
 __global__ __launch_bounds__(256) void k_residual(const SysDev* sys, int N, int mode) {
   __shared__ double lds[4];
   const SysDev sd = sys[blockIdx.y];
-  SysState* st = sd.st;
-  if (mode == 0 && !st->active) return;
+  if (mode == 0 && !sd.st->active) return;
   const int n = N * N;
-  const int nb = flat_blocks(n);
-  double acc = 0.0, bad = 0.0;
   const int K = N + 2;
-  for (int e = 0; e < FLAT_PTS / 256; ++e) {
+  double acc = 0.0, bad = 0.0;
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) {
     const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
-    if (p >= n) break;
-    const int i = p / N, j = p - i * N;
-    const double c = sd.u[p];
-    const double ue = (i + 1 < N) ? sd.u[p + N] : 0.0;
-    const double uw = (i > 0) ? sd.u[p - N] : 0.0;
-    const double un = (j + 1 < N) ? sd.u[p + 1] : 0.0;
-    const double us = (j > 0) ? sd.u[p - 1] : 0.0;
-    const double rv = sd.f[p] - stencil_at(sd.k, N, i, j, c, ue, uw, un, us);
-    if (mode == 0) {
-      // every node except the four corners is read by some interior point
-      const double kc = sd.k[(i + 1) * K + j + 1];
-      bool ok = (kc > 0.0) && isfinite(kc) && isfinite(sd.f[p]) && isfinite(c);
-      if (i == 0) { double t = sd.k[j + 1]; ok = ok && t > 0.0 && isfinite(t); }
-      if (i == N - 1) { double t = sd.k[(N + 1) * K + j + 1]; ok = ok && t > 0.0 && isfinite(t); }
-      if (j == 0) { double t = sd.k[(i + 1) * K]; ok = ok && t > 0.0 && isfinite(t); }
-      if (j == N - 1) { double t = sd.k[(i + 1) * K + N + 1]; ok = ok && t > 0.0 && isfinite(t); }
-      if (!ok) bad += 1.0;
-      sd.r[p] = rv;
+    if (p < n) {
+      const int i = p / N, j = p - i * N;
+      const double c = sd.u[p];
+      const double ue = (i + 1 < N) ? sd.u[p + N] : 0.0;
+      const double uw = (i > 0) ? sd.u[p - N] : 0.0;
+      const double un = (j + 1 < N) ? sd.u[p + 1] : 0.0;
+      const double us = (j > 0) ? sd.u[p - 1] : 0.0;
+      const double fv = sd.f[p];
+      const double rv = fv - stencil_at(sd.k, N, i, j, c, ue, uw, un, us);
+      if (mode == 0) {
+        // every node except the four corners is read by some interior point
+        const double kc = sd.k[(i + 1) * K + j + 1];
+        bool ok = (kc > 0.0) && isfinite(kc) && isfinite(fv) && isfinite(c);
+        if (i == 0) { double t = sd.k[j + 1]; ok = ok && t > 0.0 && isfinite(t); }
+        if (i == N - 1) { double t = sd.k[(N + 1) * K + j + 1]; ok = ok && t > 0.0 && isfinite(t); }
+        if (j == 0) { double t = sd.k[(i + 1) * K]; ok = ok && t > 0.0 && isfinite(t); }
+        if (j == N - 1) { double t = sd.k[(i + 1) * K + N + 1]; ok = ok && t > 0.0 && isfinite(t); }
+        if (!ok) bad += 1.0;
+        sd.r[p] = rv;
+      }
+      acc += rv * rv;
     }
-    acc += rv * rv;
   }
   acc = block_sum(acc, lds);
   if (mode == 0) bad = block_sum(bad, lds);
@@ -102,10 +103,231 @@ __global__ __launch_bounds__(256) void k_residual(const SysDev* sys, int N, int 
     sd.part[(size_t)blockIdx.x * NQ + 0] = acc;
     sd.part[(size_t)blockIdx.x * NQ + 1] = bad;
   }
-  if (!arrive_last(&st->tick[mode == 0 ? 0 : 3], nb)) return;
-  const double rr = final_sum(sd.part, nb, 0, lds);
+}
+
+// partial ||r||^2 for a standalone operator application.
+__global__ __launch_bounds__(256) void k_rnorm(const SysDev* sys, int N) {
+  __shared__ double lds[4];
+  const SysDev sd = sys[blockIdx.y];
+  const int n = N * N;
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) {
+    const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
+    if (p < n) {
+      const double v = sd.r[p];
+      acc += v * v;
+    }
+  }
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) sd.part[(size_t)blockIdx.x * NQ] = acc;
+}
+
+// Window dot products (w_i, s_k), in passes of up to 8 window vectors.
+__global__ __launch_bounds__(256) void k_wdots(const SysDev* sys, int N) {
+  __shared__ double lds[4];
+  const SysDev sd = sys[blockIdx.y];
+  const SysState* st = sd.st;
+  if (!st->active) return;
+  const int i = st->i, mm = st->m_max;
+  const int m = window_size(i, mm);
+  if (m == 0) return;
+  const int n = N * N;
+  const int ring = mm + 1;
+  const double* __restrict__ w = sd.w;
+  double wv[PPT];
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) {
+    const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
+    wv[e] = p < n ? w[p] : 0.0;
+  }
+  for (int q0 = 0; q0 < m; q0 += 8) {
+    const int nq = min(8, m - q0);
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      acc[q] = 0.0;
+      if (q < nq) {
+        const double* __restrict__ Sv = sd.S + (size_t)((i - m + q0 + q) % ring) * n;
+#pragma unroll
+        for (int e = 0; e < PPT; ++e) {
+          const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
+          if (p < n) acc[q] += wv[e] * Sv[p];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q < nq) {
+        const double v = block_sum(acc[q], lds);
+        if (threadIdx.x == 0) sd.part[(size_t)blockIdx.x * NQ + q0 + q] = v;
+      }
+    }
+  }
+}
+
+// p_i on the tile and a one-point halo, s_i = A p_i, partial (p_i, r_i), (p_i, s_i).
+__global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
+  constexpr int HW = TILE_J + 2, HN = (TILE_I + 2) * (TILE_J + 2);
+  constexpr int HR = (HN + 255) / 256;
+  constexpr int IR = TILE_I * TILE_J / 256;
+  __shared__ double lds[4];
+  __shared__ double pl[HN];
+  __shared__ double cf[MAXW];
+  const SysDev sd = sys[blockIdx.y];
+  const SysState* st = sd.st;
+  if (!st->active) return;
+  const int i = st->i, ring = st->m_max + 1;
+  const int m = st->m;
+  const int n = N * N;
+  const int tj = (N + TILE_J - 1) / TILE_J;
+  const int bi = blockIdx.x / tj, bj = blockIdx.x - bi * tj;
+  const int i0 = bi * TILE_I, j0 = bj * TILE_J;
+  if (threadIdx.x < m) cf[threadIdx.x] = st->coef[threadIdx.x];
+  __syncthreads();
+  int hp[HR];
+  double hv[HR];
+#pragma unroll
+  for (int e = 0; e < HR; ++e) {
+    const int t = threadIdx.x + 256 * e;
+    const int a = t / HW, c = t - a * HW;
+    const int gi = i0 - 1 + a, gj = j0 - 1 + c;
+    hp[e] = (t < HN && gi >= 0 && gi < N && gj >= 0 && gj < N) ? gi * N + gj : -1;
+    hv[e] = hp[e] >= 0 ? sd.w[hp[e]] : 0.0;
+  }
+  for (int q = 0; q < m; ++q) {
+    const double* __restrict__ Pq = sd.P + (size_t)((i - m + q) % ring) * n;
+    const double c = cf[q];
+#pragma unroll
+    for (int e = 0; e < HR; ++e)
+      if (hp[e] >= 0) hv[e] -= c * Pq[hp[e]];
+  }
+#pragma unroll
+  for (int e = 0; e < HR; ++e) {
+    const int t = threadIdx.x + 256 * e;
+    if (t < HN) pl[t] = hv[e];
+  }
+  __syncthreads();
+  double* __restrict__ Pi = sd.P + (size_t)(i % ring) * n;
+  double* __restrict__ Si = sd.S + (size_t)(i % ring) * n;
+  double pr = 0.0, ps = 0.0;
+#pragma unroll
+  for (int e = 0; e < IR; ++e) {
+    const int t = threadIdx.x + 256 * e;
+    const int a = t / TILE_J, c = t - a * TILE_J;
+    const int gi = i0 + a, gj = j0 + c;
+    if (gi < N && gj < N) {
+      const int h = (a + 1) * HW + (c + 1);
+      const double pc = pl[h];
+      const double s = stencil_at(sd.k, N, gi, gj, pc, pl[h + HW], pl[h - HW], pl[h + 1], pl[h - 1]);
+      const int p = gi * N + gj;
+      const double rv = sd.r[p];
+      Pi[p] = pc;
+      Si[p] = s;
+      pr += pc * rv;
+      ps += pc * s;
+    }
+  }
+  pr = block_sum(pr, lds);
+  ps = block_sum(ps, lds);
+  if (threadIdx.x == 0) {
+    sd.part[(size_t)blockIdx.x * NQ + 0] = pr;
+    sd.part[(size_t)blockIdx.x * NQ + 1] = ps;
+  }
+}
+
+// u += alpha p_i, r -= alpha s_i, partial ||r_{i+1}||^2.
+__global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
+  __shared__ double lds[4];
+  const SysDev sd = sys[blockIdx.y];
+  const SysState* st = sd.st;
+  if (!st->active) return;
+  const int i = st->i, ring = st->m_max + 1;
+  const double alpha = st->alpha;
+  const int n = N * N;
+  const double* __restrict__ Pi = sd.P + (size_t)(i % ring) * n;
+  const double* __restrict__ Si = sd.S + (size_t)(i % ring) * n;
+  double* __restrict__ u = sd.u;
+  double* __restrict__ r = sd.r;
+  double uv[PPT], pv[PPT], rv[PPT], sv[PPT];
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) {
+    const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
+    if (p < n) {
+      uv[e] = u[p];
+      pv[e] = Pi[p];
+      rv[e] = r[p];
+      sv[e] = Si[p];
+    }
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) {
+    const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
+    if (p < n) {
+      const double rn = rv[e] - alpha * sv[e];
+      u[p] = uv[e] + alpha * pv[e];
+      r[p] = rn;
+      acc += rn * rn;
+    }
+  }
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) sd.part[(size_t)blockIdx.x * NQ] = acc;
+}
+
+// One block per system: fixed-order sums of the partial slots and the scalar
+// steps of Algorithm 1 that follow them.
+//   mode 0: window coefficients c_k        (after k_wdots)
+//   mode 1: alpha_i or breakdown           (after k_dir)
+//   mode 2: rho_{i+1}, stopping test, i+1  (after k_update)
+//   mode 3: ||r_0||, input status          (after k_residual mode 0)
+//   mode 4: true relative residual         (after k_residual mode 1)
+//   mode 5: operator input scale           (after k_rnorm)
+__global__ __launch_bounds__(256) void k_fin(const SysDev* sys, int N, int mode) {
+  __shared__ double lds[4];
+  const SysDev sd = sys[blockIdx.x];
+  SysState* st = sd.st;
+  if (mode != 4 && mode != 5 && !st->active) return;
+  const int nb = (mode == 1) ? tile_blocks(N) : flat_blocks(N * N);
+  auto fsum = [&](int q) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) v += sd.part[(size_t)b * NQ + q];
+    return block_sum(v, lds);
+  };
+  const int i = st->i, ring = st->m_max + 1;
   if (mode == 0) {
-    const double nbad = final_sum(sd.part, nb, 1, lds);
+    const int m = window_size(i, st->m_max);
+    for (int q = 0; q < m; ++q) {
+      const double d = fsum(q);
+      if (threadIdx.x == 0) st->coef[q] = d / st->ps_ring[(i - m + q) % ring];
+    }
+    if (threadIdx.x == 0) st->m = m;
+  } else if (mode == 1) {
+    const double PR = fsum(0), PS = fsum(1);
+    if (threadIdx.x == 0) {
+      if (!(isfinite(PS) && isfinite(PR)) || !(PS > 0.0)) {
+        st->alpha = 0.0;
+        deactivate(st, sd.n_active, S_BREAK, i);
+      } else {
+        st->alpha = PR / PS;
+        st->ps_ring[i % ring] = PS;
+      }
+    }
+  } else if (mode == 2) {
+    const double rr = fsum(0);
+    if (threadIdx.x == 0) {
+      const double rho = sqrt(rr / st->rr0);
+      st->rr = rr;
+      st->snorm = sqrt(rr) / (double)N;
+      sd.hist[i + 1] = rho;
+      st->i = i + 1;
+      st->iters = i + 1;
+      if (!isfinite(rho)) deactivate(st, sd.n_active, S_BREAK, i + 1);
+      else if (rho <= st->rtol) deactivate(st, sd.n_active, S_OK, i + 1);
+      else if (i + 1 >= st->max_iter) deactivate(st, sd.n_active, S_NOTCONV, i + 1);
+    }
+  } else if (mode == 3) {
+    const double rr = fsum(0), nbad = fsum(1);
     if (threadIdx.x == 0) {
       st->rr0 = rr;
       st->rr = rr;
@@ -118,192 +340,15 @@ __global__ __launch_bounds__(256) void k_residual(const SysDev* sys, int N, int 
         if (rr == 0.0) deactivate(st, sd.n_active, S_OK, 0);
       }
     }
-  } else if (threadIdx.x == 0) {
-    st->tres = st->rr0 > 0.0 ? sqrt(rr / st->rr0) : 0.0;
-  }
-}
-
-// ||r||/N for the operator's input scale, for a standalone operator application.
-__global__ __launch_bounds__(256) void k_rnorm(const SysDev* sys, int N) {
-  __shared__ double lds[4];
-  const SysDev sd = sys[blockIdx.y];
-  const int n = N * N;
-  const int nb = flat_blocks(n);
-  double acc = 0.0;
-  for (int e = 0; e < FLAT_PTS / 256; ++e) {
-    const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
-    if (p >= n) break;
-    const double v = sd.r[p];
-    acc += v * v;
-  }
-  acc = block_sum(acc, lds);
-  if (threadIdx.x == 0) sd.part[(size_t)blockIdx.x * NQ] = acc;
-  if (!arrive_last(&sd.st->tick[0], nb)) return;
-  const double rr = final_sum(sd.part, nb, 0, lds);
-  if (threadIdx.x == 0) {
-    sd.st->snorm = sqrt(rr) / (double)N;
-    sd.st->active = 1;
-  }
-}
-
-// Window dot products (w_i, s_k), in passes of up to 8 window vectors.
-__global__ __launch_bounds__(256) void k_wdots(const SysDev* sys, int N) {
-  __shared__ double lds[4];
-  const SysDev sd = sys[blockIdx.y];
-  SysState* st = sd.st;
-  if (!st->active) return;
-  const int i = st->i, mm = st->m_max;
-  const int m = window_size(i, mm);
-  if (m == 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->m = 0;
-    return;
-  }
-  const int n = N * N;
-  const int nb = flat_blocks(n);
-  const int ring = mm + 1;
-  for (int q0 = 0; q0 < m; q0 += 8) {
-    double acc[8];
-    const double* Sv[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      acc[q] = 0.0;
-      const int kk = i - m + q0 + q;
-      Sv[q] = sd.S + (size_t)((kk >= 0 ? kk : 0) % ring) * n;
-    }
-    const int nq = min(8, m - q0);
-    for (int e = 0; e < FLAT_PTS / 256; ++e) {
-      const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
-      if (p >= n) break;
-      const double wv = sd.w[p];
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q < nq) acc[q] += wv * Sv[q][p];
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      if (q < nq) {
-        const double v = block_sum(acc[q], lds);
-        if (threadIdx.x == 0) sd.part[(size_t)blockIdx.x * NQ + q0 + q] = v;
-      }
-    }
-  }
-  if (!arrive_last(&st->tick[1], nb)) return;
-  for (int q = 0; q < m; ++q) {
-    const double d = final_sum(sd.part, nb, q, lds);
+  } else if (mode == 4) {
+    const double rr = fsum(0);
+    if (threadIdx.x == 0) st->tres = st->rr0 > 0.0 ? sqrt(rr / st->rr0) : 0.0;
+  } else {
+    const double rr = fsum(0);
     if (threadIdx.x == 0) {
-      const int kk = i - m + q;
-      st->coef[q] = d / st->ps_ring[kk % ring];
+      st->snorm = sqrt(rr) / (double)N;
+      st->active = 1;
     }
-  }
-  if (threadIdx.x == 0) st->m = m;
-}
-
-// p_i on the tile and a one-point halo, s_i = A p_i, partial (p_i, r_i), (p_i, s_i).
-__global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
-  __shared__ double lds[4];
-  __shared__ double pl[(TILE_I + 2) * (TILE_J + 2)];
-  __shared__ double cf[MAXW];
-  __shared__ const double* pv[MAXW];
-  const SysDev sd = sys[blockIdx.y];
-  SysState* st = sd.st;
-  if (!st->active) return;
-  const int i = st->i, mm = st->m_max, ring = mm + 1;
-  const int m = st->m;
-  const int n = N * N;
-  const int tj = (N + TILE_J - 1) / TILE_J;
-  const int ti = (N + TILE_I - 1) / TILE_I;
-  const int nb = ti * tj;
-  const int bi = blockIdx.x / tj, bj = blockIdx.x - bi * tj;
-  const int i0 = bi * TILE_I, j0 = bj * TILE_J;
-  if (threadIdx.x < m) {
-    cf[threadIdx.x] = st->coef[threadIdx.x];
-    pv[threadIdx.x] = sd.P + (size_t)((i - m + threadIdx.x) % ring) * n;
-  }
-  __syncthreads();
-  constexpr int HW = TILE_J + 2, HN = (TILE_I + 2) * (TILE_J + 2);
-  for (int t = threadIdx.x; t < HN; t += 256) {
-    const int a = t / HW, c = t - a * HW;
-    const int gi = i0 - 1 + a, gj = j0 - 1 + c;
-    double v = 0.0;
-    if (gi >= 0 && gi < N && gj >= 0 && gj < N) {
-      const int p = gi * N + gj;
-      v = sd.w[p];
-      for (int q = 0; q < m; ++q) v -= cf[q] * pv[q][p];
-    }
-    pl[t] = v;
-  }
-  __syncthreads();
-  double* Pi = sd.P + (size_t)(i % ring) * n;
-  double* Si = sd.S + (size_t)(i % ring) * n;
-  double pr = 0.0, ps = 0.0;
-  for (int t = threadIdx.x; t < TILE_I * TILE_J; t += 256) {
-    const int a = t / TILE_J, c = t - a * TILE_J;
-    const int gi = i0 + a, gj = j0 + c;
-    if (gi >= N || gj >= N) continue;
-    const int h = (a + 1) * HW + (c + 1);
-    const double pc = pl[h];
-    const double s = stencil_at(sd.k, N, gi, gj, pc, pl[h + HW], pl[h - HW], pl[h + 1], pl[h - 1]);
-    const int p = gi * N + gj;
-    Pi[p] = pc;
-    Si[p] = s;
-    pr += pc * sd.r[p];
-    ps += pc * s;
-  }
-  pr = block_sum(pr, lds);
-  ps = block_sum(ps, lds);
-  if (threadIdx.x == 0) {
-    sd.part[(size_t)blockIdx.x * NQ + 0] = pr;
-    sd.part[(size_t)blockIdx.x * NQ + 1] = ps;
-  }
-  if (!arrive_last(&st->tick[2], nb)) return;
-  const double PR = final_sum(sd.part, nb, 0, lds);
-  const double PS = final_sum(sd.part, nb, 1, lds);
-  if (threadIdx.x == 0) {
-    if (!(isfinite(PS) && isfinite(PR)) || !(PS > 0.0)) {
-      st->alpha = 0.0;
-      deactivate(st, sd.n_active, S_BREAK, i);
-    } else {
-      st->alpha = PR / PS;
-      st->ps_ring[i % ring] = PS;
-    }
-  }
-}
-
-// u += alpha p_i, r -= alpha s_i, ||r_{i+1}||^2 and the stopping test.
-__global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
-  __shared__ double lds[4];
-  const SysDev sd = sys[blockIdx.y];
-  SysState* st = sd.st;
-  if (!st->active) return;
-  const int i = st->i, ring = st->m_max + 1;
-  const double alpha = st->alpha;
-  const int n = N * N;
-  const int nb = flat_blocks(n);
-  const double* Pi = sd.P + (size_t)(i % ring) * n;
-  const double* Si = sd.S + (size_t)(i % ring) * n;
-  double acc = 0.0;
-  for (int e = 0; e < FLAT_PTS / 256; ++e) {
-    const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
-    if (p >= n) break;
-    sd.u[p] += alpha * Pi[p];
-    const double rv = sd.r[p] - alpha * Si[p];
-    sd.r[p] = rv;
-    acc += rv * rv;
-  }
-  acc = block_sum(acc, lds);
-  if (threadIdx.x == 0) sd.part[(size_t)blockIdx.x * NQ] = acc;
-  if (!arrive_last(&st->tick[3], nb)) return;
-  const double rr = final_sum(sd.part, nb, 0, lds);
-  if (threadIdx.x == 0) {
-    const double rho = sqrt(rr / st->rr0);
-    st->rr = rr;
-    st->snorm = sqrt(rr) / (double)N;
-    sd.hist[i + 1] = rho;
-    st->i = i + 1;
-    st->iters = i + 1;
-    if (!isfinite(rho)) deactivate(st, sd.n_active, S_BREAK, i + 1);
-    else if (rho <= st->rtol) deactivate(st, sd.n_active, S_OK, i + 1);
-    else if (i + 1 >= st->max_iter) deactivate(st, sd.n_active, S_NOTCONV, i + 1);
   }
 }
 
@@ -311,25 +356,43 @@ __global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
 
 static inline int flat_nb(int N) { return (N * N + FLAT_PTS - 1) / FLAT_PTS; }
 
+static void fin(const KrylovLaunch& L, int mode) {
+  hipLaunchKernelGGL(k_fin, dim3(L.nsys), dim3(256), 0, L.stream, L.sys, L.N, mode);
+}
+
 void launch_init_state(const KrylovLaunch& L, int max_iter, double rtol) {
   hipLaunchKernelGGL(k_init_state, dim3((L.nsys + 63) / 64), dim3(64), 0, L.stream, L.sys, L.nsys,
                      max_iter, L.m_max, rtol);
 }
 void launch_residual(const KrylovLaunch& L, int mode) {
   hipLaunchKernelGGL(k_residual, dim3(flat_nb(L.N), L.nsys), dim3(256), 0, L.stream, L.sys, L.N, mode);
+  fin(L, mode == 0 ? 3 : 4);
 }
 void launch_rnorm(const KrylovLaunch& L) {
   hipLaunchKernelGGL(k_rnorm, dim3(flat_nb(L.N), L.nsys), dim3(256), 0, L.stream, L.sys, L.N);
+  fin(L, 5);
 }
 void launch_wdots(const KrylovLaunch& L) {
-  hipLaunchKernelGGL(k_wdots, dim3(flat_nb(L.N), L.nsys), dim3(256), 0, L.stream, L.sys, L.N);
+  {
+    ProfScope ps(PK_WDOTS, L.stream);
+    hipLaunchKernelGGL(k_wdots, dim3(flat_nb(L.N), L.nsys), dim3(256), 0, L.stream, L.sys, L.N);
+  }
+  fin(L, 0);
 }
 void launch_dir(const KrylovLaunch& L) {
   const int nb = ((L.N + TILE_I - 1) / TILE_I) * ((L.N + TILE_J - 1) / TILE_J);
-  hipLaunchKernelGGL(k_dir, dim3(nb, L.nsys), dim3(256), 0, L.stream, L.sys, L.N);
+  {
+    ProfScope ps(PK_DIR, L.stream);
+    hipLaunchKernelGGL(k_dir, dim3(nb, L.nsys), dim3(256), 0, L.stream, L.sys, L.N);
+  }
+  fin(L, 1);
 }
 void launch_update(const KrylovLaunch& L) {
-  hipLaunchKernelGGL(k_update, dim3(flat_nb(L.N), L.nsys), dim3(256), 0, L.stream, L.sys, L.N);
+  {
+    ProfScope ps(PK_UPDATE, L.stream);
+    hipLaunchKernelGGL(k_update, dim3(flat_nb(L.N), L.nsys), dim3(256), 0, L.stream, L.sys, L.N);
+  }
+  fin(L, 2);
 }
 
 }  // namespace fcgno

@@ -23,6 +23,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "prof.h"
 
 namespace fcgno {
 
@@ -84,6 +85,12 @@ template <> struct Mf<PBF> {
 };
 
 __host__ __device__ inline int round16(int v) { return (v + 15) & ~15; }
+
+// CB contiguous elements of type T as one vector access.
+template <typename T, int CB>
+struct Vec {
+  typedef T type __attribute__((ext_vector_type(CB)));
+};
 
 // ---------------------------------------------------------------------------
 // Tables: E64/Eacc[m] = (cos, sin)(2 pi m / N); T[y][2q], T[y][2q+1] = cos, sin
@@ -152,29 +159,28 @@ __global__ __launch_bounds__(256) void k_rowdft(const SysDev* sys, int N, int M,
   if (x >= N) return;
   const int lane = threadIdx.x & 63;
   const int MP = round16(2 * M);
+  // harmonics q = 0..15 of e^{2 pi i y / N} by complex-multiplication recurrence
   double acc[32];
 #pragma unroll
   for (int q = 0; q < 32; ++q) acc[q] = 0.0;
   for (int y = lane; y < N; y += 64) {
     const double v = row_field<FIELD>(sd, N, x, y);
-    int idx = 0;
+    const double c1 = E64[2 * y], s1 = E64[2 * y + 1];
+    double c = 1.0, sn = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      if (q < M) {
-        acc[2 * q] += v * E64[2 * idx];
-        acc[2 * q + 1] += v * E64[2 * idx + 1];
-        idx += y;
-        if (idx >= N) idx -= N;
-      }
+      acc[2 * q] += v * c;
+      acc[2 * q + 1] += v * sn;
+      const double cn = c * c1 - sn * s1;
+      sn = sn * c1 + c * s1;
+      c = cn;
     }
   }
   double* out = (FIELD == 0 ? sd.Gr : out_base + out_sys_stride * blockIdx.y) + (size_t)x * MP;
 #pragma unroll
   for (int q = 0; q < 32; ++q) {
-    if (q < 2 * M) {
-      const double s = wave_sum(acc[q]);
-      if (lane == 0) out[q] = s;
-    }
+    const double s = wave_sum(acc[q]);
+    if (lane == 0 && q < 2 * M) out[q] = s;
   }
 }
 
@@ -228,117 +234,227 @@ __global__ __launch_bounds__(256) void k_vconst(const SysDev* sys, int N, int M,
 }
 
 // ---------------------------------------------------------------------------
-// Spectral part of one layer for one ky.
+// Spectral part of one layer, two launches.
+//   k_spec_fwd (grid M x systems): for one ky, the x-direction forward DFT of
+//     the row partials, V^[c][a] = sum_x (Gc - i Gs)[x][c] e^{-2 pi i kx_a x/N}
+//     (rows staged through LDS in chunks of 64), then the per-mode mixing
+//     W^[o][a] = sum_c V^[c][a] R[c][o][a][ky], written to Wh[ky][o][a].
+//     Layer 0 builds V^ from the DFT of r and the per-solve constant part.
+//   k_spec_inv (grid N/16 x systems): the x-direction synthesis
+//     H[x][o][ky] = sum_a W^[o][a][ky] e^{+2 pi i kx_a x/N}, written as the
+//     complete rows Hc[x][o][.] = (N^-2 g_ky Re H, -N^-2 g_ky Im H), g_0 = 1,
+//     g_ky = 2 otherwise.
 // ---------------------------------------------------------------------------
 struct SpecArgs {
   const SysDev* sys;
-  int N, S, M, layer0;
+  int N, S, M, layer0, XS;   // XS: x-chunks of SX rows in the forward transform
   const void* Eacc;
   const double* E64;
   const void* R;     // [M][2M][C][C] complex, accumulate precision
   const void* WL0;   // [C] accumulate precision
 };
 
+constexpr int SX = 64;   // rows per chunk in the forward transform
+
+// Partial forward x-DFT over one chunk of SX rows for one ky:
+// Vp[ky][xs][c][a] = sum_{x in chunk} (Gc - i Gs)[x][c] e^{-2 pi i kx_a x / N}.
+// Layer 0 transforms the single channel of r's row partials instead.
 template <int PREC, int C>
-__global__ __launch_bounds__(256) void k_spectral(SpecArgs a) {
+__global__ __launch_bounds__(256) void k_spec_fwd(SpecArgs a) {
   using M_ = Mf<PREC>;
-  using in_t = typename M_::in_t;
   using acc_t = typename M_::acc_t;
-  __shared__ acc_t Vr[C][33], Vi[C][33], Wr[C][33], Wi[C][33];
-  __shared__ double Rr[32], Ri[32];
+  constexpr int CH = C;                        // channels per chunk row
+  constexpr int LPT = SX * CH / 256;           // loads per thread
+  __shared__ acc_t Gr_[SX][CH + 1], Gi_[SX][CH + 1];
+  __shared__ acc_t Er_[32][SX + 1], Ei_[32][SX + 1];
+  const int ky = blockIdx.x, xs = blockIdx.y;
+  const SysDev sd = a.sys[blockIdx.z];
+  if (!sd.st->active) return;
+  const int N = a.N, M = a.M, twoM = 2 * M, MP = round16(twoM);
+  const int x0 = xs * SX, nx = min(SX, N - x0);
+  const acc_t* E = (const acc_t*)a.Eacc;
+  const int t = threadIdx.x;
+  acc_t* Vp = (acc_t*)sd.Vp + ((size_t)(ky * a.XS + xs) * C) * twoM * 2;
+  for (int q = t; q < twoM * SX; q += 256) {
+    const int kx = q / SX, xl = q - kx * SX;
+    const int kv = kx < M ? kx : N - twoM + kx;
+    const int idx = (int)(((long long)kv * (x0 + xl)) % N);
+    Er_[kx][xl] = E[2 * idx];
+    Ei_[kx][xl] = -E[2 * idx + 1];
+  }
+  if (a.layer0) {
+    if (t < SX) {
+      const bool v = t < nx;
+      Gr_[t][0] = v ? (acc_t)sd.Gr[(size_t)(x0 + t) * MP + 2 * ky] : (acc_t)0;
+      Gi_[t][0] = v ? (acc_t)(-sd.Gr[(size_t)(x0 + t) * MP + 2 * ky + 1]) : (acc_t)0;
+    }
+    __syncthreads();
+    if (t < twoM) {
+      acc_t sr = 0, si = 0;
+      for (int xl = 0; xl < nx; ++xl) {
+        const acc_t gr = Gr_[xl][0], gi = Gi_[xl][0], er = Er_[t][xl], ei = Ei_[t][xl];
+        sr += gr * er - gi * ei;
+        si += gr * ei + gi * er;
+      }
+      Vp[2 * t] = sr;
+      Vp[2 * t + 1] = si;
+    }
+    return;
+  }
+  const acc_t* Gp = (const acc_t*)sd.Gp;
+  acc_t gc[LPT], gs[LPT];
+#pragma unroll
+  for (int u = 0; u < LPT; ++u) {
+    const int q = t + 256 * u;
+    const int xl = q / CH, c = q - xl * CH;
+    gc[u] = 0;
+    gs[u] = 0;
+    if (xl < nx) {
+      for (int sg = 0; sg < a.S; ++sg) {
+        const acc_t* row = Gp + (size_t)((x0 + xl) * a.S + sg) * MP * C;
+        gc[u] += row[(2 * ky) * C + c];
+        gs[u] += row[(2 * ky + 1) * C + c];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < LPT; ++u) {
+    const int q = t + 256 * u;
+    const int xl = q / CH, c = q - xl * CH;
+    Gr_[xl][c] = gc[u];
+    Gi_[xl][c] = -gs[u];
+  }
+  __syncthreads();
+  for (int q = t; q < C * twoM; q += 256) {
+    const int c = q % C, kx = q / C;
+    acc_t sr = 0, si = 0;
+    for (int xl = 0; xl < nx; ++xl) {
+      const acc_t gr = Gr_[xl][c], gi = Gi_[xl][c], er = Er_[kx][xl], ei = Ei_[kx][xl];
+      sr += gr * er - gi * ei;
+      si += gr * ei + gi * er;
+    }
+    Vp[2 * (c * twoM + kx)] = sr;
+    Vp[2 * (c * twoM + kx) + 1] = si;
+  }
+}
+
+// Sum of the chunk partials in chunk order and the per-mode mixing
+// W^[o][a] = sum_c V^[c][a] R[c][o][a][ky], written to Wh[ky][o][a].
+template <int PREC, int C>
+__global__ __launch_bounds__(256) void k_spec_mix(SpecArgs a) {
+  using M_ = Mf<PREC>;
+  using acc_t = typename M_::acc_t;
+  __shared__ acc_t Vr[C][33], Vi[C][33];
   const int ky = blockIdx.x;
   const SysDev sd = a.sys[blockIdx.y];
   if (!sd.st->active) return;
-  const int N = a.N, M = a.M, twoM = 2 * M, MP = round16(twoM);
-  const acc_t* E = (const acc_t*)a.Eacc;
+  const int M = a.M, twoM = 2 * M;
+  const int t = threadIdx.x;
+  const acc_t* Vp = (const acc_t*)sd.Vp + (size_t)ky * a.XS * C * twoM * 2;
   if (a.layer0) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int kx = wv; kx < twoM; kx += 4) {
-      const int kv = kx < M ? kx : N - twoM + kx;
-      double sr = 0.0, si = 0.0;
-      int idx = (int)(((long long)kv * lane) % N);
-      const int step = (int)(((long long)kv * 64) % N);
-      for (int x = lane; x < N; x += 64) {
-        const double gc = sd.Gr[(size_t)x * MP + 2 * ky], gs = sd.Gr[(size_t)x * MP + 2 * ky + 1];
-        const double c = a.E64[2 * idx], s = a.E64[2 * idx + 1];
-        sr += gc * c - gs * s;
-        si -= gc * s + gs * c;
-        idx += step;
-        if (idx >= N) idx -= N;
-      }
-      sr = wave_sum(sr);
-      si = wave_sum(si);
-      if (lane == 0) {
-        Rr[kx] = sr;
-        Ri[kx] = si;
-      }
-    }
-    __syncthreads();
     const double snorm = sd.st->snorm;
     const double inv_s = snorm > 0.0 ? 1.0 / snorm : 0.0;
-    for (int t = threadIdx.x; t < C * twoM; t += 256) {
-      const int c = t / twoM, kx = t - c * twoM;
+    for (int q = t; q < C * twoM; q += 256) {
+      const int c = q / twoM, kx = q - c * twoM;
+      acc_t rr = 0, ri = 0;
+      for (int xs = 0; xs < a.XS; ++xs) {
+        rr += Vp[(size_t)xs * C * twoM * 2 + 2 * kx];
+        ri += Vp[(size_t)xs * C * twoM * 2 + 2 * kx + 1];
+      }
       const double wl = (double)((const acc_t*)a.WL0)[c] * inv_s;
       const acc_t* vc = (const acc_t*)sd.Vc + 2 * ((size_t)(c * twoM + kx) * M + ky);
-      Vr[c][kx] = (acc_t)(wl * Rr[kx]) + vc[0];
-      Vi[c][kx] = (acc_t)(wl * Ri[kx]) + vc[1];
+      Vr[c][kx] = (acc_t)(wl * (double)rr) + vc[0];
+      Vi[c][kx] = (acc_t)(wl * (double)ri) + vc[1];
     }
   } else {
-    const acc_t* Gp = (const acc_t*)sd.Gp;
-    for (int t = threadIdx.x; t < C * twoM; t += 256) {
-      const int c = t % C, kx = t / C;
-      const int kv = kx < M ? kx : N - twoM + kx;
-      acc_t sr = 0, si = 0;
-      int idx = 0;
-      for (int x = 0; x < N; ++x) {
-        acc_t gc = 0, gs = 0;
-        for (int sg = 0; sg < a.S; ++sg) {
-          const acc_t* row = Gp + (size_t)(x * a.S + sg) * MP * C;
-          gc += row[(2 * ky) * C + c];
-          gs += row[(2 * ky + 1) * C + c];
-        }
-        const acc_t cs = E[2 * idx], sn = E[2 * idx + 1];
-        sr += gc * cs - gs * sn;
-        si -= gc * sn + gs * cs;
-        idx += kv;
-        if (idx >= N) idx -= N;
+    for (int q = t; q < C * twoM; q += 256) {
+      const int c = q / twoM, kx = q - c * twoM;
+      acc_t vr = 0, vi = 0;
+      for (int xs = 0; xs < a.XS; ++xs) {
+        vr += Vp[(size_t)xs * C * twoM * 2 + 2 * q];
+        vi += Vp[(size_t)xs * C * twoM * 2 + 2 * q + 1];
       }
-      Vr[c][kx] = sr;
-      Vi[c][kx] = si;
+      Vr[c][kx] = vr;
+      Vi[c][kx] = vi;
     }
   }
   __syncthreads();
+  const int MP = round16(twoM);
   const acc_t* R = (const acc_t*)a.R + (size_t)ky * twoM * C * C * 2;
-  for (int t = threadIdx.x; t < C * twoM; t += 256) {
-    const int o = t % C, kx = t / C;
+  acc_t* Wh = (acc_t*)sd.Wh + (size_t)ky * C * MP * 2;
+  for (int q = t; q < C * twoM; q += 256) {
+    const int o = q % C, kx = q / C;
     const acc_t* Rk = R + (size_t)kx * C * C * 2;
     acc_t sr = 0, si = 0;
+#pragma unroll 8
     for (int c = 0; c < C; ++c) {
       const acc_t rr = Rk[2 * (c * C + o)], ri = Rk[2 * (c * C + o) + 1];
       sr += Vr[c][kx] * rr - Vi[c][kx] * ri;
       si += Vr[c][kx] * ri + Vi[c][kx] * rr;
     }
-    Wr[o][kx] = sr;
-    Wi[o][kx] = si;
+    Wh[2 * (o * MP + kx)] = sr;
+    Wh[2 * (o * MP + kx) + 1] = si;
+  }
+}
+
+// x-direction synthesis for SR rows: H[x][o][ky] = sum_a W^[ky][o][a]
+// e^{+2 pi i kx_a x/N}, staged in LDS as complete rows Hc[x][o][0..MP) and
+// written out contiguously.
+template <int PREC> struct SynthRows { static constexpr int SR = 16; };
+template <> struct SynthRows<P64> { static constexpr int SR = 8; };
+
+template <int PREC, int C, int MP>
+__global__ __launch_bounds__(256) void k_spec_inv(SpecArgs a) {
+  using M_ = Mf<PREC>;
+  using in_t = typename M_::in_t;
+  using acc_t = typename M_::acc_t;
+  constexpr int SR = SynthRows<PREC>::SR;
+  __shared__ acc_t Er_[SR][MP], Ei_[SR][MP];   // zero for kx >= 2M
+  __shared__ __attribute__((aligned(16))) in_t tile[SR * C * MP];
+  const SysDev sd = a.sys[blockIdx.y];
+  if (!sd.st->active) return;
+  const int N = a.N, M = a.M, twoM = 2 * M;
+  const int x0 = blockIdx.x * SR;
+  const int nx = min(SR, N - x0);
+  const acc_t* E = (const acc_t*)a.Eacc;
+  const int t = threadIdx.x;
+  for (int q = t; q < SR * MP; q += 256) {
+    const int xl = q / MP, kx = q - xl * MP;
+    const int kv = kx < M ? kx : N - twoM + kx;
+    const int idx = (int)(((long long)kv * (x0 + xl)) % N);
+    Er_[xl][kx] = kx < twoM ? E[2 * idx] : (acc_t)0;
+    Ei_[xl][kx] = kx < twoM ? E[2 * idx + 1] : (acc_t)0;
+  }
+  for (int q = t; q < SR * C * MP; q += 256) tile[q] = M_::cvt((acc_t)0);
+  __syncthreads();
+  const double scale = 1.0 / ((double)N * (double)N);
+  for (int q = t; q < C * M; q += 256) {
+    const int o = q / M, ky = q - o * M;
+    const acc_t* Wh = (const acc_t*)sd.Wh + ((size_t)ky * C + o) * MP * 2;   // zero past 2M
+    acc_t wr[MP], wi[MP];
+#pragma unroll
+    for (int kx = 0; kx < MP; ++kx) {
+      wr[kx] = Wh[2 * kx];
+      wi[kx] = Wh[2 * kx + 1];
+    }
+    const acc_t sc = (acc_t)((ky == 0 ? 1.0 : 2.0) * scale);
+    for (int xl = 0; xl < nx; ++xl) {
+      acc_t hr = 0, hi = 0;
+#pragma unroll
+      for (int kx = 0; kx < MP; ++kx) {
+        hr += wr[kx] * Er_[xl][kx] - wi[kx] * Ei_[xl][kx];
+        hi += wr[kx] * Ei_[xl][kx] + wi[kx] * Er_[xl][kx];
+      }
+      tile[(xl * C + o) * MP + 2 * ky] = M_::cvt(sc * hr);
+      tile[(xl * C + o) * MP + 2 * ky + 1] = M_::cvt(-sc * hi);
+    }
   }
   __syncthreads();
-  const acc_t sc = (acc_t)((ky == 0 ? 1.0 : 2.0) / ((double)N * (double)N));
-  in_t* Hc = (in_t*)sd.Hc;
-  for (int t = threadIdx.x; t < N * C; t += 256) {
-    const int x = t / C, o = t - x * C;
-    acc_t hr = 0, hi = 0;
-    int idx = 0;
-    for (int kx = 0; kx < twoM; ++kx) {
-      if (kx == M) idx = (int)(((long long)(N - M) * x) % N);
-      const acc_t cs = E[2 * idx], sn = E[2 * idx + 1];
-      hr += Wr[o][kx] * cs - Wi[o][kx] * sn;
-      hi += Wr[o][kx] * sn + Wi[o][kx] * cs;
-      idx += x;
-      if (idx >= N) idx -= N;
-    }
-    Hc[((size_t)x * C + o) * MP + 2 * ky] = M_::cvt(sc * hr);
-    Hc[((size_t)x * C + o) * MP + 2 * ky + 1] = M_::cvt(-sc * hi);
-  }
+  // contiguous copy of rows x0 .. x0+nx-1 (nx*C*MP elements, a multiple of 16 bytes)
+  const int nbytes = nx * C * MP * (int)sizeof(in_t);
+  const uint4* src = (const uint4*)tile;
+  uint4* dst = (uint4*)((char*)sd.Hc + (size_t)x0 * C * MP * sizeof(in_t));
+  for (int q = t; q < nbytes / 16; q += 256) dst[q] = src[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -369,6 +485,13 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
   constexpr int KIN = FEAT ? 1 : C / KSTEP;
   constexpr int KWP = KIN * KSTEP;
   constexpr int MB = MP / 16;
+  // Activations are stored [point][C] in channel order.  Lane group g loads the
+  // CB = C/4 contiguous channels [g*CB, (g+1)*CB) of its point with one vector
+  // access; input K-step ks, element e then carries channel g*CB + ks*KPL + e
+  // (the host lays out the bypass weights in that order).
+  constexpr int CB = C / 4;
+  constexpr int PADE = 16 / (int)sizeof(in_t);   // LDS row padding, 16 bytes
+  __shared__ __attribute__((aligned(16))) in_t otile[4][16 * (C + PADE)];
   const int lane = threadIdx.x & 63;
   const int n16 = lane & 15, g = lane >> 4;
   const SysDev sd = a.sys[blockIdx.y];
@@ -409,18 +532,53 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
   const double inv_s = snorm > 0.0 ? 1.0 / snorm : 0.0;
   const double h = 1.0 / (double)(N + 1);
 
+  // Operands of one 16-point tile: A fragments (twiddles and inputs); for the
+  // feature layer the raw features.  Loaded one tile ahead of their use.
+  struct TileIn {
+    frag_t Af[KT + KIN];
+    double rr;
+    acc_t lk;
+  };
+  auto load_tile = [&](int t, TileIn& ti) {
+    const int y0 = t * 16;
+    const int ya = y0 + n16;
+    const bool va = ya < N;
+#pragma unroll
+    for (int ks = 0; ks < KT; ++ks) ti.Af[ks] = M_::ld(T + ya * MP + ks * KSTEP + g * KPL);
+    if constexpr (FEAT) {
+      ti.rr = va ? sd.r[(size_t)x * N + ya] : 0.0;
+      ti.lk = va ? M_::up(((const in_t*)sd.logk)[(size_t)x * N + ya]) : (acc_t)0;
+    } else {
+      typedef typename Vec<in_t, CB>::type vec_t;
+      vec_t vv = {};
+      if (va) vv = *(const vec_t*)(act_in + (size_t)ya * C + g * CB);
+#pragma unroll
+      for (int ks = 0; ks < KIN; ++ks) {
+        if constexpr (KPL == 4) {
+          ti.Af[KT + ks] = short4_t{(short)vv[ks * 4 + 0], (short)vv[ks * 4 + 1], (short)vv[ks * 4 + 2],
+                                    (short)vv[ks * 4 + 3]};
+        } else {
+          ti.Af[KT + ks] = vv[ks];
+        }
+      }
+    }
+  };
+  TileIn nxt;
+  if (t0 < t1) load_tile(t0, nxt);
   for (int t = t0; t < t1; ++t) {
     const int y0 = t * 16;
     const int ya = y0 + n16;
     const bool va = ya < N;
+    TileIn cur = nxt;
+    if (t + 1 < t1) load_tile(t + 1, nxt);
     frag_t Af[KT + KIN];
 #pragma unroll
-    for (int ks = 0; ks < KT; ++ks) Af[ks] = M_::ld(T + ya * MP + ks * KSTEP + g * KPL);
+    for (int ks = 0; ks < KT + KIN; ++ks) Af[ks] = cur.Af[ks];
     if constexpr (FEAT) {
       acc_t f0 = 0, f1 = 0, f2 = 0, f3 = 0;
       if (va) {
-        f0 = (acc_t)(sd.r[(size_t)x * N + ya] * inv_s);
-        f1 = M_::up(((const in_t*)sd.logk)[(size_t)x * N + ya]);
+        f0 = (acc_t)(cur.rr * inv_s);
+        f1 = cur.lk;
         f2 = (acc_t)((double)(x + 1) * h);
         f3 = (acc_t)((double)(ya + 1) * h);
       }
@@ -431,64 +589,66 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
         const acc_t fv = g == 0 ? f0 : (g == 1 ? f1 : (g == 2 ? f2 : f3));
         Af[KT] = (frag_t)fv;
       }
-    } else {
-#pragma unroll
-      for (int ks = 0; ks < KIN; ++ks)
-        Af[KT + ks] = va ? M_::ld(act_in + (size_t)ya * C + ks * KSTEP + g * KPL) : M_::zero();
     }
     accv_t acc[NOB];
 #pragma unroll
     for (int ob = 0; ob < NOB; ++ob) {
       acc[ob] = accv_t{bias[ob], bias[ob], bias[ob], bias[ob]};
+      // twiddle columns past 2M are zero in T and Hc, so every K-step runs
 #pragma unroll
-      for (int ks = 0; ks < KT; ++ks)
-        if (ks * KSTEP < twoM) acc[ob] = M_::mma(Af[ks], Bf[ks][ob], acc[ob]);
+      for (int ks = 0; ks < KT; ++ks) acc[ob] = M_::mma(Af[ks], Bf[ks][ob], acc[ob]);
 #pragma unroll
       for (int ks = 0; ks < KIN; ++ks) acc[ob] = M_::mma(Af[KT + ks], Bf[KT + ks][ob], acc[ob]);
     }
     // lane holds z[y0 + row(g, i)][ob*16 + n16]
-    acc_t v[NOB][4];
-#pragma unroll
-    for (int ob = 0; ob < NOB; ++ob)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int yv = y0 + M_::row(g, i);
-        const acc_t gv = gelu(acc[ob][i]);
-        v[ob][i] = yv < N ? (PROJ ? gv : M_::up(M_::cvt(gv))) : (acc_t)0;
-      }
     if constexpr (PROJ) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
+        const int yv = y0 + M_::row(g, i);
         acc_t part = 0;
 #pragma unroll
-        for (int ob = 0; ob < NOB; ++ob) part += wp[ob] * v[ob][i];
+        for (int ob = 0; ob < NOB; ++ob) part += wp[ob] * gelu(acc[ob][i]);
         part += __shfl_xor(part, 1, 64);
         part += __shfl_xor(part, 2, 64);
         part += __shfl_xor(part, 4, 64);
         part += __shfl_xor(part, 8, 64);
-        const int yv = y0 + M_::row(g, i);
         if (n16 == i && yv < N) sd.w[(size_t)x * N + yv] = snorm * ((double)part + a.bP);
       }
     } else {
+      // v' = GELU(z) rounded once to the op precision; rows past N are zero
+      in_t hv[NOB][4];
 #pragma unroll
       for (int ob = 0; ob < NOB; ++ob)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int yv = y0 + M_::row(g, i);
-          if (yv < N) act_out[(size_t)yv * C + ob * 16 + n16] = M_::cvt(v[ob][i]);
+          const acc_t gv = gelu(acc[ob][i]);
+          hv[ob][i] = M_::cvt(yv < N ? gv : (acc_t)0);
         }
-      if constexpr (KPL == 4) {
-        frag_t B2[NOB];
+      // transpose the 16 x C tile through LDS, then 16-byte coalesced stores
+      in_t* ot = otile[threadIdx.x >> 6];
 #pragma unroll
-        for (int ob = 0; ob < NOB; ++ob)
-          B2[ob] = short4_t{(short)f2bf(v[ob][0]), (short)f2bf(v[ob][1]), (short)f2bf(v[ob][2]),
-                            (short)f2bf(v[ob][3])};
+      for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ot[M_::row(g, i) * (C + PADE) + ob * 16 + n16] = hv[ob][i];
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      constexpr int CPR = C * (int)sizeof(in_t) / 16;   // 16-byte chunks per point
+      for (int q = lane; q < 16 * CPR; q += 64) {
+        const int pt = q / CPR, ch = q - pt * CPR;
+        if (y0 + pt < N) {
+          const uint4 val = *(const uint4*)((const char*)ot + pt * (C + PADE) * sizeof(in_t) + ch * 16);
+          *(uint4*)((char*)act_out + ((size_t)(y0 + pt) * C) * sizeof(in_t) + ch * 16) = val;
+        }
+      }
+      // next layer's y-direction analysis: G2[j][o] += sum_y T[y][j] v'[y][o]
+      if constexpr (KPL == 4) {
 #pragma unroll
         for (int jb = 0; jb < MB; ++jb) {
-          if (jb * 16 < twoM) {
-            const frag_t A2 = M_::ld(TT + (jb * 16 + n16) * NP + y0 + 4 * g);
+          const frag_t A2 = M_::ld(TT + (jb * 16 + n16) * NP + y0 + 4 * g);
 #pragma unroll
-            for (int ob = 0; ob < NOB; ++ob) G2[jb][ob] = M_::mma(A2, B2[ob], G2[jb][ob]);
+          for (int ob = 0; ob < NOB; ++ob) {
+            const frag_t B2 = short4_t{(short)hv[ob][0], (short)hv[ob][1], (short)hv[ob][2], (short)hv[ob][3]};
+            G2[jb][ob] = M_::mma(A2, B2, G2[jb][ob]);
           }
         }
       } else {
@@ -497,11 +657,9 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
           const int yv = y0 + M_::row(g, i);
 #pragma unroll
           for (int jb = 0; jb < MB; ++jb) {
-            if (jb * 16 < twoM) {
-              const frag_t A2 = T[yv * MP + jb * 16 + n16];
+            const frag_t A2 = T[yv * MP + jb * 16 + n16];
 #pragma unroll
-              for (int ob = 0; ob < NOB; ++ob) G2[jb][ob] = M_::mma(A2, (frag_t)v[ob][i], G2[jb][ob]);
-            }
+            for (int ob = 0; ob < NOB; ++ob) G2[jb][ob] = M_::mma(A2, (frag_t)hv[ob][i], G2[jb][ob]);
           }
         }
       }
@@ -566,13 +724,27 @@ static void layer_dispatch(const NOLaunch& L, const LayerArgs& la, bool feat, bo
 
 template <int PREC, int C>
 static void apply_pc(const NOLaunch& L) {
-  hipLaunchKernelGGL(k_rowdft<0>, dim3((L.N + 3) / 4, L.nsys), dim3(256), 0, L.stream, L.sys, L.N, L.M,
-                     L.tab.E64, (double*)nullptr, (size_t)0);
+  {
+    ProfScope ps(PK_ROWDFT, L.stream);
+    hipLaunchKernelGGL(k_rowdft<0>, dim3((L.N + 3) / 4, L.nsys), dim3(256), 0, L.stream, L.sys, L.N, L.M,
+                       L.tab.E64, (double*)nullptr, (size_t)0);
+  }
   for (int l = 0; l < L.L; ++l) {
-    SpecArgs sa{L.sys, L.N, L.S, L.M, l == 0 ? 1 : 0, L.tab.Eacc, L.tab.E64, L.Rmix[l], L.WL0};
-    hipLaunchKernelGGL((k_spectral<PREC, C>), dim3(L.M, L.nsys), dim3(256), 0, L.stream, sa);
+    const int XS = (L.N + SX - 1) / SX;
+    SpecArgs sa{L.sys, L.N, L.S, L.M, l == 0 ? 1 : 0, XS, L.tab.Eacc, L.tab.E64, L.Rmix[l], L.WL0};
+    {
+      ProfScope ps(PK_SPECTRAL, L.stream);
+      constexpr int SR = SynthRows<PREC>::SR;
+      hipLaunchKernelGGL((k_spec_fwd<PREC, C>), dim3(L.M, XS, L.nsys), dim3(256), 0, L.stream, sa);
+      hipLaunchKernelGGL((k_spec_mix<PREC, C>), dim3(L.M, L.nsys), dim3(256), 0, L.stream, sa);
+      if (L.MP == 16)
+        hipLaunchKernelGGL((k_spec_inv<PREC, C, 16>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(256), 0, L.stream, sa);
+      else
+        hipLaunchKernelGGL((k_spec_inv<PREC, C, 32>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(256), 0, L.stream, sa);
+    }
     LayerArgs la{L.sys, L.N, L.S, 2 * L.M, 0, 0, L.tab.T, L.tab.TT, L.Wfrag[l], L.bias[l], L.WP, L.bP};
     const bool feat = l == 0, proj = l == L.L - 1;
+    ProfScope ps(PK_LAYER, L.stream);
     if (L.MP == 16) layer_dispatch<PREC, C, 16>(L, la, feat, proj);
     else layer_dispatch<PREC, C, 32>(L, la, feat, proj);
   }
