@@ -149,6 +149,54 @@ fcgno_status fcgno_precond_apply(const fcgno_model* m, int32_t n, int32_t batch,
                                  void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Training (Sec. 3.1): the operator is trained on the error form of the      */
+/* Notay loss, mean_b ||B(r_b) - e_b||_A / ||e_b||_A with e_b = A^-1 r_b, on  */
+/* residuals drawn from Krylov subspaces; the backward pass is hand-written.  */
+/* Training precisions: FCGNO_OP_FP64 or FCGNO_OP_FP32.  The model's float64  */
+/* master weights live on the device and are updated in place.               */
+/* ------------------------------------------------------------------------ */
+typedef struct fcgno_optim fcgno_optim;
+
+/* AdamW with decoupled weight decay (the optimiser of the training table):
+ * theta <- theta (1 - lr wd), then the Adam step with bias-corrected moments.
+ * Errors: E_INVALID (lr <= 0, wd < 0, betas outside [0,1), eps <= 0), E_HIP. */
+fcgno_status fcgno_optim_create(const fcgno_model* m, double lr, double weight_decay, double beta1,
+                                double beta2, double eps, fcgno_optim** out);
+fcgno_status fcgno_optim_set_lr(fcgno_optim* o, double lr);
+void fcgno_optim_destroy(fcgno_optim* o);
+
+/* Workspace of fcgno_op_forward / fcgno_op_backward / fcgno_train_step. */
+size_t fcgno_train_workspace_bytes(const fcgno_model* m, int32_t n, int32_t batch, int32_t op);
+
+/* w = B(r) (device [batch][N][N]) keeping the activations the backward pass
+ * needs in ws.  k, r as for fcgno_precond_apply.  Asynchronous. */
+fcgno_status fcgno_op_forward(const fcgno_model* m, int32_t n, int32_t batch, int32_t op,
+                              const double* k, const double* r, double* w,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* Gradient of sum_b <grad_w_b, B(r_b)> with respect to the weights, written
+ * to grad_params (device float64, blob order, every entry overwritten).
+ * Must follow fcgno_op_forward with the same model, k, r and ws. */
+fcgno_status fcgno_op_backward(const fcgno_model* m, int32_t n, int32_t batch, int32_t op,
+                               const double* k, const double* r, const double* grad_w,
+                               double* grad_params, void* ws, size_t ws_bytes, void* stream);
+
+/* Energy-norm loss per system, loss_dev[b] = ||w_b - e_b||_A / ||e_b||_A
+ * (device [batch]), and if grad_w is not NULL the gradient of the batch mean,
+ * grad_w[b] = A (w_b - e_b) / (batch ||w_b - e_b||_A ||e_b||_A).  Async. */
+size_t fcgno_energy_loss_workspace_bytes(int32_t n, int32_t batch);
+fcgno_status fcgno_energy_loss(int32_t n, int32_t batch, const double* k, const double* w,
+                               const double* e, double* loss_dev, double* grad_w,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* One step: forward, loss on (r, e) pairs (device [batch][N][N] each),
+ * backward, AdamW update of the model.  loss_host (nullable) receives the
+ * batch-mean loss before the update; the call then synchronises the stream. */
+fcgno_status fcgno_train_step(fcgno_model* m, fcgno_optim* opt, int32_t n, int32_t batch, int32_t op,
+                              const double* k, const double* r, const double* e, double* loss_host,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing: HIP event pairs recorded on the launch stream around each   */
 /* launch of a kernel family while enabled; read after the work completed.    */
 /* kernel ids: 0 operator layer kernel (matrix cores), 1 operator spectral    */

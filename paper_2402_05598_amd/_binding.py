@@ -63,6 +63,25 @@ def lib():
     L.fcgno_precond_workspace_bytes.restype = c_size_t
     L.fcgno_precond_apply.argtypes = [vp, c_int32, c_int32, c_int32, vp, vp, vp, vp, c_size_t, vp]
     L.fcgno_precond_apply.restype = c_int32
+    L.fcgno_optim_create.argtypes = [vp, c_double, c_double, c_double, c_double, c_double, POINTER(vp)]
+    L.fcgno_optim_create.restype = c_int32
+    L.fcgno_optim_set_lr.argtypes = [vp, c_double]
+    L.fcgno_optim_set_lr.restype = c_int32
+    L.fcgno_optim_destroy.argtypes = [vp]
+    L.fcgno_optim_destroy.restype = None
+    L.fcgno_train_workspace_bytes.argtypes = [vp, c_int32, c_int32, c_int32]
+    L.fcgno_train_workspace_bytes.restype = c_size_t
+    L.fcgno_op_forward.argtypes = [vp, c_int32, c_int32, c_int32, vp, vp, vp, vp, c_size_t, vp]
+    L.fcgno_op_forward.restype = c_int32
+    L.fcgno_op_backward.argtypes = [vp, c_int32, c_int32, c_int32, vp, vp, vp, vp, vp, c_size_t, vp]
+    L.fcgno_op_backward.restype = c_int32
+    L.fcgno_energy_loss_workspace_bytes.argtypes = [c_int32, c_int32]
+    L.fcgno_energy_loss_workspace_bytes.restype = c_size_t
+    L.fcgno_energy_loss.argtypes = [c_int32, c_int32, vp, vp, vp, vp, vp, vp, c_size_t, vp]
+    L.fcgno_energy_loss.restype = c_int32
+    L.fcgno_train_step.argtypes = [vp, vp, c_int32, c_int32, c_int32, vp, vp, vp, POINTER(c_double), vp,
+                                   c_size_t, vp]
+    L.fcgno_train_step.restype = c_int32
     L.fcgno_profile_enable.argtypes = [c_int32]
     L.fcgno_profile_enable.restype = None
     L.fcgno_profile_reset.argtypes = []
@@ -217,3 +236,112 @@ def profile_read(kernel):
     _check(lib().fcgno_profile_read(PROFILE_KERNELS[kernel], ctypes.byref(n), ctypes.byref(ms)),
            "fcgno_profile_read")
     return int(n.value), float(ms.value)
+
+
+# ---------------------------------------------------------------------------
+# Training
+# ---------------------------------------------------------------------------
+
+class Optim:
+    """AdamW state on the device for one model (decoupled weight decay)."""
+
+    def __init__(self, model, lr=1e-3, weight_decay=1e-2, beta1=0.9, beta2=0.999, eps=1e-8):
+        h = ctypes.c_void_p()
+        _check(lib().fcgno_optim_create(model.handle, lr, weight_decay, beta1, beta2, eps, ctypes.byref(h)),
+               "fcgno_optim_create")
+        self.handle = h
+        self.lr = lr
+
+    def set_lr(self, lr):
+        _check(lib().fcgno_optim_set_lr(self.handle, lr), "fcgno_optim_set_lr")
+        self.lr = lr
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().fcgno_optim_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def train_workspace(model, n, batch, op="fp32", device=None):
+    nbytes = lib().fcgno_train_workspace_bytes(model.handle, n, batch, OP[op])
+    if nbytes == 0:
+        raise FcgnoError("invalid training shape: " + lib().fcgno_last_error().decode(errors="replace"))
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device or torch.device("cuda"))
+
+
+def op_forward(model, k, r, op="fp64", workspace=None, stream=None):
+    """w = B(r), keeping the activations for op_backward in the workspace."""
+    B, N = r.shape[0], r.shape[-1]
+    ws = workspace if workspace is not None else train_workspace(model, N, B, op, r.device)
+    w = torch.empty_like(r)
+    _check(lib().fcgno_op_forward(model.handle, N, B, OP[op], _dev_f64(k, "k"), _dev_f64(r, "r"),
+                                  _dev_f64(w, "w"), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+           "fcgno_op_forward")
+    return w, ws
+
+
+def op_backward(model, k, r, grad_w, ws, op="fp64", stream=None):
+    """Gradient of sum <grad_w, B(r)> with respect to the weight blob (device float64)."""
+    B, N = r.shape[0], r.shape[-1]
+    g = torch.empty(model.n_weights, dtype=torch.float64, device=r.device)
+    _check(lib().fcgno_op_backward(model.handle, N, B, OP[op], _dev_f64(k, "k"), _dev_f64(r, "r"),
+                                   _dev_f64(grad_w.contiguous(), "grad_w"), _dev_f64(g, "grad"),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+           "fcgno_op_backward")
+    return g
+
+
+def energy_loss(k, w, e, grad=True, stream=None):
+    """Per-system ||w-e||_A/||e||_A and (optionally) the gradient of their mean."""
+    B, N = w.shape[0], w.shape[-1]
+    nbytes = lib().fcgno_energy_loss_workspace_bytes(N, B)
+    ws = torch.empty(int(nbytes), dtype=torch.uint8, device=w.device)
+    loss = torch.empty(B, dtype=torch.float64, device=w.device)
+    g = torch.empty_like(w) if grad else None
+    _check(lib().fcgno_energy_loss(N, B, _dev_f64(k, "k"), _dev_f64(w, "w"), _dev_f64(e, "e"),
+                                   _dev_f64(loss, "loss"), _dev_f64(g, "grad") if grad else None,
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+           "fcgno_energy_loss")
+    return loss, g
+
+
+def train_step(model, opt, k, r, e, op="fp32", workspace=None, stream=None):
+    """One AdamW step on the energy-norm loss; returns the batch-mean loss."""
+    B, N = r.shape[0], r.shape[-1]
+    ws = workspace if workspace is not None else train_workspace(model, N, B, op, r.device)
+    out = c_double(0.0)
+    _check(lib().fcgno_train_step(model.handle, opt.handle, N, B, OP[op], _dev_f64(k, "k"), _dev_f64(r, "r"),
+                                  _dev_f64(e, "e"), ctypes.byref(out), ctypes.c_void_p(ws.data_ptr()),
+                                  ws.numel(), _stream(stream)), "fcgno_train_step")
+    return float(out.value)
+
+
+class OperatorFunction(torch.autograd.Function):
+    """w = B(r; theta) with the hand-written HIP backward for theta.
+
+    ``weights`` is the float64 blob; it is loaded into ``model`` when it differs
+    from the model's current weights.  No gradient flows to k or r."""
+
+    @staticmethod
+    def forward(ctx, weights, model, k, r, op="fp64"):
+        wh = weights.detach().to("cpu", torch.float64).contiguous().numpy()
+        if getattr(model, "_loaded", None) is None or not np.array_equal(model._loaded, wh):
+            model.set_weights(wh)
+            model._loaded = wh.copy()
+        w, ws = op_forward(model, k, r, op)
+        ctx.model, ctx.op, ctx.ws = model, op, ws
+        ctx.save_for_backward(k, r)
+        ctx.wdev = weights.device
+        return w
+
+    @staticmethod
+    def backward(ctx, grad_w):
+        k, r = ctx.saved_tensors
+        g = op_backward(ctx.model, k, r, grad_w, ctx.ws, ctx.op)
+        return g.to(ctx.wdev), None, None, None, None

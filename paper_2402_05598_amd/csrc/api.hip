@@ -1,5 +1,7 @@
 // C ABI of libfcgno: model lifecycle, workspace planning, the FCG solve
-// driver (Algorithm 1) and the standalone operator application.
+// driver (Algorithm 1), the standalone operator application and the training
+// entry points (forward with saved activations, hand-written backward, energy
+// loss, AdamW step).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -9,6 +11,7 @@
 #include "common.h"
 #include "fcgno.h"
 #include "prof.h"
+#include "train.h"
 
 using namespace fcgno;
 
@@ -21,33 +24,18 @@ fcgno_status fail(fcgno_status s, const std::string& msg) {
   return s;
 }
 
-#define HIPCHK(x)                                                                       \
-  do {                                                                                  \
-    hipError_t e_ = (x);                                                                \
+#define HIPCHK(x)                                                                                    \
+  do {                                                                                               \
+    hipError_t e_ = (x);                                                                             \
     if (e_ != hipSuccess) return fail(FCGNO_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
 inline int round16(int v) { return (v + 15) & ~15; }
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-uint16_t host_f2bf(float f) {
-  uint32_t b;
-  std::memcpy(&b, &f, 4);
-  if ((b & 0x7f800000u) == 0x7f800000u) return (uint16_t)((b >> 16) | ((b & 0xffffu) ? 0x40u : 0u));
-  b += 0x7fffu + ((b >> 16) & 1u);
-  return (uint16_t)(b >> 16);
-}
-
 int op_esize(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
 int acc_esize(int prec) { return prec == P64 ? 8 : 4; }
 int kstep(int prec) { return prec == PBF ? 16 : 4; }
-
-// Append value v in element type of size esz (8: f64, 4: f32, 2: bf16).
-void put(std::vector<char>& buf, size_t off, int esz, double v) {
-  if (esz == 8) std::memcpy(buf.data() + off, &v, 8);
-  else if (esz == 4) { float f = (float)v; std::memcpy(buf.data() + off, &f, 4); }
-  else { uint16_t h = host_f2bf((float)v); std::memcpy(buf.data() + off, &h, 2); }
-}
 
 struct Carver {
   size_t n = 0;
@@ -58,21 +46,48 @@ struct Carver {
   }
 };
 
+// Offsets of the parameter groups in the float64 blob.
+struct BlobLayout {
+  size_t WL, bL, WP, bP, nR;
+  std::vector<size_t> Rre, Rim, W, b;
+  BlobLayout(int C, int M, int L) : Rre(L), Rim(L), W(L), b(L) {
+    nR = (size_t)C * C * 2 * M * M;
+    size_t o = 0;
+    WL = o; o += (size_t)C * 4;
+    bL = o; o += C;
+    for (int l = 0; l < L; ++l) {
+      Rre[l] = o; o += nR;
+      Rim[l] = o; o += nR;
+      W[l] = o; o += (size_t)C * C;
+      b[l] = o; o += C;
+    }
+    WP = o; o += C;
+    bP = o;
+  }
+};
+
 }  // namespace
 
 struct fcgno_model {
   fcgno_arch arch{};
-  std::vector<double> w;       // float64 master copy (host)
-  char* dev = nullptr;         // one device allocation for every derived array
+  std::vector<double> w;       // host copy of the weights (refreshed lazily after training)
+  bool host_stale = false;
+  double* blob = nullptr;      // device float64 master weights, blob order
+  char* dev = nullptr;         // derived device arrays of every precision
   size_t dev_bytes = 0;
   int device = 0;
-  // per precision (P64, P32, PBF)
   std::vector<const void*> Wfrag[3], bias[3], Rmix[3];
   const void* WP[3] = {nullptr, nullptr, nullptr};
   const void* WL0[3] = {nullptr, nullptr, nullptr};
-  const double* WL = nullptr;  // float64 [C][4]
-  const double* bL = nullptr;  // float64 [C]
-  double bP = 0.0;
+  DeriveArgs derive[3];
+};
+
+struct fcgno_optim {
+  size_t n = 0;
+  double lr = 1e-3, wd = 1e-2, b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  long long t = 0;
+  double* m = nullptr;
+  double* v = nullptr;
 };
 
 extern "C" size_t fcgno_weight_count(const fcgno_arch* a) {
@@ -81,37 +96,9 @@ extern "C" size_t fcgno_weight_count(const fcgno_arch* a) {
   return C * Cin + C + (size_t)a->layers * (2 * C * C * 2 * M * M + C * C + C) + C + 1;
 }
 
-static fcgno_status upload_weights(fcgno_model* m) {
-  const int C = m->arch.width, M = m->arch.modes, L = m->arch.layers, Cin = 4;
-  const double* w = m->w.data();
-  // unpack the blob
-  size_t o = 0;
-  const double* WL = w + o; o += (size_t)C * Cin;
-  const double* bL = w + o; o += C;
-  std::vector<const double*> Rre(L), Rim(L), W(L), b(L);
-  const size_t nR = (size_t)C * C * 2 * M * M;
-  for (int l = 0; l < L; ++l) {
-    Rre[l] = w + o; o += nR;
-    Rim[l] = w + o; o += nR;
-    W[l] = w + o; o += (size_t)C * C;
-    b[l] = w + o; o += C;
-  }
-  const double* WP = w + o; o += C;
-  const double bP = w[o];
-  m->bP = bP;
-  // composed layer-0 bypass on the features: (W_0 W_L), W_0 b_L + b_0
-  std::vector<double> W0L((size_t)C * 4), b0c(C);
-  for (int oc = 0; oc < C; ++oc) {
-    for (int f = 0; f < 4; ++f) {
-      double s = 0.0;
-      for (int c = 0; c < C; ++c) s += W[0][oc * C + c] * WL[c * Cin + f];
-      W0L[oc * 4 + f] = s;
-    }
-    double s = b[0][oc];
-    for (int c = 0; c < C; ++c) s += W[0][oc * C + c] * bL[c];
-    b0c[oc] = s;
-  }
-  // plan the device buffer
+// Lay out the derived arrays once; their contents come from the device blob.
+static fcgno_status alloc_derived(fcgno_model* m) {
+  const int C = m->arch.width, M = m->arch.modes, L = m->arch.layers;
   Carver cv;
   struct Off { std::vector<size_t> Wf, bias, R; size_t WP, WL0; } off[3];
   for (int p = 0; p < 3; ++p) {
@@ -126,67 +113,48 @@ static fcgno_status upload_weights(fcgno_model* m) {
     off[p].WP = cv.take((size_t)C * asz);
     off[p].WL0 = cv.take((size_t)C * asz);
   }
-  const size_t offWL = cv.take((size_t)C * 4 * 8), offbL = cv.take((size_t)C * 8);
-  std::vector<char> hb(cv.n, 0);
-  for (int p = 0; p < 3; ++p) {
-    const int esz = op_esize(p), asz = acc_esize(p), ks = kstep(p);
-    for (int l = 0; l < L; ++l) {
-      const int KWP = l == 0 ? ks : C;
-      for (int oc = 0; oc < C; ++oc) {
-        for (int kw = 0; kw < KWP; ++kw) {
-          double v = 0.0;
-          if (l == 0) {
-            v = kw < 4 ? W0L[oc * 4 + kw] : 0.0;
-          } else {
-            // input K index kw = ks*KSTEP + g*KPL + e carries channel g*(C/4) + ks*KPL + e
-            const int kpl = ks / 4, kss = kw / ks, rem = kw % ks, g = rem / kpl, e = rem % kpl;
-            v = W[l][oc * C + g * (C / 4) + kss * kpl + e];
-          }
-          put(hb, off[p].Wf[l] + ((size_t)oc * KWP + kw) * esz, esz, v);
-        }
-        put(hb, off[p].bias[l] + (size_t)oc * asz, asz, l == 0 ? b0c[oc] : b[l][oc]);
-      }
-      // Rmix[ky][a][c][o] (re, im) from R[c][o][a][ky]
-      for (int ky = 0; ky < M; ++ky)
-        for (int a = 0; a < 2 * M; ++a)
-          for (int c = 0; c < C; ++c)
-            for (int oc = 0; oc < C; ++oc) {
-              const size_t src = (((size_t)c * C + oc) * 2 * M + a) * M + ky;
-              const size_t dst = ((((size_t)ky * 2 * M + a) * C + c) * C + oc) * 2;
-              put(hb, off[p].R[l] + dst * asz, asz, Rre[l][src]);
-              put(hb, off[p].R[l] + (dst + 1) * asz, asz, Rim[l][src]);
-            }
-    }
-    for (int oc = 0; oc < C; ++oc) {
-      put(hb, off[p].WP + (size_t)oc * asz, asz, WP[oc]);
-      put(hb, off[p].WL0 + (size_t)oc * asz, asz, WL[oc * Cin + 0]);
-    }
-  }
-  std::memcpy(hb.data() + offWL, WL, (size_t)C * 4 * 8);
-  std::memcpy(hb.data() + offbL, bL, (size_t)C * 8);
-  if (m->dev && m->dev_bytes != cv.n) {
-    HIPCHK(hipFree(m->dev));
-    m->dev = nullptr;
-  }
-  if (!m->dev) {
-    HIPCHK(hipMalloc((void**)&m->dev, cv.n));
-    m->dev_bytes = cv.n;
-  }
-  HIPCHK(hipMemcpy(m->dev, hb.data(), cv.n, hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc((void**)&m->dev, cv.n));
+  m->dev_bytes = cv.n;
+  HIPCHK(hipMalloc((void**)&m->blob, m->w.size() * sizeof(double)));
   for (int p = 0; p < 3; ++p) {
     m->Wfrag[p].resize(L); m->bias[p].resize(L); m->Rmix[p].resize(L);
+    DeriveArgs& d = m->derive[p];
+    std::memset(&d, 0, sizeof(d));
+    d.blob = m->blob;
+    d.C = C; d.M = M; d.L = L; d.kpl = kstep(p) / 4;
     for (int l = 0; l < L; ++l) {
-      m->Wfrag[p][l] = m->dev + off[p].Wf[l];
-      m->bias[p][l] = m->dev + off[p].bias[l];
-      m->Rmix[p][l] = m->dev + off[p].R[l];
+      d.Wfrag[l] = m->dev + off[p].Wf[l];
+      d.bias[l] = m->dev + off[p].bias[l];
+      d.Rmix[l] = m->dev + off[p].R[l];
+      m->Wfrag[p][l] = d.Wfrag[l];
+      m->bias[p][l] = d.bias[l];
+      m->Rmix[p][l] = d.Rmix[l];
     }
-    m->WP[p] = m->dev + off[p].WP;
-    m->WL0[p] = m->dev + off[p].WL0;
+    d.WP = m->dev + off[p].WP;
+    d.WL0 = m->dev + off[p].WL0;
+    m->WP[p] = d.WP;
+    m->WL0[p] = d.WL0;
   }
-  m->WL = (const double*)(m->dev + offWL);
-  m->bL = (const double*)(m->dev + offbL);
   return FCGNO_OK;
 }
+
+// Derived arrays of every precision from the device blob (stream-ordered).
+static void derive_all(fcgno_model* m, hipStream_t s) {
+  for (int p = 0; p < 3; ++p) launch_derive(m->derive[p], p, s);
+}
+
+static fcgno_status upload_weights(fcgno_model* m) {
+  HIPCHK(hipMemcpy(m->blob, m->w.data(), m->w.size() * sizeof(double), hipMemcpyHostToDevice));
+  derive_all(m, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipDeviceSynchronize());
+  m->host_stale = false;
+  return FCGNO_OK;
+}
+
+static const double* dev_WL(const fcgno_model* m) { return m->blob; }
+static const double* dev_bL(const fcgno_model* m) { return m->blob + (size_t)m->arch.width * 4; }
+static const double* dev_bP(const fcgno_model* m) { return m->blob + m->w.size() - 1; }
 
 extern "C" fcgno_status fcgno_model_create(const fcgno_arch* arch, const double* weights_host,
                                            size_t n_weights, fcgno_model** out) {
@@ -201,13 +169,13 @@ extern "C" fcgno_status fcgno_model_create(const fcgno_arch* arch, const double*
   fcgno_model* m = new fcgno_model();
   m->arch = *arch;
   m->w.assign(weights_host, weights_host + n_weights);
-  if (hipGetDevice(&m->device) != hipSuccess) {
-    delete m;
-    return fail(FCGNO_E_HIP, "hipGetDevice failed");
-  }
-  fcgno_status s = upload_weights(m);
+  fcgno_status s = FCGNO_OK;
+  if (hipGetDevice(&m->device) != hipSuccess) s = fail(FCGNO_E_HIP, "hipGetDevice failed");
+  if (s == FCGNO_OK) s = alloc_derived(m);
+  if (s == FCGNO_OK) s = upload_weights(m);
   if (s != FCGNO_OK) {
     if (m->dev) (void)hipFree(m->dev);
+    if (m->blob) (void)hipFree(m->blob);
     delete m;
     return s;
   }
@@ -215,9 +183,20 @@ extern "C" fcgno_status fcgno_model_create(const fcgno_arch* arch, const double*
   return FCGNO_OK;
 }
 
+static fcgno_status sync_host(const fcgno_model* mc) {
+  fcgno_model* m = const_cast<fcgno_model*>(mc);
+  if (!m->host_stale) return FCGNO_OK;
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(m->w.data(), m->blob, m->w.size() * sizeof(double), hipMemcpyDeviceToHost));
+  m->host_stale = false;
+  return FCGNO_OK;
+}
+
 extern "C" fcgno_status fcgno_model_get_weights(const fcgno_model* m, double* wh, size_t n) {
   if (!m || !wh) return fail(FCGNO_E_INVALID, "null argument");
   if (n != m->w.size()) return fail(FCGNO_E_INVALID, "weight count mismatch");
+  fcgno_status s = sync_host(m);
+  if (s != FCGNO_OK) return s;
   std::memcpy(wh, m->w.data(), n * sizeof(double));
   return FCGNO_OK;
 }
@@ -234,24 +213,29 @@ extern "C" fcgno_status fcgno_model_set_weights(fcgno_model* m, const double* wh
 extern "C" void fcgno_model_destroy(fcgno_model* m) {
   if (!m) return;
   if (m->dev) (void)hipFree(m->dev);
+  if (m->blob) (void)hipFree(m->blob);
   delete m;
 }
 
 // ---------------------------------------------------------------------------
-// Workspace plan
+// Workspace plans
 // ---------------------------------------------------------------------------
 namespace {
 
+constexpr int KIND_SOLVE = 0, KIND_APPLY = 1, KIND_TRAIN = 2;
+
 struct Plan {
   size_t total = 0;
-  size_t sysdev, state, counter, hist, part;
-  size_t r, w, P, S;
-  size_t act, logk, Gr, Gp, Hc, Vc, Wh, Vp;
-  size_t vp_bytes_per_sys;
-  size_t E64, Eacc, T, TT;
-  size_t n_part_blocks;
-  size_t gp_bytes_per_sys;
-  int S_seg, MP;
+  size_t sysdev = 0, state = 0, counter = 0, hist = 0, part = 0;
+  size_t r = 0, w = 0, P = 0, S = 0;
+  size_t act = 0, logk = 0, Gr = 0, Gp = 0, Hc = 0, Vc = 0, Wh = 0, Vp = 0;
+  size_t E64 = 0, Eacc = 0, T = 0, TT = 0;
+  size_t n_part_blocks = 0, gp_bytes_per_sys = 0, vp_bytes_per_sys = 0, wh_bytes_per_sys = 0;
+  int S_seg = 1, MP = 16, act_slots = 1;
+  // training
+  size_t z = 0, vsave = 0, tw = 0, gw = 0, dvec = 0, dzA = 0, dzB = 0, Gh = 0, gscale = 0, loss = 0, lpart = 0;
+  size_t pdW = 0, pdb = 0, pdWP = 0, pdbP = 0, pdWL = 0, pdbL = 0, grad = 0;
+  int Sb = 1, nbs = 1, nblk = 1, loss_nb = 1;
 };
 
 size_t part_blocks(int N) {
@@ -260,9 +244,21 @@ size_t part_blocks(int N) {
   return std::max(flat, tile);
 }
 
-// kind 0: solve, 1: operator application
+// backward row-kernel geometry for N points per row
+void bwd_geometry(int N, int prec, int& Sb, int& nbs) {
+  const int PB = prec == P64 ? PtsPerBlock<double>::value : PtsPerBlock<float>::value;
+  if (N <= PB) {
+    const int RB = PB / N;
+    Sb = 1;
+    nbs = (N + RB - 1) / RB;
+  } else {
+    Sb = (N + PB - 1) / PB;
+    nbs = N * Sb;
+  }
+}
+
 Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int op, int kind) {
-  Plan p{};
+  Plan p;
   Carver cv;
   const size_t n = (size_t)N * N;
   p.n_part_blocks = part_blocks(N);
@@ -270,7 +266,7 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
   p.state = cv.take((size_t)B * sizeof(SysState));
   p.counter = cv.take(sizeof(int));
   p.part = cv.take((size_t)B * p.n_part_blocks * NQ * sizeof(double));
-  if (kind == 0) {
+  if (kind == KIND_SOLVE) {
     p.hist = cv.take((size_t)B * (max_iter + 1) * sizeof(double));
     p.r = cv.take((size_t)B * n * 8);
     p.P = cv.take((size_t)B * (m_max + 1) * n * 8);
@@ -278,21 +274,27 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
     p.w = op != PID ? cv.take((size_t)B * n * 8) : 0;
   }
   if (op != PID && m) {
-    const int C = m->arch.width, M = m->arch.modes;
+    const int C = m->arch.width, M = m->arch.modes, L = m->arch.layers;
     const int MP = round16(2 * M), NP = round16(N);
     const int nyt = NP / 16;
     const int S = (nyt + TPW - 1) / TPW;
     const int esz = op_esize(op), asz = acc_esize(op);
+    if (kind == KIND_TRAIN) {
+      bwd_geometry(N, op, p.Sb, p.nbs);
+      p.nblk = B * p.nbs;
+    }
     p.S_seg = S;
     p.MP = MP;
-    p.act = cv.take((size_t)B * n * C * esz);
+    p.act_slots = kind == KIND_TRAIN ? std::max(1, L - 1) : 1;
+    p.act = cv.take((size_t)p.act_slots * B * n * C * esz);
     p.logk = cv.take((size_t)B * n * esz);
     p.Gr = cv.take((size_t)B * N * MP * 8);
-    p.gp_bytes_per_sys = std::max((size_t)N * S * MP * C * asz, (size_t)4 * N * MP * 8);
+    p.gp_bytes_per_sys = std::max((size_t)N * std::max(S, p.Sb) * MP * C * asz, (size_t)4 * N * MP * 8);
     p.Gp = cv.take((size_t)B * p.gp_bytes_per_sys);
     p.Hc = cv.take((size_t)B * N * C * MP * esz);
     p.Vc = cv.take((size_t)B * C * 2 * M * M * 2 * asz);
-    p.Wh = cv.take((size_t)B * C * MP * M * 2 * asz);
+    p.wh_bytes_per_sys = (size_t)C * MP * M * 2 * asz;
+    p.Wh = cv.take((size_t)B * p.wh_bytes_per_sys);
     const int XS = (N + 63) / 64;
     p.vp_bytes_per_sys = (size_t)M * XS * C * 2 * M * 2 * asz;
     p.Vp = cv.take((size_t)B * p.vp_bytes_per_sys);
@@ -300,6 +302,28 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
     p.Eacc = cv.take((size_t)N * 2 * asz);
     p.T = cv.take((size_t)NP * MP * esz);
     p.TT = cv.take((size_t)MP * NP * esz);
+    if (kind == KIND_TRAIN) {
+      const size_t vs = (size_t)M * C * 2 * M * 2;
+      p.z = cv.take((size_t)L * B * n * C * esz);
+      p.vsave = cv.take((size_t)L * B * vs * asz);
+      p.tw = cv.take((size_t)B * n * 8);
+      p.gw = cv.take((size_t)B * n * 8);
+      p.dvec = cv.take((size_t)B * n * 8);
+      p.dzA = cv.take((size_t)B * n * C * asz);
+      p.dzB = cv.take((size_t)B * n * C * asz);
+      p.Gh = cv.take((size_t)B * vs * asz);
+      p.gscale = cv.take((size_t)B * 8);
+      p.loss = cv.take((size_t)B * 8);
+      p.loss_nb = (int)((n + FLAT_PTS - 1) / FLAT_PTS);
+      p.lpart = cv.take((size_t)B * p.loss_nb * 2 * 8);
+      p.pdW = cv.take((size_t)p.nblk * C * C * asz);
+      p.pdb = cv.take((size_t)p.nblk * C * asz);
+      p.pdWP = cv.take((size_t)p.nblk * C * asz);
+      p.pdbP = cv.take((size_t)p.nblk * asz);
+      p.pdWL = cv.take((size_t)p.nblk * C * 4 * asz);
+      p.pdbL = cv.take((size_t)p.nblk * C * asz);
+      p.grad = cv.take(m->w.size() * 8);
+    }
   }
   p.total = cv.n;
   return p;
@@ -307,21 +331,20 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
 
 bool arch_ok_for(const fcgno_model* m, int N) { return m && 2 * m->arch.modes <= N; }
 
-// Fill the per-system operator pointers and the NOLaunch of a plan.
-void fill_no(const fcgno_model* m, const Plan& p, char* base, int N, int B, int op,
-             std::vector<SysDev>& h) {
+// Fill the per-system operator pointers of a plan.
+void fill_no(const fcgno_model* m, const Plan& p, char* base, int N, int B, int op, std::vector<SysDev>& h) {
   const int C = m->arch.width, M = m->arch.modes, MP = p.MP;
   const size_t n = (size_t)N * N;
   const int esz = op_esize(op), asz = acc_esize(op);
   for (int b = 0; b < B; ++b) {
     h[b].act = base + p.act + (size_t)b * n * C * esz;
-    h[b].act_stride = n * C;
+    h[b].act_stride = (size_t)B * n * C;   // elements between activation slots
     h[b].logk = base + p.logk + (size_t)b * n * esz;
     h[b].Gr = (double*)(base + p.Gr) + (size_t)b * N * MP;
     h[b].Gp = base + p.Gp + (size_t)b * p.gp_bytes_per_sys;
     h[b].Hc = base + p.Hc + (size_t)b * N * C * MP * esz;
     h[b].Vc = base + p.Vc + (size_t)b * C * 2 * M * M * 2 * asz;
-    h[b].Wh = base + p.Wh + (size_t)b * C * MP * M * 2 * asz;
+    h[b].Wh = base + p.Wh + (size_t)b * p.wh_bytes_per_sys;
     h[b].Vp = base + p.Vp + (size_t)b * p.vp_bytes_per_sys;
   }
 }
@@ -346,12 +369,24 @@ NOLaunch make_no(const fcgno_model* m, const Plan& p, char* base, const SysDev* 
   L.bias = m->bias[op].data();
   L.Rmix = m->Rmix[op].data();
   L.WP = m->WP[op];
-  L.bP = m->bP;
+  L.bP = dev_bP(m);
   L.WL0 = m->WL0[op];
-  L.WL = m->WL;
-  L.bL = m->bL;
+  L.WL = dev_WL(m);
+  L.bL = dev_bL(m);
   L.stream = s;
+  L.op_bytes = op_esize(op);
+  L.acc_bytes = acc_esize(op);
   return L;
+}
+
+// Operator set-up shared by every kind: tables, log k, constant layer-0 spectrum.
+fcgno_status operator_setup(const fcgno_model* m, const Plan& p, char* base, const NOLaunch& NL, int N, int B,
+                            int op, hipStream_t s) {
+  HIPCHK(hipMemsetAsync(base + p.Hc, 0, (size_t)B * N * m->arch.width * p.MP * op_esize(op), s));
+  HIPCHK(hipMemsetAsync(base + p.Wh, 0, (size_t)B * p.wh_bytes_per_sys, s));
+  launch_tables(NL, (double*)(base + p.E64), base + p.Eacc, base + p.T, base + p.TT);
+  launch_no_setup(NL, (double*)(base + p.Gp));
+  return FCGNO_OK;
 }
 
 fcgno_status check_desc(const fcgno_model* m, const fcgno_solve_desc* d) {
@@ -373,7 +408,7 @@ fcgno_status check_desc(const fcgno_model* m, const fcgno_solve_desc* d) {
 
 extern "C" size_t fcgno_solve_workspace_bytes(const fcgno_model* m, const fcgno_solve_desc* d) {
   if (check_desc(m, d) != FCGNO_OK) return 0;
-  return make_plan(m, d->n, d->batch, d->m_max, d->max_iter, d->op, 0).total;
+  return make_plan(m, d->n, d->batch, d->m_max, d->max_iter, d->op, KIND_SOLVE).total;
 }
 
 extern "C" fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc* d, const double* k,
@@ -384,7 +419,7 @@ extern "C" fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc
   if (cs != FCGNO_OK) return cs;
   if (!k || !f || !u || !iters || !sys_status || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
   const int N = d->n, B = d->batch, op = d->op;
-  const Plan p = make_plan(m, N, B, d->m_max, d->max_iter, op, 0);
+  const Plan p = make_plan(m, N, B, d->m_max, d->max_iter, op, KIND_SOLVE);
   if (ws_bytes < p.total) return fail(FCGNO_E_NOMEM, "workspace too small");
   if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");
   char* base = (char*)ws;
@@ -416,10 +451,8 @@ extern "C" fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc
   NOLaunch NL{};
   if (op != PID) {
     NL = make_no(m, p, base, sysdev, N, B, op, s);
-    HIPCHK(hipMemsetAsync(base + p.Hc, 0, (size_t)B * N * m->arch.width * p.MP * op_esize(op), s));
-    HIPCHK(hipMemsetAsync(base + p.Wh, 0, (size_t)B * m->arch.width * p.MP * m->arch.modes * 2 * acc_esize(op), s));
-    launch_tables(NL, (double*)(base + p.E64), base + p.Eacc, base + p.T, base + p.TT);
-    launch_no_setup(NL, (double*)(base + p.Gp));
+    fcgno_status os = operator_setup(m, p, base, NL, N, B, op, s);
+    if (os != FCGNO_OK) return os;
   }
   launch_residual(KL, 0);
   HIPCHK(hipGetLastError());
@@ -464,23 +497,13 @@ extern "C" fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc
   return all_ok ? FCGNO_OK : FCGNO_NOT_CONVERGED;
 }
 
-extern "C" size_t fcgno_precond_workspace_bytes(const fcgno_model* m, int32_t n, int32_t batch, int32_t op) {
-  if (!m || n < 1 || batch < 1 || op < 0 || op >= PID || !arch_ok_for(m, n)) return 0;
-  return make_plan(m, n, batch, 1, 1, op, 1).total;
-}
+// ---------------------------------------------------------------------------
+// Operator application (and the training forward, which also saves z and V^)
+// ---------------------------------------------------------------------------
+namespace {
 
-extern "C" fcgno_status fcgno_precond_apply(const fcgno_model* m, int32_t N, int32_t B, int32_t op,
-                                            const double* k, const double* r, double* w, void* ws,
-                                            size_t ws_bytes, void* stream) {
-  if (!m || !k || !r || !w || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
-  if (N < 1 || B < 1) return fail(FCGNO_E_INVALID, "n and batch must be >= 1");
-  if (op < 0 || op >= PID) return fail(FCGNO_E_INVALID, "op must be FP64, FP32 or BF16");
-  if (!arch_ok_for(m, N)) return fail(FCGNO_E_INVALID, "need 2*modes <= n");
-  const Plan p = make_plan(m, N, B, 1, 1, op, 1);
-  if (ws_bytes < p.total) return fail(FCGNO_E_NOMEM, "workspace too small");
-  if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");
-  char* base = (char*)ws;
-  hipStream_t s = (hipStream_t)stream;
+fcgno_status operator_forward(const fcgno_model* m, const Plan& p, char* base, int N, int B, int op,
+                              const double* k, const double* r, double* w, bool train, hipStream_t s) {
   const size_t n = (size_t)N * N;
   std::vector<SysDev> h(B);
   SysState* st = (SysState*)(base + p.state);
@@ -500,13 +523,291 @@ extern "C" fcgno_status fcgno_precond_apply(const fcgno_model* m, int32_t N, int
   KrylovLaunch KL{sysdev, B, N, 1, s};
   launch_init_state(KL, 1, 1.0);
   NOLaunch NL = make_no(m, p, base, sysdev, N, B, op, s);
-  HIPCHK(hipMemsetAsync(base + p.Hc, 0, (size_t)B * N * m->arch.width * p.MP * op_esize(op), s));
-  HIPCHK(hipMemsetAsync(base + p.Wh, 0, (size_t)B * m->arch.width * p.MP * m->arch.modes * 2 * acc_esize(op), s));
-  launch_tables(NL, (double*)(base + p.E64), base + p.Eacc, base + p.T, base + p.TT);
-  launch_no_setup(NL, (double*)(base + p.Gp));
+  fcgno_status os = operator_setup(m, p, base, NL, N, B, op, s);
+  if (os != FCGNO_OK) return os;
   launch_rnorm(KL);
-  launch_no_apply(NL);
+  if (train) {
+    const int C = m->arch.width, M = m->arch.modes;
+    NL.zsave = base + p.z;
+    NL.z_sys = n * C;
+    NL.z_layer = (size_t)B * n * C;
+    NL.vsave = base + p.vsave;
+    NL.vs_sys = (size_t)M * C * 2 * M * 2;
+    NL.vs_layer = (size_t)B * NL.vs_sys;
+    ProfScope ps(PK_TRAIN_FWD, s);
+    launch_no_apply(NL);
+  } else {
+    launch_no_apply(NL);
+  }
   HIPCHK(hipGetLastError());
+  return FCGNO_OK;
+}
+
+}  // namespace
+
+extern "C" size_t fcgno_precond_workspace_bytes(const fcgno_model* m, int32_t n, int32_t batch, int32_t op) {
+  if (!m || n < 1 || batch < 1 || op < 0 || op >= PID || !arch_ok_for(m, n)) return 0;
+  return make_plan(m, n, batch, 1, 1, op, KIND_APPLY).total;
+}
+
+extern "C" fcgno_status fcgno_precond_apply(const fcgno_model* m, int32_t N, int32_t B, int32_t op,
+                                            const double* k, const double* r, double* w, void* ws,
+                                            size_t ws_bytes, void* stream) {
+  if (!m || !k || !r || !w || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
+  if (N < 1 || B < 1) return fail(FCGNO_E_INVALID, "n and batch must be >= 1");
+  if (op < 0 || op >= PID) return fail(FCGNO_E_INVALID, "op must be FP64, FP32 or BF16");
+  if (!arch_ok_for(m, N)) return fail(FCGNO_E_INVALID, "need 2*modes <= n");
+  const Plan p = make_plan(m, N, B, 1, 1, op, KIND_APPLY);
+  if (ws_bytes < p.total) return fail(FCGNO_E_NOMEM, "workspace too small");
+  if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");
+  return operator_forward(m, p, (char*)ws, N, B, op, k, r, w, false, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Training
+// ---------------------------------------------------------------------------
+namespace {
+
+fcgno_status check_train(const fcgno_model* m, int N, int B, int op) {
+  if (!m) return fail(FCGNO_E_INVALID, "null model");
+  if (N < 1 || B < 1) return fail(FCGNO_E_INVALID, "n and batch must be >= 1");
+  if (op != P64 && op != P32) return fail(FCGNO_E_INVALID, "training runs in FP64 or FP32");
+  if (!arch_ok_for(m, N)) return fail(FCGNO_E_INVALID, "need 2*modes <= n");
+  return FCGNO_OK;
+}
+
+// Backward of the operator: upstream gradient gw [B][N^2] scaled per system by
+// gscale, with the forward state saved in the plan -> grad (float64 blob).
+fcgno_status operator_backward(const fcgno_model* m, const Plan& p, char* base, int N, int B, int op,
+                               const double* k, const double* r, const double* gw, const double* gscale,
+                               double* grad, hipStream_t s) {
+  const int C = m->arch.width, M = m->arch.modes, L = m->arch.layers, MP = p.MP;
+  const size_t n = (size_t)N * N;
+  const BlobLayout bl(C, M, L);
+  const SysDev* sysdev = (const SysDev*)(base + p.sysdev);
+  NOLaunch NL = make_no(m, p, base, sysdev, N, B, op, s);
+  NL.S = p.Sb;
+  const int asz = acc_esize(op);
+  BwdArgs a{};
+  a.N = N; a.M = M; a.MP = MP; a.L = L; a.nbs = p.nbs; a.S = p.Sb;
+  a.st = (const SysState*)(base + p.state);
+  a.gscale = gscale;
+  a.gw = gw;
+  a.r = r;
+  a.k = k;
+  a.z = base + p.z;
+  a.z_sys = n * C;
+  a.z_layer = (size_t)B * n * C;
+  a.act = base + p.act;
+  a.act_sys = n * C;
+  a.act_slot = (size_t)B * n * C;
+  a.Hcb = base + p.Hc;
+  a.hc_sys = (size_t)N * C * MP;
+  a.T = base + p.T;
+  a.blob = m->blob;
+  a.off_WP = bl.WP;
+  a.off_WL = bl.WL;
+  a.off_bL = bl.bL;
+  a.Gb = base + p.Gp;
+  a.gb_sys = p.gp_bytes_per_sys / asz;
+  a.pdW = base + p.pdW; a.pdb = base + p.pdb; a.pdWP = base + p.pdWP; a.pdbP = base + p.pdbP;
+  a.pdWL = base + p.pdWL; a.pdbL = base + p.pdbL;
+  void* dz[2] = {base + p.dzA, base + p.dzB};
+  int cur = 0;
+  // start: projection, then the target layer L-1
+  a.mode = 0;
+  a.l = 0;
+  a.dz_in = nullptr;
+  a.dz_out = dz[cur];
+  launch_bwd(a, op, C, p.nblk, s);
+  launch_reduce(base + p.pdWP, op, p.nblk, C, grad + bl.WP, s);
+  launch_reduce(base + p.pdbP, op, p.nblk, 1, grad + bl.bP, s);
+  launch_reduce(base + p.pdW, op, p.nblk, C * C, grad + bl.W[L - 1], s);
+  launch_reduce(base + p.pdb, op, p.nblk, C, grad + bl.b[L - 1], s);
+  const int XS = (N + 63) / 64;
+  for (int l = L - 1; l >= 0; --l) {
+    // spectral adjoint of layer l from the row partials of dz_l
+    SpecArgs sa{sysdev, N, p.Sb, M, 0, XS, NL.tab.Eacc, NL.tab.E64, m->Rmix[op][l], m->WL0[op], nullptr, 0, 1};
+    launch_spec_fwd(NL, sa);
+    BSpecArgs ba{};
+    ba.N = N; ba.M = M; ba.B = B; ba.XS = XS;
+    ba.Vp = base + p.Vp;
+    ba.vp_sys = p.vp_bytes_per_sys / asz;
+    ba.R = m->Rmix[op][l];
+    ba.Gh = base + p.Gh;
+    ba.gh_sys = (size_t)M * C * 2 * M * 2;
+    ba.Wh = base + p.Wh;
+    ba.wh_sys = p.wh_bytes_per_sys / asz;
+    ba.Vsave = base + p.vsave + (size_t)l * B * ba.gh_sys * asz;
+    ba.vs_sys = ba.gh_sys;
+    launch_bspec_mix(ba, op, C, s);
+    launch_dR(ba, op, C, grad + bl.Rre[l], grad + bl.Rim[l], s);
+    launch_spec_inv(NL, sa);
+    // dv_l, then the next target layer (or the lift)
+    a.mode = 1;
+    a.l = l;
+    a.off_W = bl.W[l];
+    a.dz_in = dz[cur];
+    a.dz_out = dz[1 - cur];
+    launch_bwd(a, op, C, p.nblk, s);
+    if (l >= 1) {
+      launch_reduce(base + p.pdW, op, p.nblk, C * C, grad + bl.W[l - 1], s);
+      launch_reduce(base + p.pdb, op, p.nblk, C, grad + bl.b[l - 1], s);
+    } else {
+      launch_reduce(base + p.pdWL, op, p.nblk, C * 4, grad + bl.WL, s);
+      launch_reduce(base + p.pdbL, op, p.nblk, C, grad + bl.bL, s);
+    }
+    cur = 1 - cur;
+  }
+  HIPCHK(hipGetLastError());
+  return FCGNO_OK;
+}
+
+}  // namespace
+
+extern "C" fcgno_status fcgno_optim_create(const fcgno_model* m, double lr, double weight_decay, double beta1,
+                                           double beta2, double eps, fcgno_optim** out) {
+  if (!m || !out) return fail(FCGNO_E_INVALID, "null argument");
+  if (!(lr > 0.0) || !(weight_decay >= 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+      !(eps > 0.0))
+    return fail(FCGNO_E_INVALID, "invalid optimiser hyper-parameters");
+  fcgno_optim* o = new fcgno_optim();
+  o->n = m->w.size();
+  o->lr = lr; o->wd = weight_decay; o->b1 = beta1; o->b2 = beta2; o->eps = eps;
+  if (hipMalloc((void**)&o->m, o->n * 8) != hipSuccess || hipMalloc((void**)&o->v, o->n * 8) != hipSuccess ||
+      hipMemset(o->m, 0, o->n * 8) != hipSuccess || hipMemset(o->v, 0, o->n * 8) != hipSuccess) {
+    if (o->m) (void)hipFree(o->m);
+    if (o->v) (void)hipFree(o->v);
+    delete o;
+    return fail(FCGNO_E_HIP, "optimiser state allocation failed");
+  }
+  *out = o;
+  return FCGNO_OK;
+}
+
+extern "C" fcgno_status fcgno_optim_set_lr(fcgno_optim* o, double lr) {
+  if (!o || !(lr > 0.0)) return fail(FCGNO_E_INVALID, "invalid learning rate");
+  o->lr = lr;
+  return FCGNO_OK;
+}
+
+extern "C" void fcgno_optim_destroy(fcgno_optim* o) {
+  if (!o) return;
+  if (o->m) (void)hipFree(o->m);
+  if (o->v) (void)hipFree(o->v);
+  delete o;
+}
+
+extern "C" size_t fcgno_train_workspace_bytes(const fcgno_model* m, int32_t n, int32_t batch, int32_t op) {
+  if (check_train(m, n, batch, op) != FCGNO_OK) return 0;
+  return make_plan(m, n, batch, 1, 1, op, KIND_TRAIN).total;
+}
+
+extern "C" fcgno_status fcgno_op_forward(const fcgno_model* m, int32_t N, int32_t B, int32_t op, const double* k,
+                                         const double* r, double* w, void* ws, size_t ws_bytes, void* stream) {
+  fcgno_status cs = check_train(m, N, B, op);
+  if (cs != FCGNO_OK) return cs;
+  if (!k || !r || !w || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
+  const Plan p = make_plan(m, N, B, 1, 1, op, KIND_TRAIN);
+  if (ws_bytes < p.total) return fail(FCGNO_E_NOMEM, "workspace too small");
+  if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");
+  return operator_forward(m, p, (char*)ws, N, B, op, k, r, w, true, (hipStream_t)stream);
+}
+
+extern "C" fcgno_status fcgno_op_backward(const fcgno_model* m, int32_t N, int32_t B, int32_t op,
+                                          const double* k, const double* r, const double* grad_w,
+                                          double* grad_params, void* ws, size_t ws_bytes, void* stream) {
+  fcgno_status cs = check_train(m, N, B, op);
+  if (cs != FCGNO_OK) return cs;
+  if (!k || !r || !grad_w || !grad_params || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
+  const Plan p = make_plan(m, N, B, 1, 1, op, KIND_TRAIN);
+  if (ws_bytes < p.total) return fail(FCGNO_E_NOMEM, "workspace too small");
+  if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");
+  char* base = (char*)ws;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<double> ones(B, 1.0);
+  HIPCHK(hipMemcpyAsync(base + p.gscale, ones.data(), B * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return operator_backward(m, p, base, N, B, op, k, r, grad_w, (const double*)(base + p.gscale), grad_params, s);
+}
+
+namespace {
+struct LossPlan {
+  size_t total, dvec, gw, part, gscale;
+  int nb;
+};
+LossPlan loss_plan(int N, int B) {
+  LossPlan lp{};
+  const size_t n = (size_t)N * N;
+  lp.nb = (int)((n + FLAT_PTS - 1) / FLAT_PTS);
+  Carver cv;
+  lp.dvec = cv.take(B * n * 8);
+  lp.gw = cv.take(B * n * 8);
+  lp.part = cv.take((size_t)B * lp.nb * 16);
+  lp.gscale = cv.take(B * 8);
+  lp.total = cv.n;
+  return lp;
+}
+}  // namespace
+
+extern "C" size_t fcgno_energy_loss_workspace_bytes(int32_t N, int32_t B) {
+  if (N < 1 || B < 1) return 0;
+  return loss_plan(N, B).total;
+}
+
+extern "C" fcgno_status fcgno_energy_loss(int32_t N, int32_t B, const double* k, const double* w, const double* e,
+                                          double* loss_dev, double* grad_w, void* ws, size_t ws_bytes,
+                                          void* stream) {
+  if (N < 1 || B < 1 || !k || !w || !e || !loss_dev || !ws) return fail(FCGNO_E_INVALID, "invalid argument");
+  const LossPlan lp = loss_plan(N, B);
+  if (ws_bytes < lp.total) return fail(FCGNO_E_NOMEM, "workspace too small");
+  if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");
+  char* base = (char*)ws;
+  hipStream_t s = (hipStream_t)stream;
+  double* gwbuf = grad_w ? grad_w : (double*)(base + lp.gw);
+  LossArgs la{N, B, lp.nb, k, w, e, (double*)(base + lp.dvec), gwbuf, (double*)(base + lp.part), loss_dev,
+              (double*)(base + lp.gscale)};
+  launch_loss(la, s);
+  if (grad_w) launch_scale_rows(grad_w, (const double*)(base + lp.gscale), B, (size_t)N * N, s);
+  HIPCHK(hipGetLastError());
+  return FCGNO_OK;
+}
+
+extern "C" fcgno_status fcgno_train_step(fcgno_model* m, fcgno_optim* opt, int32_t N, int32_t B, int32_t op,
+                                         const double* k, const double* r, const double* e, double* loss_host,
+                                         void* ws, size_t ws_bytes, void* stream) {
+  fcgno_status cs = check_train(m, N, B, op);
+  if (cs != FCGNO_OK) return cs;
+  if (!opt || !k || !r || !e || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
+  if (opt->n != m->w.size()) return fail(FCGNO_E_INVALID, "optimiser belongs to another architecture");
+  const Plan p = make_plan(m, N, B, 1, 1, op, KIND_TRAIN);
+  if (ws_bytes < p.total) return fail(FCGNO_E_NOMEM, "workspace too small");
+  if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");
+  char* base = (char*)ws;
+  hipStream_t s = (hipStream_t)stream;
+  double* w = (double*)(base + p.tw);
+  fcgno_status fs = operator_forward(m, p, base, N, B, op, k, r, w, true, s);
+  if (fs != FCGNO_OK) return fs;
+  LossArgs la{N, B, p.loss_nb, k, w, e, (double*)(base + p.dvec), (double*)(base + p.gw),
+              (double*)(base + p.lpart), (double*)(base + p.loss), (double*)(base + p.gscale)};
+  launch_loss(la, s);
+  double* grad = (double*)(base + p.grad);
+  fs = operator_backward(m, p, base, N, B, op, k, r, (const double*)(base + p.gw),
+                         (const double*)(base + p.gscale), grad, s);
+  if (fs != FCGNO_OK) return fs;
+  opt->t += 1;
+  launch_adamw(m->blob, grad, opt->m, opt->v, opt->n, opt->lr, opt->wd, opt->b1, opt->b2, opt->eps, opt->t, s);
+  derive_all(m, s);
+  m->host_stale = true;
+  HIPCHK(hipGetLastError());
+  if (loss_host) {
+    std::vector<double> lb(B);
+    HIPCHK(hipMemcpyAsync(lb.data(), base + p.loss, B * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double sum = 0.0;
+    for (int b = 0; b < B; ++b) sum += lb[b];
+    *loss_host = sum / B;
+  }
   return FCGNO_OK;
 }
 

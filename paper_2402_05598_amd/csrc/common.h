@@ -170,14 +170,35 @@ struct NOLaunch {
   const void* const* bias;    // [L] accumulate precision [C]
   const void* const* Rmix;    // [L] accumulate precision [M][2M][C][C] complex
   const void* WP;             // accumulate precision [C]
-  double bP;
+  const double* bP;           // float64 projection bias (device)
   const void* WL0;            // accumulate precision [C]: lift weights of the r/s feature
   const double* WL;           // float64 [C][4]
   const double* bL;           // float64 [C]
   hipStream_t stream;
+  // training forward (all nullable / zero in inference)
+  void* zsave;                // pre-activations, [L][sys][N^2][C] op precision
+  size_t z_sys, z_layer;      // element strides
+  void* vsave;                // spectra V^, [L][sys][M][C][2M] complex accumulate precision
+  size_t vs_sys, vs_layer;    // element strides
+  int op_bytes, acc_bytes;
+};
+
+struct SpecArgs {
+  const SysDev* sys;
+  int N, S, M, layer0, XS;   // XS: x-chunks of 64 rows in the forward transform
+  const void* Eacc;
+  const double* E64;
+  const void* R;     // [M][2M][C][C] complex, accumulate precision
+  const void* WL0;   // [C] accumulate precision
+  void* Vsave;       // training: V^ of this layer, [sys][M][C][2M] complex (nullable)
+  size_t vs_sys;     // elements per system in Vsave
+  int unit_scale;    // synthesis without the N^-2 g_ky factor (backward pass)
 };
 
 void launch_tables(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT);
+// single stages of the spectral part (used by the backward pass)
+void launch_spec_fwd(const NOLaunch& L, const SpecArgs& a);
+void launch_spec_inv(const NOLaunch& L, const SpecArgs& a);
 void launch_no_setup(const NOLaunch& L, double* scratch);   // logk, Vc
 void launch_no_apply(const NOLaunch& L);                    // w = B(r) for active systems
 

@@ -245,15 +245,6 @@ __global__ __launch_bounds__(256) void k_vconst(const SysDev* sys, int N, int M,
 //     complete rows Hc[x][o][.] = (N^-2 g_ky Re H, -N^-2 g_ky Im H), g_0 = 1,
 //     g_ky = 2 otherwise.
 // ---------------------------------------------------------------------------
-struct SpecArgs {
-  const SysDev* sys;
-  int N, S, M, layer0, XS;   // XS: x-chunks of SX rows in the forward transform
-  const void* Eacc;
-  const double* E64;
-  const void* R;     // [M][2M][C][C] complex, accumulate precision
-  const void* WL0;   // [C] accumulate precision
-};
-
 constexpr int SX = 64;   // rows per chunk in the forward transform
 
 // Partial forward x-DFT over one chunk of SX rows for one ky:
@@ -379,6 +370,14 @@ __global__ __launch_bounds__(256) void k_spec_mix(SpecArgs a) {
     }
   }
   __syncthreads();
+  if (a.Vsave) {
+    acc_t* vs = (acc_t*)a.Vsave + a.vs_sys * blockIdx.y + (size_t)ky * C * twoM * 2;
+    for (int q = t; q < C * twoM; q += 256) {
+      const int c = q / twoM, kx = q - c * twoM;
+      vs[2 * q] = Vr[c][kx];
+      vs[2 * q + 1] = Vi[c][kx];
+    }
+  }
   const int MP = round16(twoM);
   const acc_t* R = (const acc_t*)a.R + (size_t)ky * twoM * C * C * 2;
   acc_t* Wh = (acc_t*)sd.Wh + (size_t)ky * C * MP * 2;
@@ -437,7 +436,7 @@ __global__ __launch_bounds__(256) void k_spec_inv(SpecArgs a) {
       wr[kx] = Wh[2 * kx];
       wi[kx] = Wh[2 * kx + 1];
     }
-    const acc_t sc = (acc_t)((ky == 0 ? 1.0 : 2.0) * scale);
+    const acc_t sc = a.unit_scale ? (acc_t)1 : (acc_t)((ky == 0 ? 1.0 : 2.0) * scale);
     for (int xl = 0; xl < nx; ++xl) {
       acc_t hr = 0, hi = 0;
 #pragma unroll
@@ -469,7 +468,9 @@ struct LayerArgs {
   const void* Wf;   // [C][KWP] op precision
   const void* bias; // [C] accumulate precision
   const void* WP;   // [C] accumulate precision
-  double bP;
+  const double* bP; // float64 projection bias (device)
+  void* zout;       // training: pre-activation z of this layer, [sys][N^2][C] op precision (nullable)
+  size_t z_sys;     // elements per system in zout
 };
 
 template <int PREC, int C, int MP, bool FEAT, bool PROJ>
@@ -531,6 +532,7 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
   in_t* act_out = (in_t*)sd.act + (size_t)a.slot_out * sd.act_stride + (size_t)x * N * C;
   const double inv_s = snorm > 0.0 ? 1.0 / snorm : 0.0;
   const double h = 1.0 / (double)(N + 1);
+  const double bP = PROJ ? *a.bP : 0.0;
 
   // Operands of one 16-point tile: A fragments (twiddles and inputs); for the
   // feature layer the raw features.  Loaded one tile ahead of their use.
@@ -601,6 +603,25 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
       for (int ks = 0; ks < KIN; ++ks) acc[ob] = M_::mma(Af[KT + ks], Bf[KT + ks][ob], acc[ob]);
     }
     // lane holds z[y0 + row(g, i)][ob*16 + n16]
+    constexpr int CPR = C * (int)sizeof(in_t) / 16;   // 16-byte chunks per point
+    if (a.zout) {
+      // training: keep the pre-activation (same LDS transpose as the activations)
+      in_t* ot = otile[threadIdx.x >> 6];
+#pragma unroll
+      for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ot[M_::row(g, i) * (C + PADE) + ob * 16 + n16] = M_::cvt(acc[ob][i]);
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      in_t* zo = (in_t*)a.zout + a.z_sys * blockIdx.y + (size_t)x * N * C;
+      for (int q = lane; q < 16 * CPR; q += 64) {
+        const int pt = q / CPR, ch = q - pt * CPR;
+        if (y0 + pt < N) {
+          const uint4 val = *(const uint4*)((const char*)ot + pt * (C + PADE) * sizeof(in_t) + ch * 16);
+          *(uint4*)((char*)zo + ((size_t)(y0 + pt) * C) * sizeof(in_t) + ch * 16) = val;
+        }
+      }
+      asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    }
     if constexpr (PROJ) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -612,7 +633,7 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
         part += __shfl_xor(part, 2, 64);
         part += __shfl_xor(part, 4, 64);
         part += __shfl_xor(part, 8, 64);
-        if (n16 == i && yv < N) sd.w[(size_t)x * N + yv] = snorm * ((double)part + a.bP);
+        if (n16 == i && yv < N) sd.w[(size_t)x * N + yv] = snorm * ((double)part + bP);
       }
     } else {
       // v' = GELU(z) rounded once to the op precision; rows past N are zero
@@ -632,7 +653,6 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) ot[M_::row(g, i) * (C + PADE) + ob * 16 + n16] = hv[ob][i];
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-      constexpr int CPR = C * (int)sizeof(in_t) / 16;   // 16-byte chunks per point
       for (int q = lane; q < 16 * CPR; q += 64) {
         const int pt = q / CPR, ch = q - pt * CPR;
         if (y0 + pt < N) {
@@ -723,6 +743,30 @@ static void layer_dispatch(const NOLaunch& L, const LayerArgs& la, bool feat, bo
 }
 
 template <int PREC, int C>
+static void spec_fwd_pc(const NOLaunch& L, const SpecArgs& sa) {
+  hipLaunchKernelGGL((k_spec_fwd<PREC, C>), dim3(L.M, sa.XS, L.nsys), dim3(256), 0, L.stream, sa);
+}
+template <int PREC, int C>
+static void spec_inv_pc(const NOLaunch& L, const SpecArgs& sa) {
+  constexpr int SR = SynthRows<PREC>::SR;
+  if (L.MP == 16)
+    hipLaunchKernelGGL((k_spec_inv<PREC, C, 16>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(256), 0, L.stream, sa);
+  else
+    hipLaunchKernelGGL((k_spec_inv<PREC, C, 32>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(256), 0, L.stream, sa);
+}
+
+void launch_spec_fwd(const NOLaunch& L, const SpecArgs& a) {
+  if (L.prec == P64) { if (L.C == 16) spec_fwd_pc<P64, 16>(L, a); else spec_fwd_pc<P64, 32>(L, a); }
+  else if (L.prec == P32) { if (L.C == 16) spec_fwd_pc<P32, 16>(L, a); else spec_fwd_pc<P32, 32>(L, a); }
+  else { if (L.C == 16) spec_fwd_pc<PBF, 16>(L, a); else spec_fwd_pc<PBF, 32>(L, a); }
+}
+void launch_spec_inv(const NOLaunch& L, const SpecArgs& a) {
+  if (L.prec == P64) { if (L.C == 16) spec_inv_pc<P64, 16>(L, a); else spec_inv_pc<P64, 32>(L, a); }
+  else if (L.prec == P32) { if (L.C == 16) spec_inv_pc<P32, 16>(L, a); else spec_inv_pc<P32, 32>(L, a); }
+  else { if (L.C == 16) spec_inv_pc<PBF, 16>(L, a); else spec_inv_pc<PBF, 32>(L, a); }
+}
+
+template <int PREC, int C>
 static void apply_pc(const NOLaunch& L) {
   {
     ProfScope ps(PK_ROWDFT, L.stream);
@@ -731,7 +775,8 @@ static void apply_pc(const NOLaunch& L) {
   }
   for (int l = 0; l < L.L; ++l) {
     const int XS = (L.N + SX - 1) / SX;
-    SpecArgs sa{L.sys, L.N, L.S, L.M, l == 0 ? 1 : 0, XS, L.tab.Eacc, L.tab.E64, L.Rmix[l], L.WL0};
+    SpecArgs sa{L.sys, L.N, L.S, L.M, l == 0 ? 1 : 0, XS, L.tab.Eacc, L.tab.E64, L.Rmix[l], L.WL0,
+                L.vsave ? (char*)L.vsave + L.vs_layer * l * L.acc_bytes : nullptr, L.vs_sys, 0};
     {
       ProfScope ps(PK_SPECTRAL, L.stream);
       constexpr int SR = SynthRows<PREC>::SR;
@@ -742,7 +787,11 @@ static void apply_pc(const NOLaunch& L) {
       else
         hipLaunchKernelGGL((k_spec_inv<PREC, C, 32>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(256), 0, L.stream, sa);
     }
-    LayerArgs la{L.sys, L.N, L.S, 2 * L.M, 0, 0, L.tab.T, L.tab.TT, L.Wfrag[l], L.bias[l], L.WP, L.bP};
+    // inference updates the activation in place (slot 0); training keeps
+    // v_{l+1} in slot l so the backward pass can read every layer's input
+    const int sin = L.zsave ? (l > 0 ? l - 1 : 0) : 0, sout = L.zsave ? l : 0;
+    LayerArgs la{L.sys, L.N, L.S, 2 * L.M, sin, sout, L.tab.T, L.tab.TT, L.Wfrag[l], L.bias[l], L.WP, L.bP,
+                 L.zsave ? (char*)L.zsave + L.z_layer * l * L.op_bytes : nullptr, L.z_sys};
     const bool feat = l == 0, proj = l == L.L - 1;
     ProfScope ps(PK_LAYER, L.stream);
     if (L.MP == 16) layer_dispatch<PREC, C, 16>(L, la, feat, proj);

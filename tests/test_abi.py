@@ -20,7 +20,8 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ("fcgno_solve", "fcgno_precond_apply", "fcgno_model_create"):
+    for required in ("fcgno_solve", "fcgno_precond_apply", "fcgno_train_step", "fcgno_op_forward",
+                     "fcgno_op_backward", "fcgno_energy_loss", "fcgno_model_create"):
         assert required in names, required
 
 
