@@ -1,0 +1,310 @@
+"""FCG-NO solve throughput on one MI355X.
+
+Workload: 16 systems on a 512 x 512 interior grid (k = exp(GRF) rescaled to a
+contrast drawn log-uniformly from [10, 1e3], f ~ GRF, u0 ~ N(0, I)), solved to
+1e-6 relative residual by flexible conjugate gradients (window m = 5) with the
+neural-operator preconditioner (4 layers, width 32, 12 modes) in BF16 on the
+matrix cores with FP32 accumulation; Krylov vectors, stencil, dot products and
+the final true-residual check in FP64.  The operator is trained at set-up
+(untimed) on 64 x 64 systems with the energy-norm loss on conjugate-gradient
+Krylov samples, all on the GPU through the library.
+
+One step = one batched solve of the 16 systems.  The same solves with the FP32
+and FP64 operator are timed afterwards for comparison.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "layer_bf16_512x512x16_traffic.json")
+KERNEL_SOURCES = ("paper_2402_05598_amd/csrc/no_fwd.hip", "paper_2402_05598_amd/csrc/common.h")
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--n", type=int, default=512)
+    p.add_argument("--batch", type=int, default=16)
+    p.add_argument("--train-steps", type=int, default=16000)
+    p.add_argument("--weights", default=None, help="load trained weights (.npy) instead of training")
+    p.add_argument("--save-weights", default=None)
+    p.add_argument("--ops", default="bf16,fp32,fp64", help="first one is the reported value")
+    p.add_argument("--max-iter", type=int, default=3000)
+    p.add_argument("--rtol", type=float, default=1e-6)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=20.0)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="run one 1 GiB device copy first (HBM counter calibration under rocprofv3)")
+    p.add_argument("--log", default=None, help="progress log file (default: stderr)")
+    return p.parse_args()
+
+
+def log(msg, f=None):
+    print(msg, file=f or sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def layer_bytes_per_launch(N, B, C, M, esize, asize, S):
+    """Algorithmic HBM bytes of one inner-layer kernel launch: read the layer
+    input v_l and write v_{l+1} ([point][C], op precision), read the per-row
+    synthesis operand [N][C][MP] and write the per-row partial spectra
+    [N][S][MP][C] (accumulate precision), for B systems."""
+    MP = (2 * M + 15) // 16 * 16
+    per_point = 2 * C * esize
+    per_row = C * MP * esize + S * MP * C * asize
+    return B * (N * N * per_point + N * per_row)
+
+
+def train_operator(fc, torch, dev, C, M, L, steps, logf):
+    """Energy-norm training on conjugate-gradient Krylov samples of 64 x 64
+    systems (AdamW, lr 3e-4 halved every quarter of the run, weight decay
+    1e-2).  Returns the model and a summary."""
+    import synth
+    Nt, Bs, m_iter, mb = 64, 256, 400, 64
+    blob = synth.init_weights(3, C, M, L)
+    blob[blob.size - C - 1:] *= 1e-3   # start the projection near zero: w ~ 0 has loss 1
+    model = fc.Model(blob, C, M, L)
+    if steps <= 0:
+        return model, None
+    k, f, u0, _ = synth.batch(3, Bs, Nt, (10.0, 1000.0))
+    kd, fd, ud = [torch.from_numpy(a).to(dev) for a in (k, f, u0)]
+    t0 = time.perf_counter()
+    r, e = fc.krylov_samples(kd, fd, ud, m_iter=m_iter)
+    torch.cuda.synchronize()
+    log(f"krylov samples {tuple(r.shape)} in {time.perf_counter() - t0:.2f}s", logf)
+    lr = 3e-4
+    opt = fc.Optim(model, lr=lr, weight_decay=1e-2)
+    ws = fc.train_workspace(model, Nt, mb, "fp32", dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(1234)
+    sys_i = torch.randint(0, Bs, (steps, mb), generator=g, device=dev)
+    it_i = torch.randint(0, m_iter, (steps, mb), generator=g, device=dev)
+    t0 = time.perf_counter()
+    losses = []
+    for s in range(steps):
+        if s and s % max(1, steps // 4) == 0:
+            lr *= 0.5
+            opt.set_lr(lr)
+        si, ii = sys_i[s], it_i[s]
+        want = s % 200 == 0 or s >= steps - 50
+        loss = fc.train_step(model, opt, kd[si], r[si, ii], e[si, ii], op="fp32", workspace=ws, return_loss=want)
+        if want:
+            losses.append(loss)
+        if s % 2000 == 0:
+            log(f"train step {s}: loss {loss:.4f} ({time.perf_counter() - t0:.1f}s)", logf)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    opt.close()
+    return model, {"grid": Nt, "systems": Bs, "cg_iterations_sampled": m_iter, "batch": mb, "steps": steps,
+                   "seconds": round(dt, 2), "loss_first": round(losses[0], 4),
+                   "loss_last50": round(float(np.mean(losses[-50:])), 4)}
+
+
+def time_solves(fc, torch, model, kd, fd, u0d, op, steps, warmup, args, prof_kernels=None):
+    B = fd.shape[0]
+    N = fd.shape[-1]
+    ws = torch.empty(fc.solve_workspace_bytes(model, N, B, op, 5, args.max_iter, args.rtol),
+                     dtype=torch.uint8, device=fd.device)
+    us = [u0d.clone() for _ in range(steps + warmup)]
+    outs = []
+    for w in range(warmup):
+        fc.solve(model, kd, fd, us[w], op=op, m_max=5, max_iter=args.max_iter, rtol=args.rtol,
+                 hist=False, workspace=ws)
+    torch.cuda.synchronize()
+    if prof_kernels:
+        fc.profile_reset()
+        fc.profile_enable(True, prof_kernels)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ts = time.perf_counter()
+        outs.append(fc.solve(model, kd, fd, us[warmup + s], op=op, m_max=5, max_iter=args.max_iter,
+                             rtol=args.rtol, hist=False, workspace=ws))
+        lat.append(time.perf_counter() - ts)   # the call returns after the batch completed
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    prof = {}
+    if prof_kernels:
+        fc.profile_enable(False)
+        for name in prof_kernels:
+            prof[name] = fc.profile_read(name)
+    return total, lat, outs, us[-1], prof
+
+
+def cpu_baseline(k, f, u0, blob, C, M, L, iters_needed, seconds, logf):
+    """The oracle (FP64 FCG with the FP64 operator) on system 0 of the batch,
+    for as many iterations as fit in about ``seconds``; scaled to solves/sec
+    with the iteration count the solve needs.  The oracle's time per
+    iteration does not depend on the weight values; it runs with the seeded
+    initial weights."""
+    import torch
+    import oracle
+    w = oracle.unpack_weights(blob, C, M, L)
+    kt = torch.from_numpy(k)
+
+    def pre(r):
+        return oracle.no_apply(w, kt, r)
+    # probe one iteration, then size the sample to the time budget
+    t0 = time.perf_counter()
+    oracle.fcg(k, f, u0, pre, m_max=5, max_iter=1, tol=0.0)
+    t1 = time.perf_counter() - t0
+    n_it = int(max(2, min(iters_needed, seconds / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.fcg(k, f, u0, pre, m_max=5, max_iter=n_it, tol=0.0)
+    dt = time.perf_counter() - t0
+    per_iter = dt / n_it
+    log(f"cpu oracle: {n_it} iterations in {dt:.1f}s ({per_iter:.3f}s/iter)", logf)
+    return {"value": 1.0 / (per_iter * iters_needed), "unit": "solves/sec", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"first {n_it} FCG iterations (FP64 operator, m=5) of system 0 of the batch, "
+                      f"{per_iter:.3f} s/iteration, scaled by the {iters_needed} iterations the batch's "
+                      f"FP64-operator solves took on average"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (this build has no "
+              "multi-GPU path; the batch of independent solves would shard by system).", file=sys.stderr)
+        sys.exit(2)
+    logf = open(args.log, "a") if args.log else None
+    import torch
+    import paper_2402_05598_amd as fc
+    import synth
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    N, B, C, M, L = args.n, args.batch, 32, 12, 4
+    ops = args.ops.split(",")
+
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written", logf)
+        del a, b
+
+    if args.weights:
+        model = fc.Model(np.load(args.weights), C, M, L)
+        train_info = {"loaded": os.path.basename(args.weights)}
+    else:
+        model, train_info = train_operator(fc, torch, dev, C, M, L, args.train_steps, logf)
+        if args.save_weights:
+            np.save(args.save_weights, model.get_weights())
+    k, f, u0, contrasts = synth.batch(2, B, N, (10.0, 1000.0))
+    kd, fd, u0d = [torch.from_numpy(a).to(dev) for a in (k, f, u0)]
+    torch.cuda.synchronize()
+    log(f"workload N={N} B={B} contrasts {min(contrasts):.1f}..{max(contrasts):.1f}", logf)
+
+    results = {}
+    prof = None
+    for j, op in enumerate(ops):
+        steps = args.steps if j == 0 else max(1, min(args.steps, 2))
+        pk = ["layer", "layer_feat", "layer_proj", "spectral", "rowdft", "wdots", "dir", "update"] if j == 0 else None
+        total, lat, outs, ulast, pr = time_solves(fc, torch, model, kd, fd, u0d, op, steps,
+                                                  args.warmup if j == 0 else 0, args, pk)
+        if j == 0:
+            prof = pr
+        iters = np.concatenate([o["iters"] for o in outs])
+        status = np.concatenate([o["status"] for o in outs])
+        tres = np.concatenate([o["true_rel_res"] for o in outs])
+        results[op] = {"seconds": total, "steps": steps, "lat": lat, "iters": iters, "status": status,
+                       "tres": tres, "u": ulast}
+        log(f"op={op}: {steps} solves in {total:.3f}s, iters mean {iters.mean():.1f} max {iters.max()}, "
+            f"status {np.bincount(status, minlength=4).tolist()}, true rel res max {tres.max():.2e}", logf)
+
+    main_op = ops[0]
+    R = results[main_op]
+    ms_per_step = R["seconds"] / R["steps"] * 1e3
+    value = B * R["steps"] / R["seconds"]
+    lat_ms = np.array(R["lat"]) * 1e3
+
+    # roofline of the inner layer kernel (the operator's dominant launch)
+    esize = {"bf16": 2, "fp32": 4, "fp64": 8}[main_op]
+    asize = 8 if main_op == "fp64" else 4
+    S = ((N + 15) // 16 + 31) // 32
+    nb = layer_bytes_per_launch(N, B, C, M, esize, asize, S)
+    n_l, ms_l = prof["layer"]
+    avg_us = ms_l / max(n_l, 1) * 1e3
+    achieved = nb / (avg_us * 1e-6) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == f"{N}x{N}x{B}":
+            traffic = tr["bytes_per_launch"]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": f"k_layer<{main_op}, C={C}, MP=32> inner layer", "launches": n_l,
+                "avg_us": round(avg_us, 2), "algorithmic_bytes_per_launch": nb}
+
+    per_kernel = {name: {"launches": n_, "avg_us": round(ms_ / max(n_, 1) * 1e3, 2)}
+                  for name, (n_, ms_) in prof.items()}
+    comparison = {}
+    ref = results.get("fp64")
+    for op, Rr in results.items():
+        d = {"solves_per_sec": round(B * Rr["steps"] / Rr["seconds"], 3),
+             "ms_per_solve_batch": round(Rr["seconds"] / Rr["steps"] * 1e3, 2),
+             "iters_mean": round(float(Rr["iters"].mean()), 2), "iters_max": int(Rr["iters"].max()),
+             "converged": int((Rr["status"] == 0).sum()), "of": int(Rr["status"].size),
+             "true_rel_res_max": float(Rr["tres"].max())}
+        if ref is not None and op != "fp64":
+            du = torch.linalg.vector_norm(Rr["u"] - ref["u"], dim=(1, 2)) / torch.linalg.vector_norm(ref["u"], dim=(1, 2))
+            d["u_rel_diff_vs_fp64_op_max"] = float(du.max())
+        comparison[op] = d
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        iters_needed = int(round(float(results["fp64"]["iters"].mean()))) if "fp64" in results \
+            else int(round(float(R["iters"].mean())))
+        cpu = cpu_baseline(k[0], f[0], u0[0], synth.init_weights(3, C, M, L), C, M, L, iters_needed,
+                           args.cpu_seconds, logf)
+
+    line = {
+        "metric": "solves/sec to 1e-6 rel. residual, BF16-NO vs FP64 FCG-NO; p50/p99 latency",
+        "value": round(value, 3), "unit": "solves/sec", "n_gpus": 1, "steps": R["steps"],
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": main_op, "data": "synthetic",
+        "config": {"workload": f"FCG-NO solve, {N}x{N} grid, batch {B}, k=exp(GRF) contrast 10..1e3, "
+                               f"NO L={L} C={C} M={M} trained at set-up, op {main_op} (FP32 accumulate), "
+                               f"FP64 Krylov, m=5, tol {args.rtol:g}",
+                   "grid": N, "batch": B, "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 2),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 2),
+                       "per": "batched solve of all systems (each system's result is returned with the batch)"},
+        "comparison": comparison,
+        "kernels": per_kernel,
+        "training": train_info,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    model.close()
+
+
+if __name__ == "__main__":
+    main()

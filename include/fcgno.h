@@ -165,6 +165,19 @@ fcgno_status fcgno_optim_create(const fcgno_model* m, double lr, double weight_d
 fcgno_status fcgno_optim_set_lr(fcgno_optim* o, double lr);
 void fcgno_optim_destroy(fcgno_optim* o);
 
+/* Training data drawn from Krylov subspaces (Sec. 3.1, the distribution
+ * p_Km; Fig. 2a): u* = A^-1 f by conjugate gradients to 1e-13 relative
+ * residual (at most max_iter iterations), then conjugate gradients (FCG with
+ * B = I) from u0 for m_iter iterations, keeping after iteration i = 1..m_iter
+ * r_out[b][i-1] = r_i and e_out[b][i-1] = u* - u_i (device
+ * [batch][m_iter][N][N] each).  k, f, u0 device as for fcgno_solve.  Returns
+ * FCGNO_NOT_CONVERGED if some u* missed 1e-13 (the samples are still written);
+ * synchronises the stream. */
+size_t fcgno_krylov_samples_workspace_bytes(int32_t n, int32_t batch, int32_t max_iter);
+fcgno_status fcgno_krylov_samples(int32_t n, int32_t batch, int32_t m_iter, int32_t max_iter,
+                                  const double* k, const double* f, const double* u0,
+                                  double* r_out, double* e_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Workspace of fcgno_op_forward / fcgno_op_backward / fcgno_train_step. */
 size_t fcgno_train_workspace_bytes(const fcgno_model* m, int32_t n, int32_t batch, int32_t op);
 
@@ -199,11 +212,14 @@ fcgno_status fcgno_train_step(fcgno_model* m, fcgno_optim* opt, int32_t n, int32
 /* ------------------------------------------------------------------------ */
 /* Kernel timing: HIP event pairs recorded on the launch stream around each   */
 /* launch of a kernel family while enabled; read after the work completed.    */
-/* kernel ids: 0 operator layer kernel (matrix cores), 1 operator spectral    */
-/* kernel, 2 direction+stencil, 3 window dots, 4 update, 5 row DFT of r,      */
-/* 6 training forward, 7 training backward.                                   */
+/* fcgno_profile_enable takes a bit mask of families (bit k = id k; 0 = off). */
+/* kernel ids: 0 operator inner-layer kernel (matrix cores), 1 operator      */
+/* spectral kernels (forward DFT, mixing, synthesis), 2 direction+stencil,    */
+/* 3 window dots, 4 update, 5 row DFT of r, 6 training forward, 7 training    */
+/* backward, 8 first layer kernel (lift fused), 9 last layer kernel           */
+/* (projection fused).                                                        */
 /* ------------------------------------------------------------------------ */
-void fcgno_profile_enable(int32_t on);
+void fcgno_profile_enable(int32_t mask);
 void fcgno_profile_reset(void);
 fcgno_status fcgno_profile_read(int32_t kernel, int64_t* launches, double* total_ms);
 

@@ -82,6 +82,10 @@ def lib():
     L.fcgno_train_step.argtypes = [vp, vp, c_int32, c_int32, c_int32, vp, vp, vp, POINTER(c_double), vp,
                                    c_size_t, vp]
     L.fcgno_train_step.restype = c_int32
+    L.fcgno_krylov_samples_workspace_bytes.argtypes = [c_int32, c_int32, c_int32]
+    L.fcgno_krylov_samples_workspace_bytes.restype = c_size_t
+    L.fcgno_krylov_samples.argtypes = [c_int32, c_int32, c_int32, c_int32, vp, vp, vp, vp, vp, vp, c_size_t, vp]
+    L.fcgno_krylov_samples.restype = c_int32
     L.fcgno_profile_enable.argtypes = [c_int32]
     L.fcgno_profile_enable.restype = None
     L.fcgno_profile_reset.argtypes = []
@@ -218,11 +222,20 @@ def precond_apply(model, k, r, op="bf16", w=None, workspace=None, stream=None):
 
 
 PROFILE_KERNELS = {"layer": 0, "spectral": 1, "dir": 2, "wdots": 3, "update": 4, "rowdft": 5,
-                   "train_fwd": 6, "train_bwd": 7}
+                   "train_fwd": 6, "train_bwd": 7, "layer_feat": 8, "layer_proj": 9}
 
 
-def profile_enable(on=True):
-    lib().fcgno_profile_enable(1 if on else 0)
+def profile_enable(on=True, kernels=None):
+    """Event timing of the kernel families named in ``kernels`` (all if None)."""
+    if not on:
+        mask = 0
+    elif kernels is None:
+        mask = (1 << len(PROFILE_KERNELS)) - 1
+    else:
+        mask = 0
+        for name in kernels:
+            mask |= 1 << PROFILE_KERNELS[name]
+    lib().fcgno_profile_enable(mask)
 
 
 def profile_reset():
@@ -311,15 +324,32 @@ def energy_loss(k, w, e, grad=True, stream=None):
     return loss, g
 
 
-def train_step(model, opt, k, r, e, op="fp32", workspace=None, stream=None):
-    """One AdamW step on the energy-norm loss; returns the batch-mean loss."""
+def train_step(model, opt, k, r, e, op="fp32", workspace=None, stream=None, return_loss=True):
+    """One AdamW step on the energy-norm loss; returns the batch-mean loss
+    (which synchronises the stream), or None with ``return_loss=False``."""
     B, N = r.shape[0], r.shape[-1]
     ws = workspace if workspace is not None else train_workspace(model, N, B, op, r.device)
     out = c_double(0.0)
     _check(lib().fcgno_train_step(model.handle, opt.handle, N, B, OP[op], _dev_f64(k, "k"), _dev_f64(r, "r"),
-                                  _dev_f64(e, "e"), ctypes.byref(out), ctypes.c_void_p(ws.data_ptr()),
-                                  ws.numel(), _stream(stream)), "fcgno_train_step")
-    return float(out.value)
+                                  _dev_f64(e, "e"), ctypes.byref(out) if return_loss else None,
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "fcgno_train_step")
+    return float(out.value) if return_loss else None
+
+
+def krylov_samples(k, f, u0, m_iter=100, max_iter=None, stream=None):
+    """(r_i, e_i = u* - u_i), i = 1..m_iter, of conjugate gradients from u0;
+    returns two device tensors [B][m_iter][N][N]."""
+    B, N = f.shape[0], f.shape[-1]
+    max_iter = max_iter or max(20 * N, 2000)
+    nbytes = lib().fcgno_krylov_samples_workspace_bytes(N, B, max(max_iter, m_iter))
+    ws = torch.empty(int(nbytes), dtype=torch.uint8, device=f.device)
+    r = torch.empty((B, m_iter, N, N), dtype=torch.float64, device=f.device)
+    e = torch.empty_like(r)
+    _check(lib().fcgno_krylov_samples(N, B, m_iter, max_iter, _dev_f64(k, "k"), _dev_f64(f, "f"),
+                                      _dev_f64(u0, "u0"), _dev_f64(r, "r"), _dev_f64(e, "e"),
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+           "fcgno_krylov_samples")
+    return r, e
 
 
 class OperatorFunction(torch.autograd.Function):

@@ -234,7 +234,7 @@ struct Plan {
   int S_seg = 1, MP = 16, act_slots = 1;
   // training
   size_t z = 0, vsave = 0, tw = 0, gw = 0, dvec = 0, dzA = 0, dzB = 0, Gh = 0, gscale = 0, loss = 0, lpart = 0;
-  size_t pdW = 0, pdb = 0, pdWP = 0, pdbP = 0, pdWL = 0, pdbL = 0, grad = 0;
+  size_t pdW = 0, pdb = 0, pdWP = 0, pdbP = 0, pdWL = 0, pdbL = 0, grad = 0, rstage = 0;
   int Sb = 1, nbs = 1, nblk = 1, loss_nb = 1;
 };
 
@@ -323,6 +323,7 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
       p.pdWL = cv.take((size_t)p.nblk * C * 4 * asz);
       p.pdbL = cv.take((size_t)p.nblk * C * asz);
       p.grad = cv.take(m->w.size() * 8);
+      p.rstage = cv.take((size_t)REDUCE_CHUNKS * C * C * 8);
     }
   }
   p.total = cv.n;
@@ -411,10 +412,17 @@ extern "C" size_t fcgno_solve_workspace_bytes(const fcgno_model* m, const fcgno_
   return make_plan(m, d->n, d->batch, d->m_max, d->max_iter, d->op, KIND_SOLVE).total;
 }
 
-extern "C" fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc* d, const double* k,
-                                    const double* f, double* u, double* r_out, int32_t* iters,
-                                    int32_t* sys_status, double* rel_hist, double* true_rel_res, void* ws,
-                                    size_t ws_bytes, void* stream) {
+namespace {
+struct Record {
+  int m;
+  double* rec_r;
+  double* rec_e;
+  const double* ustar;
+};
+
+fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const double* k, const double* f,
+                        double* u, double* r_out, int32_t* iters, int32_t* sys_status, double* rel_hist,
+                        double* true_rel_res, void* ws, size_t ws_bytes, void* stream, const Record* rec) {
   fcgno_status cs = check_desc(m, d);
   if (cs != FCGNO_OK) return cs;
   if (!k || !f || !u || !iters || !sys_status || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
@@ -465,6 +473,7 @@ extern "C" fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc
       launch_wdots(KL);
       launch_dir(KL);
       launch_update(KL);
+      if (rec && it < rec->m) launch_record(KL, it, rec->m, rec->rec_r, rec->rec_e, rec->ustar);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(&nact, counter, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -495,6 +504,51 @@ extern "C" fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc
     }
   }
   return all_ok ? FCGNO_OK : FCGNO_NOT_CONVERGED;
+}
+}  // namespace
+
+extern "C" fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc* d, const double* k,
+                                    const double* f, double* u, double* r_out, int32_t* iters,
+                                    int32_t* sys_status, double* rel_hist, double* true_rel_res, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  return solve_impl(m, d, k, f, u, r_out, iters, sys_status, rel_hist, true_rel_res, ws, ws_bytes, stream,
+                    nullptr);
+}
+
+extern "C" size_t fcgno_krylov_samples_workspace_bytes(int32_t n, int32_t batch, int32_t max_iter) {
+  if (n < 1 || batch < 1 || max_iter < 1) return 0;
+  const size_t sol = make_plan(nullptr, n, batch, 1, max_iter, PID, KIND_SOLVE).total;
+  return sol + align256((size_t)batch * n * n * 8) * 2;
+}
+
+extern "C" fcgno_status fcgno_krylov_samples(int32_t N, int32_t B, int32_t m_iter, int32_t max_iter,
+                                             const double* k, const double* f, const double* u0, double* r_out,
+                                             double* e_out, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || B < 1 || m_iter < 1 || max_iter < 1 || !k || !f || !u0 || !r_out || !e_out || !ws)
+    return fail(FCGNO_E_INVALID, "invalid argument");
+  if (ws_bytes < fcgno_krylov_samples_workspace_bytes(N, B, std::max(max_iter, m_iter)))
+    return fail(FCGNO_E_NOMEM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n = (size_t)N * N;
+  char* base = (char*)ws;
+  const size_t sol = make_plan(nullptr, N, B, 1, std::max(max_iter, m_iter), PID, KIND_SOLVE).total;
+  double* ustar = (double*)(base + sol);
+  double* ucur = (double*)(base + sol + align256((size_t)B * n * 8));
+  std::vector<int32_t> it(B), st(B);
+  // u* = A^-1 f by conjugate gradients to a tight tolerance
+  HIPCHK(hipMemcpyAsync(ustar, u0, (size_t)B * n * 8, hipMemcpyDeviceToDevice, s));
+  fcgno_solve_desc d1{N, B, 1, max_iter, 1e-13, PID, 0};
+  fcgno_status r1 = solve_impl(nullptr, &d1, k, f, ustar, nullptr, it.data(), st.data(), nullptr, nullptr, ws, sol,
+                               stream, nullptr);
+  if (r1 < 0) return r1;
+  // the recorded CG run (FCG with B = I, window 1) from u0
+  HIPCHK(hipMemcpyAsync(ucur, u0, (size_t)B * n * 8, hipMemcpyDeviceToDevice, s));
+  fcgno_solve_desc d2{N, B, 1, m_iter, 1e-300, PID, m_iter};
+  Record rec{m_iter, r_out, e_out, ustar};
+  fcgno_status r2 = solve_impl(nullptr, &d2, k, f, ucur, nullptr, it.data(), st.data(), nullptr, nullptr, ws, sol,
+                               stream, &rec);
+  if (r2 < 0) return r2;
+  return r1;
 }
 
 // ---------------------------------------------------------------------------
@@ -613,6 +667,7 @@ fcgno_status operator_backward(const fcgno_model* m, const Plan& p, char* base, 
   a.pdW = base + p.pdW; a.pdb = base + p.pdb; a.pdWP = base + p.pdWP; a.pdbP = base + p.pdbP;
   a.pdWL = base + p.pdWL; a.pdbL = base + p.pdbL;
   void* dz[2] = {base + p.dzA, base + p.dzB};
+  double* rst = (double*)(base + p.rstage);
   int cur = 0;
   // start: projection, then the target layer L-1
   a.mode = 0;
@@ -620,10 +675,10 @@ fcgno_status operator_backward(const fcgno_model* m, const Plan& p, char* base, 
   a.dz_in = nullptr;
   a.dz_out = dz[cur];
   launch_bwd(a, op, C, p.nblk, s);
-  launch_reduce(base + p.pdWP, op, p.nblk, C, grad + bl.WP, s);
-  launch_reduce(base + p.pdbP, op, p.nblk, 1, grad + bl.bP, s);
-  launch_reduce(base + p.pdW, op, p.nblk, C * C, grad + bl.W[L - 1], s);
-  launch_reduce(base + p.pdb, op, p.nblk, C, grad + bl.b[L - 1], s);
+  launch_reduce(base + p.pdWP, op, p.nblk, C, grad + bl.WP, rst, s);
+  launch_reduce(base + p.pdbP, op, p.nblk, 1, grad + bl.bP, rst, s);
+  launch_reduce(base + p.pdW, op, p.nblk, C * C, grad + bl.W[L - 1], rst, s);
+  launch_reduce(base + p.pdb, op, p.nblk, C, grad + bl.b[L - 1], rst, s);
   const int XS = (N + 63) / 64;
   for (int l = L - 1; l >= 0; --l) {
     // spectral adjoint of layer l from the row partials of dz_l
@@ -651,11 +706,11 @@ fcgno_status operator_backward(const fcgno_model* m, const Plan& p, char* base, 
     a.dz_out = dz[1 - cur];
     launch_bwd(a, op, C, p.nblk, s);
     if (l >= 1) {
-      launch_reduce(base + p.pdW, op, p.nblk, C * C, grad + bl.W[l - 1], s);
-      launch_reduce(base + p.pdb, op, p.nblk, C, grad + bl.b[l - 1], s);
+      launch_reduce(base + p.pdW, op, p.nblk, C * C, grad + bl.W[l - 1], rst, s);
+      launch_reduce(base + p.pdb, op, p.nblk, C, grad + bl.b[l - 1], rst, s);
     } else {
-      launch_reduce(base + p.pdWL, op, p.nblk, C * 4, grad + bl.WL, s);
-      launch_reduce(base + p.pdbL, op, p.nblk, C, grad + bl.bL, s);
+      launch_reduce(base + p.pdWL, op, p.nblk, C * 4, grad + bl.WL, rst, s);
+      launch_reduce(base + p.pdbL, op, p.nblk, C, grad + bl.bL, rst, s);
     }
     cur = 1 - cur;
   }

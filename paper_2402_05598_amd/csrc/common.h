@@ -157,6 +157,7 @@ void launch_rnorm(const KrylovLaunch& L);                 // snorm from r (opera
 void launch_wdots(const KrylovLaunch& L);
 void launch_dir(const KrylovLaunch& L);
 void launch_update(const KrylovLaunch& L);
+void launch_record(const KrylovLaunch& L, int it, int m, double* rec_r, double* rec_e, const double* ustar);
 
 struct NOLaunch {
   const SysDev* sys;

@@ -352,7 +352,25 @@ __global__ __launch_bounds__(256) void k_fin(const SysDev* sys, int N, int mode)
   }
 }
 
+// Record r_{i+1} and u* - u_{i+1} of every system after iteration it.
+__global__ __launch_bounds__(256) void k_record(const SysDev* sys, int N, int it, int m, double* rec_r,
+                                                double* rec_e, const double* ustar) {
+  const SysDev sd = sys[blockIdx.y];
+  const size_t n = (size_t)N * N;
+  const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= n) return;
+  const size_t o = ((size_t)blockIdx.y * m + it) * n + p;
+  rec_r[o] = sd.r[p];
+  rec_e[o] = ustar[(size_t)blockIdx.y * n + p] - sd.u[p];
+}
+
 // ---- launchers ------------------------------------------------------------
+
+void launch_record(const KrylovLaunch& L, int it, int m, double* rec_r, double* rec_e, const double* ustar) {
+  const size_t n = (size_t)L.N * L.N;
+  hipLaunchKernelGGL(k_record, dim3((unsigned)((n + 255) / 256), L.nsys), dim3(256), 0, L.stream, L.sys, L.N, it, m,
+                     rec_r, rec_e, ustar);
+}
 
 static inline int flat_nb(int N) { return (N * N + FLAT_PTS - 1) / FLAT_PTS; }
 

@@ -793,7 +793,7 @@ static void apply_pc(const NOLaunch& L) {
     LayerArgs la{L.sys, L.N, L.S, 2 * L.M, sin, sout, L.tab.T, L.tab.TT, L.Wfrag[l], L.bias[l], L.WP, L.bP,
                  L.zsave ? (char*)L.zsave + L.z_layer * l * L.op_bytes : nullptr, L.z_sys};
     const bool feat = l == 0, proj = l == L.L - 1;
-    ProfScope ps(PK_LAYER, L.stream);
+    ProfScope ps(feat ? PK_LAYER_FEAT : (proj ? PK_LAYER_PROJ : PK_LAYER), L.stream);
     if (L.MP == 16) layer_dispatch<PREC, C, 16>(L, la, feat, proj);
     else layer_dispatch<PREC, C, 32>(L, la, feat, proj);
   }

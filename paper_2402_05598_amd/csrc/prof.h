@@ -4,10 +4,13 @@
 
 namespace fcgno {
 
+// PK_LAYER: inner layers; PK_LAYER_FEAT / PK_LAYER_PROJ: the first (lift fused)
+// and last (projection fused) layer kernels.
 enum ProfKernel { PK_LAYER = 0, PK_SPECTRAL = 1, PK_DIR = 2, PK_WDOTS = 3, PK_UPDATE = 4, PK_ROWDFT = 5,
-                  PK_TRAIN_FWD = 6, PK_TRAIN_BWD = 7, PK_COUNT = 8 };
+                  PK_TRAIN_FWD = 6, PK_TRAIN_BWD = 7, PK_LAYER_FEAT = 8, PK_LAYER_PROJ = 9, PK_COUNT = 10 };
 
-bool prof_on();
+bool prof_on();              // any family enabled
+bool prof_on(int kernel);    // this family enabled
 void prof_begin(int kernel, hipStream_t s);
 void prof_end(int kernel, hipStream_t s);
 // Accumulate the durations of completed event pairs (call after a stream sync).
@@ -16,8 +19,8 @@ void prof_collect();
 struct ProfScope {
   int k;
   hipStream_t s;
-  ProfScope(int kernel, hipStream_t st) : k(kernel), s(st) { if (prof_on()) prof_begin(k, s); }
-  ~ProfScope() { if (prof_on()) prof_end(k, s); }
+  ProfScope(int kernel, hipStream_t st) : k(kernel), s(st) { if (prof_on(k)) prof_begin(k, s); }
+  ~ProfScope() { if (prof_on(k)) prof_end(k, s); }
 };
 
 }  // namespace fcgno

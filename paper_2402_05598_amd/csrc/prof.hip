@@ -10,7 +10,7 @@ namespace fcgno {
 namespace {
 struct Pending { int k; hipEvent_t a, b; };
 std::mutex g_mu;
-bool g_on = false;
+unsigned g_mask = 0u;
 std::vector<hipEvent_t> g_pool;
 std::vector<Pending> g_pending;
 hipEvent_t g_open[PK_COUNT];
@@ -29,7 +29,8 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
-bool prof_on() { return g_on; }
+bool prof_on() { return g_mask != 0u; }
+bool prof_on(int k) { return (g_mask >> k) & 1u; }
 
 void prof_begin(int k, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -64,9 +65,9 @@ void prof_collect() {
 
 using namespace fcgno;
 
-extern "C" void fcgno_profile_enable(int32_t on) {
+extern "C" void fcgno_profile_enable(int32_t mask) {
   std::lock_guard<std::mutex> lk(g_mu);
-  g_on = on != 0;
+  g_mask = (unsigned)mask & ((1u << PK_COUNT) - 1u);
 }
 
 extern "C" void fcgno_profile_reset(void) {

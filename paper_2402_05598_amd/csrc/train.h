@@ -73,7 +73,9 @@ void launch_loss(const LossArgs& a, hipStream_t s);
 void launch_bwd(const BwdArgs& a, int prec, int C, int nblk, hipStream_t s);
 void launch_bspec_mix(const BSpecArgs& a, int prec, int C, hipStream_t s);
 void launch_dR(const BSpecArgs& a, int prec, int C, double* gre, double* gim, hipStream_t s);
-void launch_reduce(const void* part, int prec, int nblk, int count, double* out, hipStream_t s);
+// stage: REDUCE_CHUNKS * count doubles of scratch
+constexpr int REDUCE_CHUNKS = 64;
+void launch_reduce(const void* part, int prec, int nblk, int count, double* out, double* stage, hipStream_t s);
 void launch_adamw(double* theta, const double* g, double* m, double* v, size_t n, double lr, double wd, double b1,
                   double b2, double eps, long long t, hipStream_t s);
 void launch_derive(const DeriveArgs& a, int prec, hipStream_t s);

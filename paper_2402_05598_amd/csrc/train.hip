@@ -376,13 +376,31 @@ __global__ __launch_bounds__(256) void k_dR(BSpecArgs a, double* grad_re, double
   }
 }
 
-// Fixed-order reduction of per-block partials: out[i] = sum_blk part[blk][i].
+// Fixed-order reduction of per-block partials, out[i] = sum_blk part[blk][i],
+// in two stages: stage 1 sums chunks of consecutive blocks (64 columns per
+// workgroup, four interleaved block sequences combined in a fixed order),
+// stage 2 sums the chunk results in chunk order.
 template <typename acc_t>
-__global__ __launch_bounds__(256) void k_reduce(const acc_t* part, int nblk, int count, double* out) {
+__global__ __launch_bounds__(256) void k_reduce1(const acc_t* part, int nblk, int count, int qchunk,
+                                                 double* stage) {
+  __shared__ double lds[4][64];
+  const int cl = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
+  const int q0 = blockIdx.y * qchunk, q1 = min(nblk, q0 + qchunk);
+  double s = 0.0;
+  if (c < count)
+    for (int q = q0 + rg; q < q1; q += 4) s += (double)part[(size_t)q * count + c];
+  lds[rg][cl] = s;
+  __syncthreads();
+  if (rg == 0 && c < count)
+    stage[(size_t)blockIdx.y * count + c] = (lds[0][cl] + lds[1][cl]) + (lds[2][cl] + lds[3][cl]);
+}
+
+__global__ __launch_bounds__(256) void k_reduce2(const double* stage, int nq, int count, double* out) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= count) return;
   double s = 0.0;
-  for (int q = 0; q < nblk; ++q) s += (double)part[(size_t)q * count + i];
+  for (int q = 0; q < nq; ++q) s += stage[(size_t)q * count + i];
   out[i] = s;
 }
 
@@ -515,10 +533,17 @@ void launch_dR(const BSpecArgs& a, int prec, int C, double* gre, double* gim, hi
   }
 }
 
-void launch_reduce(const void* part, int prec, int nblk, int count, double* out, hipStream_t s) {
-  const dim3 g((count + 255) / 256);
-  if (prec == P64) hipLaunchKernelGGL(k_reduce<double>, g, dim3(256), 0, s, (const double*)part, nblk, count, out);
-  else hipLaunchKernelGGL(k_reduce<float>, g, dim3(256), 0, s, (const float*)part, nblk, count, out);
+void launch_reduce(const void* part, int prec, int nblk, int count, double* out, double* stage,
+                   hipStream_t s) {
+  const int nq = std::min(REDUCE_CHUNKS, nblk);
+  const int qchunk = (nblk + nq - 1) / nq;
+  const int nqe = (nblk + qchunk - 1) / qchunk;   // chunks actually holding blocks
+  const dim3 g1((count + 63) / 64, nqe);
+  if (prec == P64)
+    hipLaunchKernelGGL(k_reduce1<double>, g1, dim3(256), 0, s, (const double*)part, nblk, count, qchunk, stage);
+  else
+    hipLaunchKernelGGL(k_reduce1<float>, g1, dim3(256), 0, s, (const float*)part, nblk, count, qchunk, stage);
+  hipLaunchKernelGGL(k_reduce2, dim3((count + 255) / 256), dim3(256), 0, s, (const double*)stage, nqe, count, out);
 }
 
 void launch_adamw(double* theta, const double* g, double* m, double* v, size_t n, double lr, double wd, double b1,

@@ -58,14 +58,14 @@ def grf(g: np.random.Generator, n: int, h: float, ell: float = 0.1,
 def coefficient_field(g: np.random.Generator, N: int, contrast: float | None = None,
                       ell: float = 0.1) -> np.ndarray:
     """Nodal coefficient ``[N+2][N+2]``: ``exp(GRF)``, or with ``contrast`` the
-    exponent rescaled to ``[0, ln contrast]`` so that ``k`` lies in ``[1, contrast]``."""
+    exponent rescaled to ``[-ln(contrast)/2, ln(contrast)/2]``."""
     h = 1.0 / (N + 1)
     gk = grf(g, N + 2, h, ell)
     if contrast is None:
         return np.exp(gk)
     lo, hi = gk.min(), gk.max()
     t = (gk - lo) / (hi - lo)
-    return np.exp(np.log(contrast) * t)
+    return np.exp(np.log(contrast) * (t - 0.5))
 
 
 def rhs_field(g: np.random.Generator, N: int, ell: float = 0.1) -> np.ndarray:
@@ -80,8 +80,10 @@ def initial_guess(g: np.random.Generator, N: int) -> np.ndarray:
 def system(seed: int, N: int, contrast_range: tuple[float, float] | None = None):
     """One seeded system ``(k, f, u0, contrast)``.
 
-    With ``contrast_range=(lo, hi)`` the contrast is log-uniform in it and is
-    drawn after u0 (so ``k`` is built last from the stored GRF sample)."""
+    With ``contrast_range=(lo, hi)`` the contrast c is log-uniform in it and is
+    drawn after u0 (so ``k`` is built last from the stored GRF sample); the
+    GRF exponent is rescaled so that k spans [c^-1/2, c^1/2] (ratio c,
+    geometric midpoint 1)."""
     g = rng(seed)
     h = 1.0 / (N + 1)
     gk = grf(g, N + 2, h)
@@ -92,7 +94,7 @@ def system(seed: int, N: int, contrast_range: tuple[float, float] | None = None)
     lo, hi = contrast_range
     c = float(np.exp(g.uniform(np.log(lo), np.log(hi))))
     t = (gk - gk.min()) / (gk.max() - gk.min())
-    return np.exp(np.log(c) * t), f, u0, c
+    return np.exp(np.log(c) * (t - 0.5)), f, u0, c
 
 
 def batch(workload: int, B: int, N: int, contrast_range=None, first: int = 0):

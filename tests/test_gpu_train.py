@@ -184,3 +184,30 @@ def test_autograd_function(dev):
     rel = np.linalg.norm(wts.grad.cpu().numpy() - gref) / np.linalg.norm(gref)
     assert rel < 1e-11
     model.close()
+
+
+def test_krylov_samples_match_oracle(dev):
+    """GPU conjugate-gradient samples (r_i, u* - u_i) against the oracle's CG
+    with u* from a sparse direct solve.  CG amplifies rounding differences
+    from one iteration to the next, so the tolerance on r_i follows the spread
+    of a shadow oracle run whose u0 is perturbed at the 1e-15 level."""
+    N, B, m = 32, 3, 24
+    k, f, u0 = _data(N, B, 900)
+    kd, fd, ud = [torch.from_numpy(a).to(dev) for a in (k, f, u0)]
+    r, e = fc.krylov_samples(kd, fd, ud, m_iter=m)
+    r, e = r.cpu().numpy(), e.cpu().numpy()
+    for b in range(B):
+        rr, ee = oracle.krylov_samples(k[b], f[b], u0[b], m)
+        rr, ee = rr.numpy(), ee.numpy()
+        pert = u0[b] * (1.0 + 1e-15 * synth.rng(b).standard_normal(u0[b].shape))
+        rs, _ = oracle.krylov_samples(k[b], f[b], pert, m)
+        rs = rs.numpy()
+        for i in range(m):
+            spread = np.linalg.norm(rs[i] - rr[i]) / np.linalg.norm(rr[i])
+            dr = np.linalg.norm(r[b, i] - rr[i]) / np.linalg.norm(rr[i])
+            de = np.linalg.norm(e[b, i] - ee[i]) / np.linalg.norm(ee[i])
+            assert dr < max(1e-10, 100 * spread) and de < max(1e-8, 100 * spread), (b, i, dr, spread, de)
+        # A e_i = r_i up to the tight solve's residual
+        Ae = oracle.stencil_apply(k[b], e[b]).numpy()
+        rel = np.linalg.norm(Ae - r[b]) / np.linalg.norm(r[b, -1])
+        assert rel < 1e-7
