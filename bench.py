@@ -41,7 +41,7 @@ def parse():
     p.add_argument("--weights", default=None, help="load trained weights (.npy) instead of training")
     p.add_argument("--save-weights", default=None)
     p.add_argument("--ops", default="bf16,fp32,fp64", help="first one is the reported value")
-    p.add_argument("--max-iter", type=int, default=3000)
+    p.add_argument("--max-iter", type=int, default=0, help="default max(2N, 300)")
     p.add_argument("--rtol", type=float, default=1e-6)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -151,7 +151,7 @@ def time_solves(fc, torch, model, kd, fd, u0d, op, steps, warmup, args, prof_ker
     return total, lat, outs, us[-1], prof
 
 
-def cpu_baseline(k, f, u0, blob, C, M, L, iters_needed, seconds, logf):
+def cpu_baseline(k, f, u0, blob, C, M, L, iters_needed, conv_frac, seconds, logf):
     """The oracle (FP64 FCG with the FP64 operator) on system 0 of the batch,
     for as many iterations as fit in about ``seconds``; scaled to solves/sec
     with the iteration count the solve needs.  The oracle's time per
@@ -174,11 +174,12 @@ def cpu_baseline(k, f, u0, blob, C, M, L, iters_needed, seconds, logf):
     dt = time.perf_counter() - t0
     per_iter = dt / n_it
     log(f"cpu oracle: {n_it} iterations in {dt:.1f}s ({per_iter:.3f}s/iter)", logf)
-    return {"value": 1.0 / (per_iter * iters_needed), "unit": "solves/sec", "cores": torch.get_num_threads(),
+    return {"value": conv_frac / (per_iter * iters_needed), "unit": "solves/sec", "cores": torch.get_num_threads(),
             "kind": "oracle",
             "sample": f"first {n_it} FCG iterations (FP64 operator, m=5) of system 0 of the batch, "
                       f"{per_iter:.3f} s/iteration, scaled by the {iters_needed} iterations the batch's "
-                      f"FP64-operator solves took on average"}
+                      f"FP64-operator solves took on average and by the fraction {conv_frac:.3f} of them "
+                      f"that reached the tolerance"}
 
 
 def main():
@@ -197,6 +198,8 @@ def main():
     dev = torch.device("cuda:0")
     N, B, C, M, L = args.n, args.batch, 32, 12, 4
     ops = args.ops.split(",")
+    if args.max_iter <= 0:
+        args.max_iter = max(2 * N, 300)
 
     if args.calibrate_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
@@ -240,48 +243,66 @@ def main():
     main_op = ops[0]
     R = results[main_op]
     ms_per_step = R["seconds"] / R["steps"] * 1e3
-    value = B * R["steps"] / R["seconds"]
+    # solves that reached the tolerance, per second of the timed steps
+    value = float((R["status"] == 0).sum()) / R["seconds"]
     lat_ms = np.array(R["lat"]) * 1e3
 
-    # roofline of the inner layer kernel (the operator's dominant launch)
+    # Roofline of the inner layer kernel.  Systems that have stopped leave
+    # their blocks at once, so a launch moves the bytes of its active systems
+    # only: (L - 2) inner-layer launches per iteration of each system, i.e.
+    # (L - 2) * sum(iters) active system-launches over the timed solves.
     esize = {"bf16": 2, "fp32": 4, "fp64": 8}[main_op]
     asize = 8 if main_op == "fp64" else 4
     S = ((N + 15) // 16 + 31) // 32
-    nb = layer_bytes_per_launch(N, B, C, M, esize, asize, S)
+    per_sys = layer_bytes_per_launch(N, 1, C, M, esize, asize, S)
     n_l, ms_l = prof["layer"]
+    sys_launches = (L - 2) * int(R["iters"].sum())
+    act_avg = sys_launches / max(n_l, 1)
+    nb = per_sys * act_avg
     avg_us = ms_l / max(n_l, 1) * 1e3
     achieved = nb / (avg_us * 1e-6) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == f"{N}x{N}x{B}":
-            traffic = tr["bytes_per_launch"]
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("grid") == N and tr.get("batch") == B \
+                and tr.get("op") == main_op:
+            # counters were taken on launches with every system active
+            traffic = round(tr["bytes_per_launch_all_active"] * act_avg / B)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"k_layer<{main_op}, C={C}, MP=32> inner layer", "launches": n_l,
-                "avg_us": round(avg_us, 2), "algorithmic_bytes_per_launch": nb}
+                "avg_us": round(avg_us, 2), "active_systems_per_launch": round(act_avg, 3),
+                "algorithmic_bytes_per_system": per_sys, "algorithmic_bytes_per_launch": round(nb)}
 
     per_kernel = {name: {"launches": n_, "avg_us": round(ms_ / max(n_, 1) * 1e3, 2)}
                   for name, (n_, ms_) in prof.items()}
     comparison = {}
     ref = results.get("fp64")
     for op, Rr in results.items():
+        conv = Rr["status"] == 0
         d = {"solves_per_sec": round(B * Rr["steps"] / Rr["seconds"], 3),
+             "converged_per_sec": round(float(conv.sum()) / Rr["seconds"], 3),
              "ms_per_solve_batch": round(Rr["seconds"] / Rr["steps"] * 1e3, 2),
              "iters_mean": round(float(Rr["iters"].mean()), 2), "iters_max": int(Rr["iters"].max()),
-             "converged": int((Rr["status"] == 0).sum()), "of": int(Rr["status"].size),
-             "true_rel_res_max": float(Rr["tres"].max())}
+             "status_counts": {"ok": int(conv.sum()), "not_converged": int((Rr["status"] == 1).sum()),
+                               "breakdown": int((Rr["status"] == 2).sum())},
+             "true_rel_res_max_converged": float(Rr["tres"][conv].max()) if conv.any() else None}
         if ref is not None and op != "fp64":
+            # same systems, last timed step of each; compare where both converged
+            lo, lr_ = Rr["status"][-B:] == 0, ref["status"][-B:] == 0
+            both = torch.from_numpy(lo & lr_).to(Rr["u"].device)
             du = torch.linalg.vector_norm(Rr["u"] - ref["u"], dim=(1, 2)) / torch.linalg.vector_norm(ref["u"], dim=(1, 2))
-            d["u_rel_diff_vs_fp64_op_max"] = float(du.max())
+            d["u_rel_diff_vs_fp64_op_max"] = float(du[both].max()) if bool(both.any()) else None
+            d["iters_diff_vs_fp64_op"] = (Rr["iters"][-B:] - ref["iters"][-B:]).tolist()
         comparison[op] = d
 
     cpu = None
     if not args.no_cpu_baseline:
-        iters_needed = int(round(float(results["fp64"]["iters"].mean()))) if "fp64" in results \
-            else int(round(float(R["iters"].mean())))
-        cpu = cpu_baseline(k[0], f[0], u0[0], synth.init_weights(3, C, M, L), C, M, L, iters_needed,
+        Rb = results.get("fp64", R)
+        iters_needed = int(round(float(Rb["iters"].mean())))
+        conv_frac = float((Rb["status"] == 0).mean())
+        cpu = cpu_baseline(k[0], f[0], u0[0], synth.init_weights(3, C, M, L), C, M, L, iters_needed, conv_frac,
                            args.cpu_seconds, logf)
 
     line = {

@@ -338,15 +338,15 @@ void fill_no(const fcgno_model* m, const Plan& p, char* base, int N, int B, int 
   const size_t n = (size_t)N * N;
   const int esz = op_esize(op), asz = acc_esize(op);
   for (int b = 0; b < B; ++b) {
-    h[b].act = base + p.act + (size_t)b * n * C * esz;
+    h[b].act = (decltype(h[b].act))(base + p.act + (size_t)b * n * C * esz);
     h[b].act_stride = (size_t)B * n * C;   // elements between activation slots
-    h[b].logk = base + p.logk + (size_t)b * n * esz;
-    h[b].Gr = (double*)(base + p.Gr) + (size_t)b * N * MP;
-    h[b].Gp = base + p.Gp + (size_t)b * p.gp_bytes_per_sys;
-    h[b].Hc = base + p.Hc + (size_t)b * N * C * MP * esz;
-    h[b].Vc = base + p.Vc + (size_t)b * C * 2 * M * M * 2 * asz;
-    h[b].Wh = base + p.Wh + (size_t)b * p.wh_bytes_per_sys;
-    h[b].Vp = base + p.Vp + (size_t)b * p.vp_bytes_per_sys;
+    h[b].logk = (decltype(h[b].logk))(base + p.logk + (size_t)b * n * esz);
+    h[b].Gr = (decltype(h[b].Gr))((double*)(base + p.Gr) + (size_t)b * N * MP);
+    h[b].Gp = (decltype(h[b].Gp))(base + p.Gp + (size_t)b * p.gp_bytes_per_sys);
+    h[b].Hc = (decltype(h[b].Hc))(base + p.Hc + (size_t)b * N * C * MP * esz);
+    h[b].Vc = (decltype(h[b].Vc))(base + p.Vc + (size_t)b * C * 2 * M * M * 2 * asz);
+    h[b].Wh = (decltype(h[b].Wh))(base + p.Wh + (size_t)b * p.wh_bytes_per_sys);
+    h[b].Vp = (decltype(h[b].Vp))(base + p.Vp + (size_t)b * p.vp_bytes_per_sys);
   }
 }
 
@@ -439,17 +439,17 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
   for (int b = 0; b < B; ++b) {
     SysDev& sd = h[b];
     std::memset(&sd, 0, sizeof(SysDev));
-    sd.k = k + (size_t)b * (N + 2) * (N + 2);
-    sd.f = f + (size_t)b * n;
-    sd.u = u + (size_t)b * n;
-    sd.r = r_out ? r_out + (size_t)b * n : (double*)(base + p.r) + (size_t)b * n;
-    sd.w = op == PID ? sd.r : (double*)(base + p.w) + (size_t)b * n;
-    sd.P = (double*)(base + p.P) + (size_t)b * (d->m_max + 1) * n;
-    sd.S = (double*)(base + p.S) + (size_t)b * (d->m_max + 1) * n;
-    sd.st = st + b;
-    sd.hist = (double*)(base + p.hist) + (size_t)b * (d->max_iter + 1);
-    sd.part = (double*)(base + p.part) + (size_t)b * p.n_part_blocks * NQ;
-    sd.n_active = counter;
+    sd.k = (decltype(sd.k))(k + (size_t)b * (N + 2) * (N + 2));
+    sd.f = (decltype(sd.f))(f + (size_t)b * n);
+    sd.u = (decltype(sd.u))(u + (size_t)b * n);
+    sd.r = (decltype(sd.r))(r_out ? r_out + (size_t)b * n : (double*)(base + p.r) + (size_t)b * n);
+    sd.w = op == PID ? sd.r : (decltype(sd.w))((double*)(base + p.w) + (size_t)b * n);
+    sd.P = (decltype(sd.P))((double*)(base + p.P) + (size_t)b * (d->m_max + 1) * n);
+    sd.S = (decltype(sd.S))((double*)(base + p.S) + (size_t)b * (d->m_max + 1) * n);
+    sd.st = (decltype(sd.st))(st + b);
+    sd.hist = (decltype(sd.hist))((double*)(base + p.hist) + (size_t)b * (d->max_iter + 1));
+    sd.part = (decltype(sd.part))((double*)(base + p.part) + (size_t)b * p.n_part_blocks * NQ);
+    sd.n_active = (decltype(sd.n_active))(counter);
   }
   if (op != PID) fill_no(m, p, base, N, B, op, h);
   const SysDev* sysdev = (const SysDev*)(base + p.sysdev);
@@ -564,12 +564,12 @@ fcgno_status operator_forward(const fcgno_model* m, const Plan& p, char* base, i
   for (int b = 0; b < B; ++b) {
     SysDev& sd = h[b];
     std::memset(&sd, 0, sizeof(SysDev));
-    sd.k = k + (size_t)b * (N + 2) * (N + 2);
-    sd.r = const_cast<double*>(r) + (size_t)b * n;
-    sd.w = w + (size_t)b * n;
-    sd.st = st + b;
-    sd.part = (double*)(base + p.part) + (size_t)b * p.n_part_blocks * NQ;
-    sd.n_active = (int*)(base + p.counter);
+    sd.k = (decltype(sd.k))(k + (size_t)b * (N + 2) * (N + 2));
+    sd.r = (decltype(sd.r))(const_cast<double*>(r) + (size_t)b * n);
+    sd.w = (decltype(sd.w))(w + (size_t)b * n);
+    sd.st = (decltype(sd.st))(st + b);
+    sd.part = (decltype(sd.part))((double*)(base + p.part) + (size_t)b * p.n_part_blocks * NQ);
+    sd.n_active = (decltype(sd.n_active))((int*)(base + p.counter));
   }
   fill_no(m, p, base, N, B, op, h);
   const SysDev* sysdev = (const SysDev*)(base + p.sysdev);

@@ -16,6 +16,18 @@ constexpr int TPW = 32;         // 16-point column tiles per wave in the layer k
 
 enum Prec { P64 = 0, P32 = 1, PBF = 2, PID = 3 };
 
+// Device memory reached through pointers that the kernels read from memory
+// (the per-system tables) is declared in the global address space for the
+// device compiler, so that accesses compile to global_* rather than flat_*
+// instructions (flat accesses also count against the LDS wait counter, which
+// makes every LDS wait drain outstanding memory loads).  Host code sees plain
+// pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GLOBAL __attribute__((address_space(1)))
+#else
+#define GLOBAL
+#endif
+
 enum SysStatus { S_OK = 0, S_NOTCONV = 1, S_BREAK = 2, S_NONFINITE = 3 };
 
 // Scalar state of one system, resident on the device.
@@ -41,27 +53,27 @@ struct SysState {
 
 // Per-system device pointers.  All systems of one launch share N.
 struct SysDev {
-  const double* k;   // [(N+2)^2]
-  const double* f;   // [N^2]
-  double* u;
-  double* r;
-  double* w;         // == r for the identity operator
-  double* P;         // ring [(m_max+1)][N^2]
-  double* S;         // ring
-  SysState* st;
-  double* hist;      // [max_iter+1]
-  double* part;      // [blocks][NQ]
-  int* n_active;     // batch counter of active systems
+  const GLOBAL double* k;   // [(N+2)^2]
+  const GLOBAL double* f;   // [N^2]
+  GLOBAL double* u;
+  GLOBAL double* r;
+  GLOBAL double* w;         // == r for the identity operator
+  GLOBAL double* P;         // ring [(m_max+1)][N^2]
+  GLOBAL double* S;         // ring
+  GLOBAL SysState* st;
+  GLOBAL double* hist;      // [max_iter+1]
+  GLOBAL double* part;      // [blocks][NQ]
+  GLOBAL int* n_active;     // batch counter of active systems
   // operator buffers (op precision unless noted)
-  void* act;         // [slots][N^2][C]
-  size_t act_stride; // elements per activation slot
-  void* logk;        // [N^2]
-  double* Gr;        // [N][MP] row DFT partials of r, float64
-  void* Gp;          // [N][S][MP][C] row DFT partials of activations, accumulate precision
-  void* Hc;          // [N][C][MP] synthesis rows for the layer kernel
-  void* Vc;          // [C][2M][M] complex, accumulate precision: constant part of layer-0 spectrum
-  void* Wh;          // [M][C][MP] complex, accumulate precision: mixed spectrum of the current layer (zero past 2M)
-  void* Vp;          // [M][XS][C][2M] complex, accumulate precision: per-chunk forward spectra
+  GLOBAL void* act;         // [slots][N^2][C]
+  size_t act_stride;        // elements per activation slot
+  GLOBAL void* logk;        // [N^2]
+  GLOBAL double* Gr;        // [N][MP] row DFT partials of r, float64
+  GLOBAL void* Gp;          // [N][S][MP][C] row DFT partials of activations, accumulate precision
+  GLOBAL void* Hc;          // [N][C][MP] synthesis rows for the layer kernel
+  GLOBAL void* Vc;          // [C][2M][M] complex, accumulate precision: constant part of layer-0 spectrum
+  GLOBAL void* Wh;          // [M][C][MP] complex, accumulate precision: mixed spectrum of the current layer (zero past 2M)
+  GLOBAL void* Vp;          // [M][XS][C][2M] complex, accumulate precision: per-chunk forward spectra
 };
 
 // Per-N tables shared by the systems of one launch.
@@ -99,7 +111,7 @@ __device__ __forceinline__ T block_sum(T v, T* lds /* >= 4 */) {
   return s;
 }
 
-__device__ __forceinline__ void deactivate(SysState* st, int* n_active, int status, int iters) {
+__device__ __forceinline__ void deactivate(GLOBAL SysState* st, GLOBAL int* n_active, int status, int iters) {
   st->status = status;
   st->iters = iters;
   st->active = 0;
@@ -140,6 +152,22 @@ __device__ __forceinline__ float erf_as(float x) {
 // GELU(z) = z/2 (1 + erf(z / sqrt 2))
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f)); }
 __device__ __forceinline__ double gelu(double z) { return 0.5 * z * (1.0 + erf(z * 0.70710678118654752440)); }
+
+// GELU of the bfloat16 operator: z * sigmoid(P(z)), P(z) = z (c1 + c3 z^2 +
+// c5 z^4 + c7 z^6) fitted for the smallest maximum deviation from the erf
+// form on [-6, 6] (argument clamped there): |error| <= 1.3e-5 in float32,
+// below the bfloat16 rounding of the result wherever |GELU(z)| > 3e-3.  Two
+// transcendental and eight plain operations against twenty-odd for erf_as.
+// The coefficients below are -c_k log2(e), so sigmoid(P) = 1 / (1 + 2^(poly)).
+__device__ __forceinline__ float gelu_bf(float z) {
+  const float zc = __builtin_amdgcn_fmed3f(z, -6.0f, 6.0f);
+  const float u = zc * zc;
+  float q = fmaf(u, 2.481038791302126e-05f, 7.364328484982252e-04f);
+  q = fmaf(q, u, -1.0598407685756683e-01f);
+  q = fmaf(q, u, -2.3016459941864014f);
+  const float e = __builtin_amdgcn_exp2f(q * zc);
+  return z * __builtin_amdgcn_rcpf(1.0f + e);
+}
 
 // ---- host-side launchers (defined in the .hip files) ---------------------
 

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(64) void k_init_state(const SysDev* sys, int nsys, 
                                                    int m_max, double rtol) {
   const int b = blockIdx.x * 64 + threadIdx.x;
   if (b >= nsys) return;
-  SysState* st = sys[b].st;
+  GLOBAL SysState* st = sys[b].st;
   st->i = 0;
   st->active = 1;
   st->status = S_NOTCONV;
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void k_rnorm(const SysDev* sys, int N) {
 __global__ __launch_bounds__(256) void k_wdots(const SysDev* sys, int N) {
   __shared__ double lds[4];
   const SysDev sd = sys[blockIdx.y];
-  const SysState* st = sd.st;
+  const GLOBAL SysState* st = sd.st;
   if (!st->active) return;
   const int i = st->i, mm = st->m_max;
   const int m = window_size(i, mm);
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
   __shared__ double pl[HN];
   __shared__ double cf[MAXW];
   const SysDev sd = sys[blockIdx.y];
-  const SysState* st = sd.st;
+  const GLOBAL SysState* st = sd.st;
   if (!st->active) return;
   const int i = st->i, ring = st->m_max + 1;
   const int m = st->m;
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
 __global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
   __shared__ double lds[4];
   const SysDev sd = sys[blockIdx.y];
-  const SysState* st = sd.st;
+  const GLOBAL SysState* st = sd.st;
   if (!st->active) return;
   const int i = st->i, ring = st->m_max + 1;
   const double alpha = st->alpha;
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
 __global__ __launch_bounds__(256) void k_fin(const SysDev* sys, int N, int mode) {
   __shared__ double lds[4];
   const SysDev sd = sys[blockIdx.x];
-  SysState* st = sd.st;
+  GLOBAL SysState* st = sd.st;
   if (mode != 4 && mode != 5 && !st->active) return;
   const int nb = (mode == 1) ? tile_blocks(N) : flat_blocks(N * N);
   auto fsum = [&](int q) {

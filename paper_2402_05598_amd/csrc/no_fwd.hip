@@ -22,6 +22,8 @@
 // (W_L[:,0]/s) DFT(r) + (a per-solve constant from log k, x1, x2, 1).
 #include <algorithm>
 
+#include <type_traits>
+
 #include "common.h"
 #include "prof.h"
 
@@ -460,6 +462,14 @@ __global__ __launch_bounds__(256) void k_spec_inv(SpecArgs a) {
 // Layer kernel: synthesis along y + bypass + bias + GELU, then either the
 // next layer's y-direction analysis or the projection.
 // ---------------------------------------------------------------------------
+// Layer activation in the accumulate precision: erf-form GELU for the float64
+// and float32 operators, the cheaper fitted form for the bfloat16 operator.
+template <int PREC, typename T>
+__device__ __forceinline__ T act(T z) {
+  if constexpr (PREC == PBF) return gelu_bf(z);
+  else return gelu(z);
+}
+
 struct LayerArgs {
   const SysDev* sys;
   int N, S, twoM, slot_in, slot_out;
@@ -534,26 +544,50 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
   const double h = 1.0 / (double)(N + 1);
   const double bP = PROJ ? *a.bP : 0.0;
 
+  // Lane-constant parts of every per-tile address; a tile adds the uniform
+  // offset of its first point y0.
+  const in_t* Tl = T + n16 * MP + g * KPL;                       // A operand rows of GEMM1
+  const in_t* TTl = TT + n16 * NP + 4 * g;                        // A operand of GEMM2 (KPL == 4)
+  const in_t* act_l = act_in + n16 * C + g * CB;                  // this lane's input channels
+  constexpr int CPR = C * (int)sizeof(in_t) / 16;                 // 16-byte chunks per point
+  static_assert(16 * CPR <= 64 || (16 * CPR) % 64 == 0, "store chunks per lane");
   // Operands of one 16-point tile: A fragments (twiddles and inputs); for the
-  // feature layer the raw features.  Loaded one tile ahead of their use.
+  // feature layer the raw features.  FULL: all 16 points lie inside the row.
+  // GEMM2's twiddle operand is part of the prefetch too: loading it at its
+  // use would make the wave wait for every older memory operation (the
+  // counter drains in order), stores and prefetches included.
+  constexpr int NA2 = PROJ ? 1 : (KPL == 4 ? MB : 4 * MB);
   struct TileIn {
     frag_t Af[KT + KIN];
+    frag_t A2[NA2];
     double rr;
     acc_t lk;
   };
-  auto load_tile = [&](int t, TileIn& ti) {
+  auto load_tile = [&](int t, TileIn& ti, auto fullc) __attribute__((always_inline)) {
+    constexpr bool FULL = decltype(fullc)::value;
     const int y0 = t * 16;
     const int ya = y0 + n16;
-    const bool va = ya < N;
+    const bool va = FULL || ya < N;
 #pragma unroll
-    for (int ks = 0; ks < KT; ++ks) ti.Af[ks] = M_::ld(T + ya * MP + ks * KSTEP + g * KPL);
+    for (int ks = 0; ks < KT; ++ks) ti.Af[ks] = M_::ld(Tl + y0 * MP + ks * KSTEP);
+    if constexpr (!PROJ) {
+      if constexpr (KPL == 4) {
+#pragma unroll
+        for (int jb = 0; jb < MB; ++jb) ti.A2[jb] = M_::ld(TTl + jb * 16 * NP + y0);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int jb = 0; jb < MB; ++jb) ti.A2[i * MB + jb] = T[(y0 + M_::row(g, i)) * MP + jb * 16 + n16];
+      }
+    }
     if constexpr (FEAT) {
       ti.rr = va ? sd.r[(size_t)x * N + ya] : 0.0;
       ti.lk = va ? M_::up(((const in_t*)sd.logk)[(size_t)x * N + ya]) : (acc_t)0;
     } else {
       typedef typename Vec<in_t, CB>::type vec_t;
       vec_t vv = {};
-      if (va) vv = *(const vec_t*)(act_in + (size_t)ya * C + g * CB);
+      if (va) vv = *(const vec_t*)(act_l + y0 * C);
 #pragma unroll
       for (int ks = 0; ks < KIN; ++ks) {
         if constexpr (KPL == 4) {
@@ -565,14 +599,12 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
       }
     }
   };
-  TileIn nxt;
-  if (t0 < t1) load_tile(t0, nxt);
-  for (int t = t0; t < t1; ++t) {
+  // One 16-point tile: GEMM1, GELU, store, GEMM2 (or the projection).
+  auto process = [&](int t, const TileIn& cur, auto fullc) __attribute__((always_inline)) {
+    constexpr bool FULL = decltype(fullc)::value;
     const int y0 = t * 16;
     const int ya = y0 + n16;
-    const bool va = ya < N;
-    TileIn cur = nxt;
-    if (t + 1 < t1) load_tile(t + 1, nxt);
+    const bool va = FULL || ya < N;
     frag_t Af[KT + KIN];
 #pragma unroll
     for (int ks = 0; ks < KT + KIN; ++ks) Af[ks] = cur.Af[ks];
@@ -603,7 +635,6 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
       for (int ks = 0; ks < KIN; ++ks) acc[ob] = M_::mma(Af[KT + ks], Bf[KT + ks][ob], acc[ob]);
     }
     // lane holds z[y0 + row(g, i)][ob*16 + n16]
-    constexpr int CPR = C * (int)sizeof(in_t) / 16;   // 16-byte chunks per point
     if (a.zout) {
       // training: keep the pre-activation (same LDS transpose as the activations)
       in_t* ot = otile[threadIdx.x >> 6];
@@ -611,16 +642,18 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
       for (int ob = 0; ob < NOB; ++ob)
 #pragma unroll
         for (int i = 0; i < 4; ++i) ot[M_::row(g, i) * (C + PADE) + ob * 16 + n16] = M_::cvt(acc[ob][i]);
-      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      // compiler-only barrier: LDS operations of one wave complete in order,
+      // so the reads below see the writes above without a wait instruction
+      asm volatile("" ::: "memory");
       in_t* zo = (in_t*)a.zout + a.z_sys * blockIdx.y + (size_t)x * N * C;
       for (int q = lane; q < 16 * CPR; q += 64) {
         const int pt = q / CPR, ch = q - pt * CPR;
-        if (y0 + pt < N) {
+        if (FULL || y0 + pt < N) {
           const uint4 val = *(const uint4*)((const char*)ot + pt * (C + PADE) * sizeof(in_t) + ch * 16);
           *(uint4*)((char*)zo + ((size_t)(y0 + pt) * C) * sizeof(in_t) + ch * 16) = val;
         }
       }
-      asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+      asm volatile("" ::: "memory");
     }
     if constexpr (PROJ) {
 #pragma unroll
@@ -628,12 +661,12 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
         const int yv = y0 + M_::row(g, i);
         acc_t part = 0;
 #pragma unroll
-        for (int ob = 0; ob < NOB; ++ob) part += wp[ob] * gelu(acc[ob][i]);
+        for (int ob = 0; ob < NOB; ++ob) part += wp[ob] * act<PREC>(acc[ob][i]);
         part += __shfl_xor(part, 1, 64);
         part += __shfl_xor(part, 2, 64);
         part += __shfl_xor(part, 4, 64);
         part += __shfl_xor(part, 8, 64);
-        if (n16 == i && yv < N) sd.w[(size_t)x * N + yv] = snorm * ((double)part + bP);
+        if (n16 == i && (FULL || yv < N)) sd.w[(size_t)x * N + yv] = snorm * ((double)part + bP);
       }
     } else {
       // v' = GELU(z) rounded once to the op precision; rows past N are zero
@@ -642,9 +675,8 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
       for (int ob = 0; ob < NOB; ++ob)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int yv = y0 + M_::row(g, i);
-          const acc_t gv = gelu(acc[ob][i]);
-          hv[ob][i] = M_::cvt(yv < N ? gv : (acc_t)0);
+          const acc_t gv = act<PREC>(acc[ob][i]);
+          hv[ob][i] = M_::cvt((FULL || y0 + M_::row(g, i) < N) ? gv : (acc_t)0);
         }
       // transpose the 16 x C tile through LDS, then 16-byte coalesced stores
       in_t* ot = otile[threadIdx.x >> 6];
@@ -652,19 +684,25 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
       for (int ob = 0; ob < NOB; ++ob)
 #pragma unroll
         for (int i = 0; i < 4; ++i) ot[M_::row(g, i) * (C + PADE) + ob * 16 + n16] = hv[ob][i];
-      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-      for (int q = lane; q < 16 * CPR; q += 64) {
+      // compiler-only barrier: LDS operations of one wave complete in order,
+      // so the reads below see the writes above without a wait instruction
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int q0 = 0; q0 < 16 * CPR; q0 += 64) {
+        const int q = q0 + lane;
         const int pt = q / CPR, ch = q - pt * CPR;
-        if (y0 + pt < N) {
-          const uint4 val = *(const uint4*)((const char*)ot + pt * (C + PADE) * sizeof(in_t) + ch * 16);
-          *(uint4*)((char*)act_out + ((size_t)(y0 + pt) * C) * sizeof(in_t) + ch * 16) = val;
+        if ((16 * CPR) % 64 == 0 || q < 16 * CPR) {
+          if (FULL || y0 + pt < N) {
+            const uint4 val = *(const uint4*)((const char*)ot + pt * (C + PADE) * sizeof(in_t) + ch * 16);
+            *(uint4*)((char*)(act_out + (size_t)y0 * C) + pt * C * sizeof(in_t) + ch * 16) = val;
+          }
         }
       }
       // next layer's y-direction analysis: G2[j][o] += sum_y T[y][j] v'[y][o]
       if constexpr (KPL == 4) {
 #pragma unroll
         for (int jb = 0; jb < MB; ++jb) {
-          const frag_t A2 = M_::ld(TT + (jb * 16 + n16) * NP + y0 + 4 * g);
+          const frag_t A2 = cur.A2[jb];
 #pragma unroll
           for (int ob = 0; ob < NOB; ++ob) {
             const frag_t B2 = short4_t{(short)hv[ob][0], (short)hv[ob][1], (short)hv[ob][2], (short)hv[ob][3]};
@@ -674,16 +712,42 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
       } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int yv = y0 + M_::row(g, i);
 #pragma unroll
           for (int jb = 0; jb < MB; ++jb) {
-            const frag_t A2 = T[yv * MP + jb * 16 + n16];
+            const frag_t A2 = cur.A2[i * MB + jb];
 #pragma unroll
             for (int ob = 0; ob < NOB; ++ob) G2[jb][ob] = M_::mma(A2, (frag_t)hv[ob][i], G2[jb][ob]);
           }
         }
       }
     }
+  };
+  using full_t = std::integral_constant<bool, true>;
+  using part_t = std::integral_constant<bool, false>;
+  // Tiles t0 .. tf-1 hold 16 points each; at most one partial tile (the
+  // row's last, when 16 does not divide N) follows.  Full tiles keep two
+  // tiles in flight per wave: they alternate between two register sets, each
+  // refilled two tiles ahead of its use.
+  const int tf = min(t1, N >> 4);
+  TileIn ta, tb;
+  if (t0 < tf) load_tile(t0, ta, full_t{});
+  if (t0 + 1 < tf) load_tile(t0 + 1, tb, full_t{});
+  for (int t = t0; t < tf; t += 2) {
+    {
+      const TileIn cur = ta;
+      if (t + 2 < tf) load_tile(t + 2, ta, full_t{});
+      process(t, cur, full_t{});
+    }
+    if (t + 1 < tf) {
+      const TileIn cur = tb;
+      if (t + 3 < tf) load_tile(t + 3, tb, full_t{});
+      process(t + 1, cur, full_t{});
+    }
+  }
+  if (tf < t1) {
+    TileIn tl;
+    load_tile(tf, tl, part_t{});
+    process(tf, tl, part_t{});
   }
   if constexpr (!PROJ) {
     acc_t* Gp = (acc_t*)sd.Gp + (size_t)(x * a.S + seg) * MP * C;
