@@ -15,8 +15,8 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   fcg                          pinned: FCG(I) == textbook CG, PCG(Jacobi),
                                one-step convergence with A^-1, A-orthogonality,
                                energy identity, finite termination, Table 1
-  no_apply                     pinned: explicit-sum DFT on tiny grids, identity
-                               and homogeneity special cases, linearity in R
+  no_apply                     pinned: brute-force explicit-sum operator on tiny
+                               grids, exact homogeneity, B(0) = 0
   notay_loss / l2_loss         pinned: closed-form values on eigenvectors
   loss gradients (autograd)    pinned: central finite differences
   jacobi / sgs                 pinned: Table 1 iteration counts (statistical)
