@@ -210,6 +210,46 @@ fcgno_status fcgno_train_step(fcgno_model* m, fcgno_optim* opt, int32_t n, int32
                               void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Serving engine: continuous batching of solves (one system per request, any */
+/* grid size).  A request waits in a FIFO queue until a slot and a block of   */
+/* the engine's device pool (allocated once, budget_bytes) hold its state;     */
+/* admitted requests of one N advance together, check_every iterations of      */
+/* Algorithm 1 per fcgno_engine_step, with the kernels of fcgno_solve; systems */
+/* at different iterations share launches.  A request's result depends only on */
+/* its own inputs and N: it is the same alone and in any mix.  k, f and u      */
+/* (in: u0, out: u_iter) are device buffers owned by the caller until the      */
+/* request is reported by fcgno_engine_poll.  All work runs on the engine's     */
+/* stream; fcgno_engine_step synchronises it.  One thread at a time.           */
+/* ------------------------------------------------------------------------ */
+typedef struct fcgno_engine fcgno_engine;
+typedef struct {
+  int32_t op;            /* FCGNO_OP_*, as for fcgno_solve */
+  int32_t m_max;         /* truncation window, 1..32 */
+  int32_t check_every;   /* iterations per step (<= 0: 8) */
+  int32_t max_slots;     /* admitted requests at most */
+  size_t budget_bytes;   /* device pool for request state and per-N tables */
+} fcgno_engine_desc;
+typedef struct {
+  int64_t id;
+  int32_t status;        /* FCGNO_SYS_* */
+  int32_t iters;
+  double true_rel_res;   /* ||f - A u|| / ||r0|| */
+} fcgno_engine_result;
+
+/* Device bytes one request of grid n takes from the pool (0 if invalid). */
+size_t fcgno_engine_request_bytes(const fcgno_model* m, const fcgno_engine_desc* d, int32_t n, int32_t max_iter);
+fcgno_status fcgno_engine_create(const fcgno_model* m, const fcgno_engine_desc* d, void* stream,
+                                 fcgno_engine** out);
+/* Queue a request; FCGNO_E_NOMEM if it can never fit the budget. */
+fcgno_status fcgno_engine_submit(fcgno_engine* e, int32_t n, const double* k, const double* f, double* u,
+                                 double rtol, int32_t max_iter, int64_t* id_out);
+/* Admit what fits, advance every group, report and release stopped requests. */
+fcgno_status fcgno_engine_step(fcgno_engine* e, int32_t* n_active, int32_t* n_queued);
+/* Move up to max_results finished requests into out; returns the count. */
+int32_t fcgno_engine_poll(fcgno_engine* e, fcgno_engine_result* out, int32_t max_results);
+void fcgno_engine_destroy(fcgno_engine* e);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing: HIP event pairs recorded on the launch stream around each   */
 /* launch of a kernel family while enabled; read after the work completed.    */
 /* fcgno_profile_enable takes a bit mask of families (bit k = id k; 0 = off). */

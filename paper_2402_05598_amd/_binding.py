@@ -27,6 +27,15 @@ class SolveDesc(ctypes.Structure):
                 ("rtol", c_double), ("op", c_int32), ("check_every", c_int32)]
 
 
+class EngineDesc(ctypes.Structure):
+    _fields_ = [("op", c_int32), ("m_max", c_int32), ("check_every", c_int32), ("max_slots", c_int32),
+                ("budget_bytes", c_size_t)]
+
+
+class EngineResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", c_int32), ("iters", c_int32), ("true_rel_res", c_double)]
+
+
 class FcgnoError(RuntimeError):
     pass
 
@@ -86,6 +95,18 @@ def lib():
     L.fcgno_krylov_samples_workspace_bytes.restype = c_size_t
     L.fcgno_krylov_samples.argtypes = [c_int32, c_int32, c_int32, c_int32, vp, vp, vp, vp, vp, vp, c_size_t, vp]
     L.fcgno_krylov_samples.restype = c_int32
+    L.fcgno_engine_request_bytes.argtypes = [vp, POINTER(EngineDesc), c_int32, c_int32]
+    L.fcgno_engine_request_bytes.restype = c_size_t
+    L.fcgno_engine_create.argtypes = [vp, POINTER(EngineDesc), vp, POINTER(vp)]
+    L.fcgno_engine_create.restype = c_int32
+    L.fcgno_engine_submit.argtypes = [vp, c_int32, vp, vp, vp, c_double, c_int32, POINTER(ctypes.c_int64)]
+    L.fcgno_engine_submit.restype = c_int32
+    L.fcgno_engine_step.argtypes = [vp, POINTER(c_int32), POINTER(c_int32)]
+    L.fcgno_engine_step.restype = c_int32
+    L.fcgno_engine_poll.argtypes = [vp, POINTER(EngineResult), c_int32]
+    L.fcgno_engine_poll.restype = c_int32
+    L.fcgno_engine_destroy.argtypes = [vp]
+    L.fcgno_engine_destroy.restype = None
     L.fcgno_profile_enable.argtypes = [c_int32]
     L.fcgno_profile_enable.restype = None
     L.fcgno_profile_reset.argtypes = []
@@ -350,6 +371,70 @@ def krylov_samples(k, f, u0, m_iter=100, max_iter=None, stream=None):
                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
            "fcgno_krylov_samples")
     return r, e
+
+
+class Engine:
+    """Continuous-batching solve engine (fcgno_engine_*).  Requests are single
+    systems of any grid size; k, f, u stay referenced until the request is
+    reported by poll()."""
+
+    def __init__(self, model, op="bf16", m_max=5, check_every=8, max_slots=64, budget_bytes=8 << 30,
+                 stream=None):
+        self.model = model
+        self.desc = EngineDesc(OP[op], m_max, check_every, max_slots, int(budget_bytes))
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = c_void_p()
+        _check(lib().fcgno_engine_create(model.handle if (model is not None and op != "identity") else None,
+                                         ctypes.byref(self.desc), ctypes.c_void_p(self._stream.cuda_stream),
+                                         ctypes.byref(h)), "fcgno_engine_create")
+        self.handle = h
+        self._held = {}
+
+    def request_bytes(self, n, max_iter):
+        m = self.model.handle if self.model is not None else None
+        return int(lib().fcgno_engine_request_bytes(m, ctypes.byref(self.desc), n, max_iter))
+
+    def submit(self, k, f, u, rtol=1e-6, max_iter=None):
+        """Queue one system: k [N+2][N+2], f and u [N][N] float64 device tensors
+        (u: in u0, out the iterate).  Returns the request id."""
+        N = f.shape[-1]
+        if tuple(k.shape) != (N + 2, N + 2) or tuple(u.shape) != (N, N):
+            raise FcgnoError("shape mismatch: k [N+2][N+2], f and u [N][N]")
+        max_iter = max_iter or max(2 * N, 300)
+        rid = ctypes.c_int64(0)
+        _check(lib().fcgno_engine_submit(self.handle, N, _dev_f64(k, "k"), _dev_f64(f, "f"), _dev_f64(u, "u"),
+                                         rtol, max_iter, ctypes.byref(rid)), "fcgno_engine_submit")
+        self._held[rid.value] = (k, f, u)
+        return rid.value
+
+    def step(self):
+        """Admit, advance every group by check_every iterations, release stopped
+        requests.  Returns (active, queued)."""
+        a, q = c_int32(0), c_int32(0)
+        _check(lib().fcgno_engine_step(self.handle, ctypes.byref(a), ctypes.byref(q)), "fcgno_engine_step")
+        return a.value, q.value
+
+    def poll(self, max_results=4096):
+        buf = (EngineResult * max_results)()
+        n = lib().fcgno_engine_poll(self.handle, buf, max_results)
+        out = []
+        for i in range(n):
+            r = buf[i]
+            self._held.pop(r.id, None)
+            out.append({"id": r.id, "status": r.status, "iters": r.iters, "true_rel_res": r.true_rel_res})
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fcgno_engine_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class OperatorFunction(torch.autograd.Function):

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -877,4 +879,408 @@ extern "C" const char* fcgno_status_string(fcgno_status s) {
     case FCGNO_E_HIP: return "HIP runtime error";
   }
   return "unknown status";
+}
+
+// ---------------------------------------------------------------------------
+// Serving engine: continuous batching of FCG-NO solves.
+//
+// Requests (one system each, any N) wait in a queue until a slot and a block
+// of the engine's device pool are free; their state then lives on the device
+// until they stop.  Active requests of one N form a group; every step
+// advances every group by K iterations with the same kernels as
+// fcgno_solve (systems at different iterations share launches: all state is
+// per system), then reports and releases the requests that stopped.  A
+// system's arithmetic depends only on its own data and N, so its result is
+// the same bits alone and in any mix.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct EngReq {
+  int64_t id = 0;
+  int N = 0, max_iter = 0;
+  double rtol = 0.0;
+  const double* k = nullptr;
+  const double* f = nullptr;
+  double* u = nullptr;
+  size_t off = 0, bytes = 0;
+  Plan p;
+  SysDev sd{};
+};
+
+struct EngGroup {
+  int N = 0;
+  size_t off = 0, bytes = 0;
+  size_t E64 = 0, Eacc = 0, T = 0, TT = 0, table = 0, ftable = 0, flags = 0, tres = 0;
+  std::vector<int64_t> members;
+  bool dirty = true;
+  size_t hoff = 0;           // this step's range in the engine's pinned export buffers
+};
+
+}  // namespace
+
+struct fcgno_engine {
+  const fcgno_model* m = nullptr;
+  fcgno_engine_desc d{};
+  hipStream_t s = nullptr;
+  char* pool = nullptr;
+  std::map<size_t, size_t> free_;       // offset -> size of free blocks
+  std::deque<EngReq> queue;
+  std::map<int64_t, EngReq> active;
+  std::map<int, EngGroup> groups;
+  std::vector<fcgno_engine_result> done;
+  int64_t next_id = 1;
+  int* hflags = nullptr;     // pinned host copies of the exported state, max_slots entries
+  double* htres = nullptr;
+};
+
+namespace {
+
+bool pool_alloc(fcgno_engine* e, size_t bytes, size_t* off) {
+  bytes = align256(bytes);
+  for (auto it = e->free_.begin(); it != e->free_.end(); ++it) {
+    if (it->second >= bytes) {
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t roff = it->first + bytes;
+      e->free_.erase(it);
+      if (rest) e->free_[roff] = rest;
+      return true;
+    }
+  }
+  return false;
+}
+
+void pool_free(fcgno_engine* e, size_t off, size_t bytes) {
+  bytes = align256(bytes);
+  auto it = e->free_.emplace(off, bytes).first;
+  auto nx = std::next(it);
+  if (nx != e->free_.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    e->free_.erase(nx);
+  }
+  if (it != e->free_.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      e->free_.erase(it);
+    }
+  }
+}
+
+size_t request_bytes(const fcgno_model* m, int op, int m_max, int N, int max_iter) {
+  return make_plan(op == PID ? nullptr : m, N, 1, m_max, max_iter, op, KIND_SOLVE).total;
+}
+
+size_t group_bytes(const fcgno_model* m, int op, int N, int slots, EngGroup* g) {
+  Carver cv;
+  const int MP = m && op != PID ? round16(2 * m->arch.modes) : 16, NP = round16(N);
+  const int esz = op_esize(op == PID ? P64 : op), asz = acc_esize(op == PID ? P64 : op);
+  EngGroup t;
+  t.E64 = cv.take((size_t)N * 16);
+  t.Eacc = cv.take((size_t)N * 2 * asz);
+  t.T = cv.take((size_t)NP * MP * esz);
+  t.TT = cv.take((size_t)MP * NP * esz);
+  t.table = cv.take((size_t)slots * sizeof(SysDev));
+  t.ftable = cv.take((size_t)slots * sizeof(SysDev));
+  t.flags = cv.take((size_t)slots * 3 * sizeof(int));
+  t.tres = cv.take((size_t)slots * sizeof(double));
+  if (g) {
+    g->E64 = t.E64; g->Eacc = t.Eacc; g->T = t.T; g->TT = t.TT;
+    g->table = t.table; g->ftable = t.ftable; g->flags = t.flags; g->tres = t.tres;
+  }
+  return cv.n;
+}
+
+NOLaunch group_no(const fcgno_engine* e, const EngGroup& g, const SysDev* table, int nsys) {
+  const fcgno_model* m = e->m;
+  const int op = e->d.op;
+  char* base = e->pool + g.off;
+  NOLaunch L{};
+  L.sys = table;
+  L.nsys = nsys;
+  L.N = g.N;
+  L.C = m->arch.width;
+  L.M = m->arch.modes;
+  L.MP = round16(2 * L.M);
+  L.L = m->arch.layers;
+  L.S = ((round16(g.N) / 16) + TPW - 1) / TPW;
+  L.prec = op;
+  L.tab.E64 = (const double*)(base + g.E64);
+  L.tab.Eacc = base + g.Eacc;
+  L.tab.T = base + g.T;
+  L.tab.TT = base + g.TT;
+  L.Wfrag = m->Wfrag[op].data();
+  L.bias = m->bias[op].data();
+  L.Rmix = m->Rmix[op].data();
+  L.WP = m->WP[op];
+  L.bP = dev_bP(m);
+  L.WL0 = m->WL0[op];
+  L.WL = dev_WL(m);
+  L.bL = dev_bL(m);
+  L.stream = e->s;
+  L.op_bytes = op_esize(op);
+  L.acc_bytes = acc_esize(op);
+  return L;
+}
+
+fcgno_status group_open(fcgno_engine* e, int N, EngGroup** out) {
+  auto it = e->groups.find(N);
+  if (it != e->groups.end()) {
+    *out = &it->second;
+    return FCGNO_OK;
+  }
+  EngGroup g;
+  g.N = N;
+  g.bytes = group_bytes(e->d.op == PID ? nullptr : e->m, e->d.op, N, e->d.max_slots, &g);
+  if (!pool_alloc(e, g.bytes, &g.off)) return FCGNO_E_NOMEM;
+  if (e->d.op != PID) {
+    const NOLaunch NL = group_no(e, g, nullptr, 0);
+    char* base = e->pool + g.off;
+    launch_tables(NL, (double*)(base + g.E64), base + g.Eacc, base + g.T, base + g.TT);
+  }
+  auto res = e->groups.emplace(N, g);
+  *out = &res.first->second;
+  return FCGNO_OK;
+}
+
+void group_close(fcgno_engine* e, int N) {
+  auto it = e->groups.find(N);
+  if (it == e->groups.end()) return;
+  pool_free(e, it->second.off, it->second.bytes);
+  e->groups.erase(it);
+}
+
+// Set up one admitted request: state, operator inputs, r0 (all stream-ordered).
+fcgno_status admit(fcgno_engine* e, EngReq& q, EngGroup& g) {
+  const fcgno_model* m = e->d.op == PID ? nullptr : e->m;
+  const int N = q.N, op = e->d.op;
+  char* base = e->pool + q.off;
+  const size_t n = (size_t)N * N;
+  const Plan& p = q.p;
+  SysDev& sd = q.sd;
+  std::memset(&sd, 0, sizeof(SysDev));
+  sd.k = (decltype(sd.k))q.k;
+  sd.f = (decltype(sd.f))q.f;
+  sd.u = (decltype(sd.u))q.u;
+  sd.r = (decltype(sd.r))(base + p.r);
+  sd.w = op == PID ? sd.r : (decltype(sd.w))(base + p.w);
+  sd.P = (decltype(sd.P))(base + p.P);
+  sd.S = (decltype(sd.S))(base + p.S);
+  sd.st = (decltype(sd.st))(base + p.state);
+  sd.hist = (decltype(sd.hist))(base + p.hist);
+  sd.part = (decltype(sd.part))(base + p.part);
+  sd.n_active = (decltype(sd.n_active))(base + p.counter);
+  if (op != PID) {
+    std::vector<SysDev> h(1, sd);
+    fill_no(m, p, base, N, 1, op, h);
+    sd = h[0];
+  }
+  const SysDev* own = (const SysDev*)(base + p.sysdev);
+  HIPCHK(hipMemcpyAsync(base + p.sysdev, &sd, sizeof(SysDev), hipMemcpyHostToDevice, e->s));
+  KrylovLaunch KL{own, 1, N, e->d.m_max, e->s};
+  launch_init_state(KL, q.max_iter, q.rtol);
+  if (op != PID) {
+    HIPCHK(hipMemsetAsync(base + p.Hc, 0, (size_t)N * m->arch.width * p.MP * op_esize(op), e->s));
+    HIPCHK(hipMemsetAsync(base + p.Wh, 0, p.wh_bytes_per_sys, e->s));
+    NOLaunch NL = group_no(e, g, own, 1);
+    launch_no_setup(NL, (double*)(base + p.Gp));
+  }
+  launch_residual(KL, 0);
+  (void)n;
+  HIPCHK(hipGetLastError());
+  return FCGNO_OK;
+}
+
+fcgno_status upload_table(fcgno_engine* e, EngGroup& g, size_t where, const std::vector<int64_t>& ids) {
+  std::vector<SysDev> h;
+  h.reserve(ids.size());
+  for (int64_t id : ids) h.push_back(e->active.at(id).sd);
+  HIPCHK(hipMemcpyAsync(e->pool + g.off + where, h.data(), h.size() * sizeof(SysDev), hipMemcpyHostToDevice, e->s));
+  return FCGNO_OK;
+}
+
+}  // namespace
+
+extern "C" size_t fcgno_engine_request_bytes(const fcgno_model* m, const fcgno_engine_desc* d, int32_t n,
+                                             int32_t max_iter) {
+  if (!d || n < 1 || max_iter < 1 || d->m_max < 1 || d->m_max > MAXW) return 0;
+  if (d->op != PID && (!m || !arch_ok_for(m, n))) return 0;
+  return align256(request_bytes(m, d->op, d->m_max, n, max_iter));
+}
+
+extern "C" fcgno_status fcgno_engine_create(const fcgno_model* m, const fcgno_engine_desc* d, void* stream,
+                                            fcgno_engine** out) {
+  if (!d || !out) return fail(FCGNO_E_INVALID, "null argument");
+  if (d->op < 0 || d->op > PID) return fail(FCGNO_E_INVALID, "unknown op precision");
+  if (d->op != PID && !m) return fail(FCGNO_E_INVALID, "operator precision needs a model");
+  if (d->m_max < 1 || d->m_max > MAXW) return fail(FCGNO_E_INVALID, "m_max must be in 1..32");
+  if (d->max_slots < 1 || d->budget_bytes < 4096) return fail(FCGNO_E_INVALID, "need max_slots >= 1 and a budget");
+  fcgno_engine* e = new fcgno_engine();
+  e->m = m;
+  e->d = *d;
+  if (e->d.check_every <= 0) e->d.check_every = 8;
+  e->s = (hipStream_t)stream;
+  const size_t bytes = d->budget_bytes & ~(size_t)255;
+  if (hipMalloc((void**)&e->pool, bytes) != hipSuccess) {
+    delete e;
+    return fail(FCGNO_E_NOMEM, "cannot allocate the engine pool");
+  }
+  e->free_[0] = bytes;
+  if (hipHostMalloc((void**)&e->hflags, (size_t)d->max_slots * 3 * sizeof(int), 0) != hipSuccess ||
+      hipHostMalloc((void**)&e->htres, (size_t)d->max_slots * sizeof(double), 0) != hipSuccess) {
+    if (e->hflags) (void)hipHostFree(e->hflags);
+    (void)hipFree(e->pool);
+    delete e;
+    return fail(FCGNO_E_HIP, "hipHostMalloc failed");
+  }
+  *out = e;
+  return FCGNO_OK;
+}
+
+extern "C" fcgno_status fcgno_engine_submit(fcgno_engine* e, int32_t N, const double* k, const double* f, double* u,
+                                            double rtol, int32_t max_iter, int64_t* id_out) {
+  if (!e || !k || !f || !u || !id_out) return fail(FCGNO_E_INVALID, "null argument");
+  if (N < 1 || max_iter < 1 || !(rtol > 0.0) || !std::isfinite(rtol)) return fail(FCGNO_E_INVALID, "bad request");
+  if (e->d.op != PID && !arch_ok_for(e->m, N)) return fail(FCGNO_E_INVALID, "need 2*modes <= n");
+  EngReq q;
+  q.id = e->next_id++;
+  q.N = N;
+  q.max_iter = max_iter;
+  q.rtol = rtol;
+  q.k = k;
+  q.f = f;
+  q.u = u;
+  q.p = make_plan(e->d.op == PID ? nullptr : e->m, N, 1, e->d.m_max, max_iter, e->d.op, KIND_SOLVE);
+  q.bytes = q.p.total;
+  const size_t gb = group_bytes(e->d.op == PID ? nullptr : e->m, e->d.op, N, e->d.max_slots, nullptr);
+  if (align256(q.bytes) + align256(gb) > (e->d.budget_bytes & ~(size_t)255))
+    return fail(FCGNO_E_NOMEM, "request larger than the engine's HBM budget");
+  *id_out = q.id;
+  e->queue.push_back(q);
+  return FCGNO_OK;
+}
+
+extern "C" fcgno_status fcgno_engine_step(fcgno_engine* e, int32_t* n_active, int32_t* n_queued) {
+  if (!e) return fail(FCGNO_E_INVALID, "null engine");
+  // 1. admission: scan the queue in arrival order, admit what fits now
+  for (auto it = e->queue.begin(); it != e->queue.end();) {
+    if ((int)e->active.size() >= e->d.max_slots) break;
+    EngGroup* g = nullptr;
+    const bool had_group = e->groups.count(it->N) != 0;
+    if (group_open(e, it->N, &g) != FCGNO_OK) { ++it; continue; }
+    size_t off = 0;
+    if (!pool_alloc(e, it->bytes, &off)) {
+      if (!had_group && g->members.empty()) group_close(e, it->N);
+      ++it;
+      continue;
+    }
+    EngReq q = *it;
+    q.off = off;
+    it = e->queue.erase(it);
+    auto ins = e->active.emplace(q.id, q).first;
+    fcgno_status st = admit(e, ins->second, *g);
+    if (st != FCGNO_OK) return st;
+    g->members.push_back(q.id);
+    g->dirty = true;
+  }
+  // 2. advance every group by K iterations, then export the state summaries
+  const int K = e->d.check_every;
+  size_t ho = 0;
+  for (auto& kv : e->groups) {
+    EngGroup& g = kv.second;
+    const int G = (int)g.members.size();
+    if (G == 0) continue;
+    char* base = e->pool + g.off;
+    if (g.dirty) {
+      fcgno_status st = upload_table(e, g, g.table, g.members);
+      if (st != FCGNO_OK) return st;
+      g.dirty = false;
+    }
+    const SysDev* table = (const SysDev*)(base + g.table);
+    KrylovLaunch KL{table, G, g.N, e->d.m_max, e->s};
+    NOLaunch NL{};
+    if (e->d.op != PID) NL = group_no(e, g, table, G);
+    for (int i = 0; i < K; ++i) {
+      if (e->d.op != PID) launch_no_apply(NL);
+      launch_wdots(KL);
+      launch_dir(KL);
+      launch_update(KL);
+    }
+    launch_export(table, G, (int*)(base + g.flags), (double*)(base + g.tres), e->s);
+    g.hoff = ho;
+    HIPCHK(hipMemcpyAsync(e->hflags + 3 * ho, base + g.flags, (size_t)G * 3 * sizeof(int), hipMemcpyDeviceToHost,
+                          e->s));
+    ho += G;
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(e->s));
+  // 3. true residual of the requests that stopped, then release them
+  bool any = false;
+  std::map<int, std::vector<int64_t>> fin;
+  for (auto& kv : e->groups) {
+    EngGroup& g = kv.second;
+    for (size_t b = 0; b < g.members.size(); ++b)
+      if (e->hflags[3 * (g.hoff + b)] == 0) fin[kv.first].push_back(g.members[b]);
+  }
+  ho = 0;
+  for (auto& kv : fin) {
+    EngGroup& g = e->groups.at(kv.first);
+    char* base = e->pool + g.off;
+    const int F = (int)kv.second.size();
+    g.hoff = ho;
+    fcgno_status st = upload_table(e, g, g.ftable, kv.second);
+    if (st != FCGNO_OK) return st;
+    const SysDev* ft = (const SysDev*)(base + g.ftable);
+    KrylovLaunch KF{ft, F, g.N, e->d.m_max, e->s};
+    launch_residual(KF, 1);
+    launch_export(ft, F, (int*)(base + g.flags), (double*)(base + g.tres), e->s);
+    HIPCHK(hipMemcpyAsync(e->hflags + 3 * ho, base + g.flags, (size_t)F * 3 * sizeof(int), hipMemcpyDeviceToHost,
+                          e->s));
+    HIPCHK(hipMemcpyAsync(e->htres + ho, base + g.tres, (size_t)F * sizeof(double), hipMemcpyDeviceToHost, e->s));
+    ho += F;
+    any = true;
+  }
+  if (any) {
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(e->s));
+    for (auto& kv : fin) {
+      EngGroup& g = e->groups.at(kv.first);
+      for (size_t b = 0; b < kv.second.size(); ++b) {
+        const int64_t id = kv.second[b];
+        fcgno_engine_result r{};
+        r.id = id;
+        r.status = e->hflags[3 * (g.hoff + b) + 1];
+        r.iters = e->hflags[3 * (g.hoff + b) + 2];
+        r.true_rel_res = e->htres[g.hoff + b];
+        e->done.push_back(r);
+        EngReq& q = e->active.at(id);
+        pool_free(e, q.off, q.bytes);
+        e->active.erase(id);
+        g.members.erase(std::find(g.members.begin(), g.members.end(), id));
+        g.dirty = true;
+      }
+      if (g.members.empty()) group_close(e, kv.first);
+    }
+  }
+  if (n_active) *n_active = (int32_t)e->active.size();
+  if (n_queued) *n_queued = (int32_t)e->queue.size();
+  return FCGNO_OK;
+}
+
+extern "C" int32_t fcgno_engine_poll(fcgno_engine* e, fcgno_engine_result* out, int32_t max_results) {
+  if (!e || !out || max_results < 1) return 0;
+  const int32_t n = (int32_t)std::min<size_t>(e->done.size(), (size_t)max_results);
+  std::copy(e->done.begin(), e->done.begin() + n, out);
+  e->done.erase(e->done.begin(), e->done.begin() + n);
+  return n;
+}
+
+extern "C" void fcgno_engine_destroy(fcgno_engine* e) {
+  if (!e) return;
+  if (e->s) (void)hipStreamSynchronize(e->s);
+  else (void)hipDeviceSynchronize();
+  (void)hipHostFree(e->hflags);
+  (void)hipHostFree(e->htres);
+  (void)hipFree(e->pool);
+  delete e;
 }

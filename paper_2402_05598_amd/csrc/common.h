@@ -186,6 +186,8 @@ void launch_wdots(const KrylovLaunch& L);
 void launch_dir(const KrylovLaunch& L);
 void launch_update(const KrylovLaunch& L);
 void launch_record(const KrylovLaunch& L, int it, int m, double* rec_r, double* rec_e, const double* ustar);
+// flags[3b..3b+2] = {active, status, iters}, tres[b] = true relative residual
+void launch_export(const SysDev* sys, int nsys, int* flags, double* tres, hipStream_t s);
 
 struct NOLaunch {
   const SysDev* sys;

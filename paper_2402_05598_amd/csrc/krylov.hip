@@ -364,7 +364,22 @@ __global__ __launch_bounds__(256) void k_record(const SysDev* sys, int N, int it
   rec_e[o] = ustar[(size_t)blockIdx.y * n + p] - sd.u[p];
 }
 
+// Per-system summary for the host: {active, status, iters} and the true residual.
+__global__ __launch_bounds__(64) void k_export(const SysDev* sys, int nsys, int* flags, double* tres) {
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  if (b >= nsys) return;
+  const GLOBAL SysState* st = sys[b].st;
+  flags[3 * b] = st->active;
+  flags[3 * b + 1] = st->status;
+  flags[3 * b + 2] = st->iters;
+  tres[b] = st->tres;
+}
+
 // ---- launchers ------------------------------------------------------------
+
+void launch_export(const SysDev* sys, int nsys, int* flags, double* tres, hipStream_t s) {
+  hipLaunchKernelGGL(k_export, dim3((nsys + 63) / 64), dim3(64), 0, s, sys, nsys, flags, tres);
+}
 
 void launch_record(const KrylovLaunch& L, int it, int m, double* rec_r, double* rec_e, const double* ustar) {
   const size_t n = (size_t)L.N * L.N;
