@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--max-iter", type=int, default=0, help="default max(2N, 300)")
     p.add_argument("--rtol", type=float, default=1e-6)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--serve-requests", type=int, default=60,
+                   help="requests per serving run (0: skip the serving leg)")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 1 GiB device copy first (HBM counter calibration under rocprofv3)")
@@ -149,6 +151,78 @@ def time_solves(fc, torch, model, kd, fd, u0d, op, steps, warmup, args, prof_ker
         for name in prof_kernels:
             prof[name] = fc.profile_read(name)
     return total, lat, outs, us[-1], prof
+
+
+def serving(fc, torch, dev, model, n_req, logf):
+    """Serving leg: requests with grids uniform over {64,...,1024}^2 (k
+    contrast log-uniform in [10, 1e3], f ~ GRF, u0 ~ N(0, I)), BF16 operator,
+    tol 1e-6, through the continuous-batching engine.  A closed-loop run (all
+    requests at t = 0) measures the saturation rate mu; an open-loop run with
+    Poisson arrivals at 0.7 mu measures latency under load."""
+    import synth
+    sizes = [64, 128, 256, 512, 1024]
+    g = np.random.default_rng(4242)
+    grids = [int(sizes[i]) for i in g.integers(0, len(sizes), n_req)]
+    reqs = []
+    for i, N in enumerate(grids):
+        k, f, u0, _ = synth.system(4000 + i, N, (10.0, 1000.0))
+        reqs.append([torch.from_numpy(a).to(dev) for a in (k, f, u0)])
+    torch.cuda.synchronize()
+
+    def run(arrivals):
+        eng = fc.Engine(model, op="bf16", m_max=5, check_every=8, max_slots=64, budget_bytes=24 << 30)
+        us = [r[2].clone() for r in reqs]
+        torch.cuda.synchronize()
+        ids, t_sub, t_done, res = {}, {}, {}, {}
+        order = np.argsort(arrivals, kind="stable")
+        nxt = 0
+        t0 = time.perf_counter()
+        while len(res) < n_req:
+            now = time.perf_counter() - t0
+            while nxt < n_req and arrivals[order[nxt]] <= now:
+                i = int(order[nxt])
+                k, f, _ = reqs[i]
+                ids[eng.submit(k, f, us[i], rtol=1e-6, max_iter=max(2 * grids[i], 300))] = i
+                t_sub[i] = time.perf_counter() - t0
+                nxt += 1
+            active, queued = eng.step()
+            for r in eng.poll():
+                i = ids[r["id"]]
+                t_done[i] = time.perf_counter() - t0
+                res[i] = r
+            if active == 0 and queued == 0 and nxt < n_req:
+                time.sleep(max(0.0, arrivals[order[nxt]] - (time.perf_counter() - t0)))
+        total = time.perf_counter() - t0
+        eng.close()
+        lat = np.array([t_done[i] - t_sub[i] for i in range(n_req)]) * 1e3
+        conv = np.array([res[i]["status"] == 0 for i in range(n_req)])
+        return total, lat, conv, res
+
+    t_closed, lat_c, conv_c, res_c = run(np.zeros(n_req))
+    mu = n_req / t_closed
+    lam = 0.7 * mu
+    arr = np.cumsum(np.random.default_rng(4343).exponential(1.0 / lam, n_req))
+    arr -= arr[0]
+    t_open, lat_o, conv_o, _ = run(arr)
+    by_n = {}
+    for N in sizes:
+        it = [res_c[i]["iters"] for i in range(n_req) if grids[i] == N]
+        ok = [res_c[i]["status"] == 0 for i in range(n_req) if grids[i] == N]
+        if it:
+            by_n[str(N)] = {"requests": len(it), "converged": int(sum(ok)), "iters_median": float(np.median(it))}
+    log(f"serving: closed {t_closed:.2f}s mu={mu:.2f}/s; open-loop at {lam:.2f}/s: {t_open:.2f}s "
+        f"p50 {np.percentile(lat_o, 50):.0f} ms p99 {np.percentile(lat_o, 99):.0f} ms", logf)
+    return {"requests": n_req, "grids": sizes, "op": "bf16", "tol": 1e-6,
+            "closed_loop": {"seconds": round(t_closed, 3), "solves_per_sec": round(mu, 3),
+                            "converged_per_sec": round(float(conv_c.sum()) / t_closed, 3),
+                            "p50_ms": round(float(np.percentile(lat_c, 50)), 1),
+                            "p99_ms": round(float(np.percentile(lat_c, 99)), 1)},
+            "open_loop": {"arrival_rate_per_sec": round(lam, 3), "seconds": round(t_open, 3),
+                          "solves_per_sec": round(n_req / t_open, 3),
+                          "converged_per_sec": round(float(conv_o.sum()) / t_open, 3),
+                          "p50_ms": round(float(np.percentile(lat_o, 50)), 1),
+                          "p99_ms": round(float(np.percentile(lat_o, 99)), 1)},
+            "by_grid": by_n}
 
 
 def cpu_baseline(k, f, u0, blob, C, M, L, iters_needed, conv_frac, seconds, logf):
@@ -297,6 +371,10 @@ def main():
             d["iters_diff_vs_fp64_op"] = (Rr["iters"][-B:] - ref["iters"][-B:]).tolist()
         comparison[op] = d
 
+    serve = None
+    if args.serve_requests > 0:
+        serve = serving(fc, torch, dev, model, args.serve_requests, logf)
+
     cpu = None
     if not args.no_cpu_baseline:
         Rb = results.get("fp64", R)
@@ -320,6 +398,7 @@ def main():
         "comparison": comparison,
         "kernels": per_kernel,
         "training": train_info,
+        "serving": serve,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
