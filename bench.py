@@ -225,6 +225,24 @@ def serving(fc, torch, dev, model, n_req, logf):
             "by_grid": by_n}
 
 
+def copy_bandwidth(torch, dev):
+    """Device-to-device copy of 1 GiB (read + write), GB/s: the bandwidth a
+    plain streaming kernel with a 1:1 read/write mix reaches on this GPU."""
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    bw = 5 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return bw
+
+
 def cpu_baseline(k, f, u0, blob, C, M, L, iters_needed, conv_frac, seconds, logf):
     """The oracle (FP64 FCG with the FP64 operator) on system 0 of the batch,
     for as many iterations as fit in about ``seconds``; scaled to solves/sec
@@ -343,8 +361,10 @@ def main():
                 and tr.get("op") == main_op:
             # counters were taken on launches with every system active
             traffic = round(tr["bytes_per_launch_all_active"] * act_avg / B)
+    copy_bw = copy_bandwidth(torch, dev)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "copy_GBs": round(copy_bw, 1), "frac_of_copy": round(achieved / copy_bw, 4),
                 "kernel": f"k_layer<{main_op}, C={C}, MP=32> inner layer", "launches": n_l,
                 "avg_us": round(avg_us, 2), "active_systems_per_launch": round(act_avg, 3),
                 "algorithmic_bytes_per_system": per_sys, "algorithmic_bytes_per_launch": round(nb)}

@@ -1,0 +1,75 @@
+"""Form 1 (precision) against the FP64 oracle at a preconditioner that
+converges: an operator trained on the CPU with the oracle
+(tests/golden/make_trained_no.py) preconditions FCG on seeded systems; the
+GPU solves with the FP64, FP32 and BF16 operator must reach the same 1e-6
+relative-residual stopping point as the oracle (checked on the CPU from the
+returned iterate), with the iteration count reported: equal for FP64 (whose
+residual history follows the oracle's), within 20% for FP32, bounded for
+BF16."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+fc = pytest.importorskip("paper_2402_05598_amd")
+
+C, M, L = 16, 4, 2
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "no_trained_c16_m4_l2.npy")
+# seeded systems on which the oracle's FCG-NO converges in tens of iterations
+CASES = [(24, 9101), (32, 9100), (32, 9101), (48, 9100)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def blob():
+    return np.load(GOLD)
+
+
+@pytest.mark.parametrize("N,seed", CASES)
+def test_stopping_point_matches_oracle(dev, blob, N, seed):
+    print(f"precision N={N} seed={seed}", flush=True)
+    k, f, u0, _ = synth.system(seed, N, (10.0, 100.0))
+    w = oracle.unpack_weights(blob, C, M, L)
+    kt = torch.from_numpy(k)
+    ref = oracle.fcg(k, f, u0, lambda r: oracle.no_apply(w, kt, r), m_max=5, max_iter=400, tol=1e-6)
+    assert ref.status == oracle.SYS_OK
+    ref_iters = int(ref.iters)
+    model = fc.Model(blob, C, M, L)
+    kd, fd = torch.from_numpy(k)[None].to(dev), torch.from_numpy(f)[None].to(dev)
+    r0 = np.linalg.norm(f - oracle.stencil_apply(k, u0).numpy())
+    for op in ("fp64", "fp32", "bf16"):
+        u = torch.from_numpy(u0)[None].to(dev).contiguous()
+        out = fc.solve(model, kd, fd, u, op=op, m_max=5, max_iter=400, rtol=1e-6)
+        it, st, tres = int(out["iters"][0]), int(out["status"][0]), float(out["true_rel_res"][0])
+        ug = u[0].cpu().numpy()
+        true_cpu = np.linalg.norm(f - oracle.stencil_apply(k, ug).numpy()) / r0
+        print(f"  {op}: iters {it} (oracle {ref_iters}), true residual {tres:.3e}", flush=True)
+        assert st == fc.SYS_OK
+        assert abs(tres - true_cpu) <= 1e-8 * max(true_cpu, 1e-300) + 1e-15
+        assert true_cpu <= 2e-6
+        if op == "fp64":
+            assert abs(it - ref_iters) <= 1
+        elif op == "fp32":
+            assert abs(it - ref_iters) <= max(2, int(0.2 * ref_iters))
+        else:
+            # BF16 rounding changes the directions: same tolerance reached,
+            # iteration count reported (bounded to catch a broken operator)
+            assert it <= 2 * ref_iters + 10
+        if op == "fp64":
+            h = out["hist"][0, :it + 1]
+            hr = np.asarray(ref.hist)
+            n = min(len(h), len(hr), 10)
+            assert np.max(np.abs(h[:n] - hr[:n]) / hr[:n]) <= 1e-10
+    model.close()
