@@ -684,7 +684,7 @@ fcgno_status operator_backward(const fcgno_model* m, const Plan& p, char* base, 
   const int XS = (N + 63) / 64;
   for (int l = L - 1; l >= 0; --l) {
     // spectral adjoint of layer l from the row partials of dz_l
-    SpecArgs sa{sysdev, N, p.Sb, M, 0, XS, NL.tab.Eacc, NL.tab.E64, m->Rmix[op][l], m->WL0[op], nullptr, 0, 1};
+    SpecArgs sa{sysdev, N, p.Sb, M, 0, XS, B, NL.tab.Eacc, NL.tab.E64, m->Rmix[op][l], m->WL0[op], nullptr, 0, 1};
     launch_spec_fwd(NL, sa);
     BSpecArgs ba{};
     ba.N = N; ba.M = M; ba.B = B; ba.XS = XS;

@@ -217,6 +217,7 @@ struct NOLaunch {
 struct SpecArgs {
   const SysDev* sys;
   int N, S, M, layer0, XS;   // XS: x-chunks of 64 rows in the forward transform
+  int nsys;                  // systems in the table (the mixing kernel groups them)
   const void* Eacc;
   const double* E64;
   const void* R;     // [M][2M][C][C] complex, accumulate precision

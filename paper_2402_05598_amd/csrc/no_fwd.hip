@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) void k_spec_fwd(SpecArgs a) {
   for (int q = t; q < twoM * SX; q += 256) {
     const int kx = q / SX, xl = q - kx * SX;
     const int kv = kx < M ? kx : N - twoM + kx;
-    const int idx = (int)(((long long)kv * (x0 + xl)) % N);
+    const int idx = (int)(((unsigned)kv * (unsigned)(x0 + xl)) % (unsigned)N);   // N^2 < 2^32
     Er_[kx][xl] = E[2 * idx];
     Ei_[kx][xl] = -E[2 * idx + 1];
   }
@@ -401,11 +401,14 @@ __global__ __launch_bounds__(256) void k_spec_mix(SpecArgs a) {
 // x-direction synthesis for SR rows: H[x][o][ky] = sum_a W^[ky][o][a]
 // e^{+2 pi i kx_a x/N}, staged in LDS as complete rows Hc[x][o][0..MP) and
 // written out contiguously.
-template <int PREC> struct SynthRows { static constexpr int SR = 16; };
+// One thread per (o, ky) pair: the block has C*M threads rounded up to whole
+// waves (at most 512).
+template <int PREC> struct SynthRows { static constexpr int SR = 8; };
 template <> struct SynthRows<P64> { static constexpr int SR = 8; };
+__host__ __device__ inline int synth_threads(int C, int M) { return ((C * M + 63) / 64) * 64; }
 
 template <int PREC, int C, int MP>
-__global__ __launch_bounds__(256) void k_spec_inv(SpecArgs a) {
+__global__ __launch_bounds__(512) void k_spec_inv(SpecArgs a) {
   using M_ = Mf<PREC>;
   using in_t = typename M_::in_t;
   using acc_t = typename M_::acc_t;
@@ -418,18 +421,18 @@ __global__ __launch_bounds__(256) void k_spec_inv(SpecArgs a) {
   const int x0 = blockIdx.x * SR;
   const int nx = min(SR, N - x0);
   const acc_t* E = (const acc_t*)a.Eacc;
-  const int t = threadIdx.x;
-  for (int q = t; q < SR * MP; q += 256) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int q = t; q < SR * MP; q += nt) {
     const int xl = q / MP, kx = q - xl * MP;
     const int kv = kx < M ? kx : N - twoM + kx;
-    const int idx = (int)(((long long)kv * (x0 + xl)) % N);
+    const int idx = (int)(((unsigned)kv * (unsigned)(x0 + xl)) % (unsigned)N);   // N^2 < 2^32
     Er_[xl][kx] = kx < twoM ? E[2 * idx] : (acc_t)0;
     Ei_[xl][kx] = kx < twoM ? E[2 * idx + 1] : (acc_t)0;
   }
-  for (int q = t; q < SR * C * MP; q += 256) tile[q] = M_::cvt((acc_t)0);
+  for (int q = t; q < SR * C * MP; q += nt) tile[q] = M_::cvt((acc_t)0);
   __syncthreads();
   const double scale = 1.0 / ((double)N * (double)N);
-  for (int q = t; q < C * M; q += 256) {
+  for (int q = t; q < C * M; q += nt) {
     const int o = q / M, ky = q - o * M;
     const acc_t* Wh = (const acc_t*)sd.Wh + ((size_t)ky * C + o) * MP * 2;   // zero past 2M
     acc_t wr[MP], wi[MP];
@@ -455,7 +458,7 @@ __global__ __launch_bounds__(256) void k_spec_inv(SpecArgs a) {
   const int nbytes = nx * C * MP * (int)sizeof(in_t);
   const uint4* src = (const uint4*)tile;
   uint4* dst = (uint4*)((char*)sd.Hc + (size_t)x0 * C * MP * sizeof(in_t));
-  for (int q = t; q < nbytes / 16; q += 256) dst[q] = src[q];
+  for (int q = t; q < nbytes / 16; q += nt) dst[q] = src[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -814,9 +817,11 @@ template <int PREC, int C>
 static void spec_inv_pc(const NOLaunch& L, const SpecArgs& sa) {
   constexpr int SR = SynthRows<PREC>::SR;
   if (L.MP == 16)
-    hipLaunchKernelGGL((k_spec_inv<PREC, C, 16>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(256), 0, L.stream, sa);
+    hipLaunchKernelGGL((k_spec_inv<PREC, C, 16>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(synth_threads(C, L.M)), 0,
+                       L.stream, sa);
   else
-    hipLaunchKernelGGL((k_spec_inv<PREC, C, 32>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(256), 0, L.stream, sa);
+    hipLaunchKernelGGL((k_spec_inv<PREC, C, 32>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(synth_threads(C, L.M)), 0,
+                       L.stream, sa);
 }
 
 void launch_spec_fwd(const NOLaunch& L, const SpecArgs& a) {
@@ -839,7 +844,7 @@ static void apply_pc(const NOLaunch& L) {
   }
   for (int l = 0; l < L.L; ++l) {
     const int XS = (L.N + SX - 1) / SX;
-    SpecArgs sa{L.sys, L.N, L.S, L.M, l == 0 ? 1 : 0, XS, L.tab.Eacc, L.tab.E64, L.Rmix[l], L.WL0,
+    SpecArgs sa{L.sys, L.N, L.S, L.M, l == 0 ? 1 : 0, XS, L.nsys, L.tab.Eacc, L.tab.E64, L.Rmix[l], L.WL0,
                 L.vsave ? (char*)L.vsave + L.vs_layer * l * L.acc_bytes : nullptr, L.vs_sys, 0};
     {
       ProfScope ps(PK_SPECTRAL, L.stream);
@@ -847,9 +852,11 @@ static void apply_pc(const NOLaunch& L) {
       hipLaunchKernelGGL((k_spec_fwd<PREC, C>), dim3(L.M, XS, L.nsys), dim3(256), 0, L.stream, sa);
       hipLaunchKernelGGL((k_spec_mix<PREC, C>), dim3(L.M, L.nsys), dim3(256), 0, L.stream, sa);
       if (L.MP == 16)
-        hipLaunchKernelGGL((k_spec_inv<PREC, C, 16>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(256), 0, L.stream, sa);
+        hipLaunchKernelGGL((k_spec_inv<PREC, C, 16>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(synth_threads(C, L.M)), 0,
+                       L.stream, sa);
       else
-        hipLaunchKernelGGL((k_spec_inv<PREC, C, 32>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(256), 0, L.stream, sa);
+        hipLaunchKernelGGL((k_spec_inv<PREC, C, 32>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(synth_threads(C, L.M)), 0,
+                       L.stream, sa);
     }
     // inference updates the activation in place (slot 0); training keeps
     // v_{l+1} in slot l so the backward pass can read every layer's input
