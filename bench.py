@@ -44,8 +44,10 @@ def parse():
     p.add_argument("--max-iter", type=int, default=0, help="default max(2N, 300)")
     p.add_argument("--rtol", type=float, default=1e-6)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--serve-requests", type=int, default=60,
-                   help="requests per serving run (0: skip the serving leg)")
+    p.add_argument("--serve-requests", type=int, default=0,
+                   help="requests per serving run through the continuous-batching engine (0: no serving leg; "
+                        "it runs the same layer kernel, so it is kept out of the default run whose kernel "
+                        "statistics the roofline quotes)")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 1 GiB device copy first (HBM counter calibration under rocprofv3)")
