@@ -51,6 +51,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 1 GiB device copy first (HBM counter calibration under rocprofv3)")
+    p.add_argument("--ablation", action="store_true",
+                   help="also train with the Euclidean loss and with random-residual samples (Sec. 3.3) "
+                        "and compare FCG iteration counts")
+    p.add_argument("--ablation-steps", type=int, default=6000)
     p.add_argument("--log", default=None, help="progress log file (default: stderr)")
     return p.parse_args()
 
@@ -78,10 +82,12 @@ def layer_bytes_per_launch(N, B, C, M, esize, asize, S):
     return B * (N * N * per_point + N * per_row)
 
 
-def train_operator(fc, torch, dev, C, M, L, steps, logf):
+def train_operator(fc, torch, dev, C, M, L, steps, logf, loss="energy", sampling="krylov"):
     """Energy-norm training on conjugate-gradient Krylov samples of 64 x 64
     systems (AdamW, lr 3e-4 halved every quarter of the run, weight decay
-    1e-2).  Returns the model and a summary."""
+    1e-2).  loss="l2" and sampling="random" give the two alternatives of the
+    ablation in Sec. 3.3 (random samples: u ~ N(0, I), f ~ GRF per sample,
+    r = f - A u, e = A^-1 f - u).  Returns the model and a summary."""
     import synth
     Nt, Bs, m_iter, mb = 64, 256, 400, 64
     blob = synth.init_weights(3, C, M, L)
@@ -92,9 +98,19 @@ def train_operator(fc, torch, dev, C, M, L, steps, logf):
     k, f, u0, _ = synth.batch(3, Bs, Nt, (10.0, 1000.0))
     kd, fd, ud = [torch.from_numpy(a).to(dev) for a in (k, f, u0)]
     t0 = time.perf_counter()
-    r, e = fc.krylov_samples(kd, fd, ud, m_iter=m_iter)
+    if sampling == "krylov":
+        r, e = fc.krylov_samples(kd, fd, ud, m_iter=m_iter)
+    else:
+        per = 32
+        g = synth.rng(77)
+        fs = np.stack([synth.rhs_field(g, Nt) for _ in range(Bs * per)])
+        us = g.standard_normal((Bs * per, Nt, Nt))
+        kr = kd.repeat_interleave(per, dim=0).contiguous()
+        rr, ee = fc.residual_samples(kr, torch.from_numpy(fs).to(dev), torch.from_numpy(us).to(dev))
+        r, e = rr.view(Bs, per, Nt, Nt), ee.view(Bs, per, Nt, Nt)
+        m_iter = per
     torch.cuda.synchronize()
-    log(f"krylov samples {tuple(r.shape)} in {time.perf_counter() - t0:.2f}s", logf)
+    log(f"{sampling} samples {tuple(r.shape)} in {time.perf_counter() - t0:.2f}s", logf)
     lr = 3e-4
     opt = fc.Optim(model, lr=lr, weight_decay=1e-2)
     ws = fc.train_workspace(model, Nt, mb, "fp32", dev)
@@ -110,17 +126,50 @@ def train_operator(fc, torch, dev, C, M, L, steps, logf):
             opt.set_lr(lr)
         si, ii = sys_i[s], it_i[s]
         want = s % 200 == 0 or s >= steps - 50
-        loss = fc.train_step(model, opt, kd[si], r[si, ii], e[si, ii], op="fp32", workspace=ws, return_loss=want)
+        val = fc.train_step(model, opt, kd[si], r[si, ii], e[si, ii], op="fp32", workspace=ws, return_loss=want,
+                            loss=loss)
         if want:
-            losses.append(loss)
+            losses.append(val)
         if s % 2000 == 0:
-            log(f"train step {s}: loss {loss:.4f} ({time.perf_counter() - t0:.1f}s)", logf)
+            log(f"train step {s}: {loss} loss {val:.4f} ({time.perf_counter() - t0:.1f}s)", logf)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     opt.close()
-    return model, {"grid": Nt, "systems": Bs, "cg_iterations_sampled": m_iter, "batch": mb, "steps": steps,
+    return model, {"grid": Nt, "systems": Bs, "sampling": sampling, "loss": loss,
+                   "samples_per_system": m_iter, "batch": mb, "steps": steps,
                    "seconds": round(dt, 2), "loss_first": round(losses[0], 4),
                    "loss_last50": round(float(np.mean(losses[-50:])), 4)}
+
+
+def ablation(fc, torch, dev, C, M, L, steps, logf):
+    """Sec. 3.3: the energy-norm loss against the Euclidean loss, and Krylov
+    samples against random residuals; FCG (m = 5, FP32 operator, tol 1e-6)
+    iteration counts on 16 held-out systems per grid, next to CG."""
+    import synth
+    out = {}
+    tests = {}
+    for N in (64, 128):
+        k, f, u0, _ = synth.batch(5, 16, N, (10.0, 1000.0))
+        tests[N] = [torch.from_numpy(a).to(dev) for a in (k, f, u0)]
+
+    def evaluate(model, op):
+        res = {}
+        for N, (kd, fd, ud) in tests.items():
+            u = ud.clone()
+            o = fc.solve(model, kd, fd, u, op=op, m_max=5, max_iter=1000, rtol=1e-6, hist=False)
+            ok = o["status"] == 0
+            res[str(N)] = {"converged": int(ok.sum()), "of": int(ok.size),
+                           "iters_median": float(np.median(o["iters"])),
+                           "iters_median_converged": float(np.median(o["iters"][ok])) if ok.any() else None}
+        return res
+    out["cg"] = evaluate(None, "identity")
+    for name, loss, sampling in (("energy_krylov", "energy", "krylov"), ("l2_krylov", "l2", "krylov"),
+                                 ("energy_random", "energy", "random")):
+        model, info = train_operator(fc, torch, dev, C, M, L, steps, logf, loss=loss, sampling=sampling)
+        out[name] = {"training": info, "fcg": evaluate(model, "fp32")}
+        log(f"ablation {name}: {out[name]['fcg']}", logf)
+        model.close()
+    return out
 
 
 def time_solves(fc, torch, model, kd, fd, u0d, op, steps, warmup, args, prof_kernels=None):
@@ -393,6 +442,10 @@ def main():
             d["iters_diff_vs_fp64_op"] = (Rr["iters"][-B:] - ref["iters"][-B:]).tolist()
         comparison[op] = d
 
+    abl = None
+    if args.ablation:
+        abl = ablation(fc, torch, dev, C, M, L, args.ablation_steps, logf)
+
     serve = None
     if args.serve_requests > 0:
         serve = serving(fc, torch, dev, model, args.serve_requests, logf)
@@ -421,6 +474,7 @@ def main():
         "kernels": per_kernel,
         "training": train_info,
         "serving": serve,
+        "ablation": abl,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -71,6 +71,13 @@ enum {
     FCGNO_OP_IDENTITY = 3,  /* B = I: FCG is then conjugate gradients (Fig. 2a) */
 };
 
+/* training loss: the energy-norm (Notay) loss of Sec. 2.4, or the Euclidean
+ * loss the ablation of Sec. 3.3 compares it with */
+enum {
+    FCGNO_LOSS_ENERGY = 0,  /* ||w - e||_A / ||e||_A */
+    FCGNO_LOSS_L2 = 1,      /* ||w - e||_2 / ||e||_2 */
+};
+
 typedef struct {
     int32_t layers;       /* L >= 1 */
     int32_t width;        /* C in {16, 32} */
@@ -178,6 +185,16 @@ fcgno_status fcgno_krylov_samples(int32_t n, int32_t batch, int32_t m_iter, int3
                                   const double* k, const double* f, const double* u0,
                                   double* r_out, double* e_out, void* ws, size_t ws_bytes, void* stream);
 
+/* Residuals from random right-hand sides (the alternative sampling of the
+ * ablation in Sec. 3.3): for device [batch] triples (k, f, u), r_out = f - A u
+ * and e_out = A^-1 f - u (device [batch][N][N] each), A^-1 f by conjugate
+ * gradients to 1e-13 from u (at most max_iter iterations).  Workspace as for
+ * fcgno_krylov_samples; returns FCGNO_NOT_CONVERGED if some A^-1 f missed
+ * 1e-13 (the samples are still written); synchronises the stream. */
+fcgno_status fcgno_residual_samples(int32_t n, int32_t batch, int32_t max_iter, const double* k,
+                                    const double* f, const double* u, double* r_out, double* e_out,
+                                    void* ws, size_t ws_bytes, void* stream);
+
 /* Workspace of fcgno_op_forward / fcgno_op_backward / fcgno_train_step. */
 size_t fcgno_train_workspace_bytes(const fcgno_model* m, int32_t n, int32_t batch, int32_t op);
 
@@ -201,6 +218,11 @@ size_t fcgno_energy_loss_workspace_bytes(int32_t n, int32_t batch);
 fcgno_status fcgno_energy_loss(int32_t n, int32_t batch, const double* k, const double* w,
                                const double* e, double* loss_dev, double* grad_w,
                                void* ws, size_t ws_bytes, void* stream);
+/* The same for either loss (FCGNO_LOSS_*); the Euclidean gradient is
+ * (w_b - e_b) / (batch ||w_b - e_b||_2 ||e_b||_2).  Same workspace. */
+fcgno_status fcgno_loss(int32_t loss_kind, int32_t n, int32_t batch, const double* k, const double* w,
+                        const double* e, double* loss_dev, double* grad_w, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /* One step: forward, loss on (r, e) pairs (device [batch][N][N] each),
  * backward, AdamW update of the model.  loss_host (nullable) receives the
@@ -208,6 +230,11 @@ fcgno_status fcgno_energy_loss(int32_t n, int32_t batch, const double* k, const 
 fcgno_status fcgno_train_step(fcgno_model* m, fcgno_optim* opt, int32_t n, int32_t batch, int32_t op,
                               const double* k, const double* r, const double* e, double* loss_host,
                               void* ws, size_t ws_bytes, void* stream);
+/* The same step with the loss chosen (FCGNO_LOSS_*); fcgno_train_step is
+ * this with FCGNO_LOSS_ENERGY. */
+fcgno_status fcgno_train_step_loss(fcgno_model* m, fcgno_optim* opt, int32_t n, int32_t batch, int32_t op,
+                                   int32_t loss_kind, const double* k, const double* r, const double* e,
+                                   double* loss_host, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Serving engine: continuous batching of solves (one system per request, any */

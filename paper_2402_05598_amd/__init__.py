@@ -5,4 +5,4 @@ from ._binding import (OP, SYS_BREAKDOWN, SYS_NONFINITE, SYS_NOT_CONVERGED, SYS_
                        FcgnoError, Model, lib, precond_apply, solve, solve_workspace_bytes,
                        weight_count, profile_enable, profile_reset, profile_read, PROFILE_KERNELS,
                        Optim, train_workspace, op_forward, op_backward, energy_loss, train_step,
-                       OperatorFunction, krylov_samples, Engine)
+                       OperatorFunction, krylov_samples, residual_samples, Engine, LOSS)

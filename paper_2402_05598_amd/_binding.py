@@ -95,6 +95,13 @@ def lib():
     L.fcgno_krylov_samples_workspace_bytes.restype = c_size_t
     L.fcgno_krylov_samples.argtypes = [c_int32, c_int32, c_int32, c_int32, vp, vp, vp, vp, vp, vp, c_size_t, vp]
     L.fcgno_krylov_samples.restype = c_int32
+    L.fcgno_residual_samples.argtypes = [c_int32, c_int32, c_int32, vp, vp, vp, vp, vp, vp, c_size_t, vp]
+    L.fcgno_residual_samples.restype = c_int32
+    L.fcgno_loss.argtypes = [c_int32, c_int32, c_int32, vp, vp, vp, vp, vp, vp, c_size_t, vp]
+    L.fcgno_loss.restype = c_int32
+    L.fcgno_train_step_loss.argtypes = [vp, vp, c_int32, c_int32, c_int32, c_int32, vp, vp, vp, POINTER(c_double),
+                                        vp, c_size_t, vp]
+    L.fcgno_train_step_loss.restype = c_int32
     L.fcgno_engine_request_bytes.argtypes = [vp, POINTER(EngineDesc), c_int32, c_int32]
     L.fcgno_engine_request_bytes.restype = c_size_t
     L.fcgno_engine_create.argtypes = [vp, POINTER(EngineDesc), vp, POINTER(vp)]
@@ -331,30 +338,51 @@ def op_backward(model, k, r, grad_w, ws, op="fp64", stream=None):
     return g
 
 
-def energy_loss(k, w, e, grad=True, stream=None):
-    """Per-system ||w-e||_A/||e||_A and (optionally) the gradient of their mean."""
+LOSS = {"energy": 0, "l2": 1}
+
+
+def energy_loss(k, w, e, grad=True, stream=None, kind="energy"):
+    """Per-system ||w-e||/||e|| in the energy norm (or the Euclidean norm with
+    kind="l2") and (optionally) the gradient of their mean."""
     B, N = w.shape[0], w.shape[-1]
     nbytes = lib().fcgno_energy_loss_workspace_bytes(N, B)
     ws = torch.empty(int(nbytes), dtype=torch.uint8, device=w.device)
     loss = torch.empty(B, dtype=torch.float64, device=w.device)
     g = torch.empty_like(w) if grad else None
-    _check(lib().fcgno_energy_loss(N, B, _dev_f64(k, "k"), _dev_f64(w, "w"), _dev_f64(e, "e"),
-                                   _dev_f64(loss, "loss"), _dev_f64(g, "grad") if grad else None,
-                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
-           "fcgno_energy_loss")
+    _check(lib().fcgno_loss(LOSS[kind], N, B, _dev_f64(k, "k"), _dev_f64(w, "w"), _dev_f64(e, "e"),
+                            _dev_f64(loss, "loss"), _dev_f64(g, "grad") if grad else None,
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "fcgno_loss")
     return loss, g
 
 
-def train_step(model, opt, k, r, e, op="fp32", workspace=None, stream=None, return_loss=True):
-    """One AdamW step on the energy-norm loss; returns the batch-mean loss
-    (which synchronises the stream), or None with ``return_loss=False``."""
+def train_step(model, opt, k, r, e, op="fp32", workspace=None, stream=None, return_loss=True, loss="energy"):
+    """One AdamW step on the energy-norm loss (or loss="l2"); returns the
+    batch-mean loss (which synchronises the stream), or None with
+    ``return_loss=False``."""
     B, N = r.shape[0], r.shape[-1]
     ws = workspace if workspace is not None else train_workspace(model, N, B, op, r.device)
     out = c_double(0.0)
-    _check(lib().fcgno_train_step(model.handle, opt.handle, N, B, OP[op], _dev_f64(k, "k"), _dev_f64(r, "r"),
-                                  _dev_f64(e, "e"), ctypes.byref(out) if return_loss else None,
-                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "fcgno_train_step")
+    _check(lib().fcgno_train_step_loss(model.handle, opt.handle, N, B, OP[op], LOSS[loss], _dev_f64(k, "k"),
+                                       _dev_f64(r, "r"), _dev_f64(e, "e"),
+                                       ctypes.byref(out) if return_loss else None,
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+           "fcgno_train_step_loss")
     return float(out.value) if return_loss else None
+
+
+def residual_samples(k, f, u, max_iter=None, stream=None):
+    """(f - A u, A^-1 f - u) for a batch of random right-hand sides and points;
+    returns two device tensors [B][N][N]."""
+    B, N = f.shape[0], f.shape[-1]
+    max_iter = max_iter or max(20 * N, 2000)
+    nbytes = lib().fcgno_krylov_samples_workspace_bytes(N, B, max_iter)
+    ws = torch.empty(int(nbytes), dtype=torch.uint8, device=f.device)
+    r = torch.empty((B, N, N), dtype=torch.float64, device=f.device)
+    e = torch.empty_like(r)
+    _check(lib().fcgno_residual_samples(N, B, max_iter, _dev_f64(k, "k"), _dev_f64(f, "f"), _dev_f64(u, "u"),
+                                        _dev_f64(r, "r"), _dev_f64(e, "e"), ctypes.c_void_p(ws.data_ptr()),
+                                        ws.numel(), _stream(stream)), "fcgno_residual_samples")
+    return r, e
 
 
 def krylov_samples(k, f, u0, m_iter=100, max_iter=None, stream=None):

@@ -553,6 +553,50 @@ extern "C" fcgno_status fcgno_krylov_samples(int32_t N, int32_t B, int32_t m_ite
   return r1;
 }
 
+extern "C" fcgno_status fcgno_residual_samples(int32_t N, int32_t B, int32_t max_iter, const double* k,
+                                               const double* f, const double* u, double* r_out, double* e_out,
+                                               void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || B < 1 || max_iter < 1 || !k || !f || !u || !r_out || !e_out || !ws)
+    return fail(FCGNO_E_INVALID, "invalid argument");
+  if (ws_bytes < fcgno_krylov_samples_workspace_bytes(N, B, max_iter))
+    return fail(FCGNO_E_NOMEM, "workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n = (size_t)N * N;
+  char* base = (char*)ws;
+  const Plan p = make_plan(nullptr, N, B, 1, max_iter, PID, KIND_SOLVE);
+  double* ustar = (double*)(base + p.total);
+  std::vector<int32_t> it(B), st(B);
+  // A^-1 f by conjugate gradients to a tight tolerance, starting from u
+  HIPCHK(hipMemcpyAsync(ustar, u, (size_t)B * n * 8, hipMemcpyDeviceToDevice, s));
+  fcgno_solve_desc d1{N, B, 1, max_iter, 1e-13, PID, 0};
+  fcgno_status r1 = solve_impl(nullptr, &d1, k, f, ustar, nullptr, it.data(), st.data(), nullptr, nullptr, ws,
+                               p.total, stream, nullptr);
+  if (r1 < 0) return r1;
+  // r = f - A u into r_out, then e = A^-1 f - u (state and partials reused from the plan)
+  std::vector<SysDev> h(B);
+  for (int b = 0; b < B; ++b) {
+    SysDev& sd = h[b];
+    std::memset(&sd, 0, sizeof(SysDev));
+    sd.k = (decltype(sd.k))(k + (size_t)b * (N + 2) * (N + 2));
+    sd.f = (decltype(sd.f))(f + (size_t)b * n);
+    sd.u = (decltype(sd.u))(const_cast<double*>(u) + (size_t)b * n);
+    sd.r = (decltype(sd.r))(r_out + (size_t)b * n);
+    sd.st = (decltype(sd.st))((SysState*)(base + p.state) + b);
+    // the initial-residual kernels also write the history's first entry
+    sd.hist = (decltype(sd.hist))((double*)(base + p.hist) + (size_t)b * (max_iter + 1));
+    sd.part = (decltype(sd.part))((double*)(base + p.part) + (size_t)b * p.n_part_blocks * NQ);
+    sd.n_active = (decltype(sd.n_active))(base + p.counter);
+  }
+  HIPCHK(hipMemcpyAsync(base + p.sysdev, h.data(), B * sizeof(SysDev), hipMemcpyHostToDevice, s));
+  KrylovLaunch KL{(const SysDev*)(base + p.sysdev), B, N, 1, s};
+  launch_init_state(KL, 1, 1.0);
+  launch_residual(KL, 0);
+  launch_record(KL, 0, 1, r_out, e_out, ustar);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return r1;
+}
+
 // ---------------------------------------------------------------------------
 // Operator application (and the training forward, which also saves z and V^)
 // ---------------------------------------------------------------------------
@@ -812,9 +856,10 @@ extern "C" size_t fcgno_energy_loss_workspace_bytes(int32_t N, int32_t B) {
   return loss_plan(N, B).total;
 }
 
-extern "C" fcgno_status fcgno_energy_loss(int32_t N, int32_t B, const double* k, const double* w, const double* e,
-                                          double* loss_dev, double* grad_w, void* ws, size_t ws_bytes,
-                                          void* stream) {
+extern "C" fcgno_status fcgno_loss(int32_t kind, int32_t N, int32_t B, const double* k, const double* w,
+                                   const double* e, double* loss_dev, double* grad_w, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  if (kind != FCGNO_LOSS_ENERGY && kind != FCGNO_LOSS_L2) return fail(FCGNO_E_INVALID, "unknown loss");
   if (N < 1 || B < 1 || !k || !w || !e || !loss_dev || !ws) return fail(FCGNO_E_INVALID, "invalid argument");
   const LossPlan lp = loss_plan(N, B);
   if (ws_bytes < lp.total) return fail(FCGNO_E_NOMEM, "workspace too small");
@@ -823,16 +868,23 @@ extern "C" fcgno_status fcgno_energy_loss(int32_t N, int32_t B, const double* k,
   hipStream_t s = (hipStream_t)stream;
   double* gwbuf = grad_w ? grad_w : (double*)(base + lp.gw);
   LossArgs la{N, B, lp.nb, k, w, e, (double*)(base + lp.dvec), gwbuf, (double*)(base + lp.part), loss_dev,
-              (double*)(base + lp.gscale)};
+              (double*)(base + lp.gscale), kind};
   launch_loss(la, s);
   if (grad_w) launch_scale_rows(grad_w, (const double*)(base + lp.gscale), B, (size_t)N * N, s);
   HIPCHK(hipGetLastError());
   return FCGNO_OK;
 }
 
-extern "C" fcgno_status fcgno_train_step(fcgno_model* m, fcgno_optim* opt, int32_t N, int32_t B, int32_t op,
-                                         const double* k, const double* r, const double* e, double* loss_host,
-                                         void* ws, size_t ws_bytes, void* stream) {
+extern "C" fcgno_status fcgno_energy_loss(int32_t N, int32_t B, const double* k, const double* w, const double* e,
+                                          double* loss_dev, double* grad_w, void* ws, size_t ws_bytes,
+                                          void* stream) {
+  return fcgno_loss(FCGNO_LOSS_ENERGY, N, B, k, w, e, loss_dev, grad_w, ws, ws_bytes, stream);
+}
+
+extern "C" fcgno_status fcgno_train_step_loss(fcgno_model* m, fcgno_optim* opt, int32_t N, int32_t B, int32_t op,
+                                              int32_t loss_kind, const double* k, const double* r, const double* e,
+                                              double* loss_host, void* ws, size_t ws_bytes, void* stream) {
+  if (loss_kind != FCGNO_LOSS_ENERGY && loss_kind != FCGNO_LOSS_L2) return fail(FCGNO_E_INVALID, "unknown loss");
   fcgno_status cs = check_train(m, N, B, op);
   if (cs != FCGNO_OK) return cs;
   if (!opt || !k || !r || !e || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
@@ -846,7 +898,7 @@ extern "C" fcgno_status fcgno_train_step(fcgno_model* m, fcgno_optim* opt, int32
   fcgno_status fs = operator_forward(m, p, base, N, B, op, k, r, w, true, s);
   if (fs != FCGNO_OK) return fs;
   LossArgs la{N, B, p.loss_nb, k, w, e, (double*)(base + p.dvec), (double*)(base + p.gw),
-              (double*)(base + p.lpart), (double*)(base + p.loss), (double*)(base + p.gscale)};
+              (double*)(base + p.lpart), (double*)(base + p.loss), (double*)(base + p.gscale), loss_kind};
   launch_loss(la, s);
   double* grad = (double*)(base + p.grad);
   fs = operator_backward(m, p, base, N, B, op, k, r, (const double*)(base + p.gw),
@@ -866,6 +918,12 @@ extern "C" fcgno_status fcgno_train_step(fcgno_model* m, fcgno_optim* opt, int32
     *loss_host = sum / B;
   }
   return FCGNO_OK;
+}
+
+extern "C" fcgno_status fcgno_train_step(fcgno_model* m, fcgno_optim* opt, int32_t N, int32_t B, int32_t op,
+                                         const double* k, const double* r, const double* e, double* loss_host,
+                                         void* ws, size_t ws_bytes, void* stream) {
+  return fcgno_train_step_loss(m, opt, N, B, op, FCGNO_LOSS_ENERGY, k, r, e, loss_host, ws, ws_bytes, stream);
 }
 
 extern "C" const char* fcgno_last_error(void) { return g_err.c_str(); }
@@ -914,6 +972,7 @@ struct EngGroup {
   std::vector<int64_t> members;
   bool dirty = true;
   size_t hoff = 0;           // this step's range in the engine's pinned export buffers
+  hipStream_t s = nullptr;   // the engine lane this group's work runs on
 };
 
 }  // namespace
@@ -931,6 +990,12 @@ struct fcgno_engine {
   int64_t next_id = 1;
   int* hflags = nullptr;     // pinned host copies of the exported state, max_slots entries
   double* htres = nullptr;
+  // Groups of different N run on separate streams (default priority), so a
+  // large group's bandwidth-bound launches and a small group's latency-bound
+  // ones overlap on the device; every step first waits for the caller's stream.
+  std::vector<hipStream_t> lanes;
+  hipEvent_t ready = nullptr;
+  int next_lane = 0;
 };
 
 namespace {
@@ -1017,7 +1082,7 @@ NOLaunch group_no(const fcgno_engine* e, const EngGroup& g, const SysDev* table,
   L.WL0 = m->WL0[op];
   L.WL = dev_WL(m);
   L.bL = dev_bL(m);
-  L.stream = e->s;
+  L.stream = g.s;
   L.op_bytes = op_esize(op);
   L.acc_bytes = acc_esize(op);
   return L;
@@ -1031,6 +1096,7 @@ fcgno_status group_open(fcgno_engine* e, int N, EngGroup** out) {
   }
   EngGroup g;
   g.N = N;
+  g.s = e->lanes[e->next_lane];
   g.bytes = group_bytes(e->d.op == PID ? nullptr : e->m, e->d.op, N, e->d.max_slots, &g);
   if (!pool_alloc(e, g.bytes, &g.off)) return FCGNO_E_NOMEM;
   if (e->d.op != PID) {
@@ -1038,6 +1104,7 @@ fcgno_status group_open(fcgno_engine* e, int N, EngGroup** out) {
     char* base = e->pool + g.off;
     launch_tables(NL, (double*)(base + g.E64), base + g.Eacc, base + g.T, base + g.TT);
   }
+  e->next_lane = (e->next_lane + 1) % (int)e->lanes.size();
   auto res = e->groups.emplace(N, g);
   *out = &res.first->second;
   return FCGNO_OK;
@@ -1076,12 +1143,12 @@ fcgno_status admit(fcgno_engine* e, EngReq& q, EngGroup& g) {
     sd = h[0];
   }
   const SysDev* own = (const SysDev*)(base + p.sysdev);
-  HIPCHK(hipMemcpyAsync(base + p.sysdev, &sd, sizeof(SysDev), hipMemcpyHostToDevice, e->s));
-  KrylovLaunch KL{own, 1, N, e->d.m_max, e->s};
+  HIPCHK(hipMemcpyAsync(base + p.sysdev, &sd, sizeof(SysDev), hipMemcpyHostToDevice, g.s));
+  KrylovLaunch KL{own, 1, N, e->d.m_max, g.s};
   launch_init_state(KL, q.max_iter, q.rtol);
   if (op != PID) {
-    HIPCHK(hipMemsetAsync(base + p.Hc, 0, (size_t)N * m->arch.width * p.MP * op_esize(op), e->s));
-    HIPCHK(hipMemsetAsync(base + p.Wh, 0, p.wh_bytes_per_sys, e->s));
+    HIPCHK(hipMemsetAsync(base + p.Hc, 0, (size_t)N * m->arch.width * p.MP * op_esize(op), g.s));
+    HIPCHK(hipMemsetAsync(base + p.Wh, 0, p.wh_bytes_per_sys, g.s));
     NOLaunch NL = group_no(e, g, own, 1);
     launch_no_setup(NL, (double*)(base + p.Gp));
   }
@@ -1095,7 +1162,7 @@ fcgno_status upload_table(fcgno_engine* e, EngGroup& g, size_t where, const std:
   std::vector<SysDev> h;
   h.reserve(ids.size());
   for (int64_t id : ids) h.push_back(e->active.at(id).sd);
-  HIPCHK(hipMemcpyAsync(e->pool + g.off + where, h.data(), h.size() * sizeof(SysDev), hipMemcpyHostToDevice, e->s));
+  HIPCHK(hipMemcpyAsync(e->pool + g.off + where, h.data(), h.size() * sizeof(SysDev), hipMemcpyHostToDevice, g.s));
   return FCGNO_OK;
 }
 
@@ -1120,19 +1187,36 @@ extern "C" fcgno_status fcgno_engine_create(const fcgno_model* m, const fcgno_en
   e->d = *d;
   if (e->d.check_every <= 0) e->d.check_every = 8;
   e->s = (hipStream_t)stream;
-  const size_t bytes = d->budget_bytes & ~(size_t)255;
-  if (hipMalloc((void**)&e->pool, bytes) != hipSuccess) {
+  bool ok = hipEventCreateWithFlags(&e->ready, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; ok && i < 4; ++i) {
+    hipStream_t ls = nullptr;
+    ok = hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) == hipSuccess;
+    if (ok) e->lanes.push_back(ls);
+  }
+  if (!ok) {
+    for (hipStream_t ls : e->lanes) (void)hipStreamDestroy(ls);
+    if (e->ready) (void)hipEventDestroy(e->ready);
     delete e;
-    return fail(FCGNO_E_NOMEM, "cannot allocate the engine pool");
+    return fail(FCGNO_E_HIP, "cannot create the engine's streams");
+  }
+  const size_t bytes = d->budget_bytes & ~(size_t)255;
+  fcgno_status st = FCGNO_OK;
+  if (hipMalloc((void**)&e->pool, bytes) != hipSuccess) {
+    e->pool = nullptr;
+    st = fail(FCGNO_E_NOMEM, "cannot allocate the engine pool");
+  } else if (hipHostMalloc((void**)&e->hflags, (size_t)d->max_slots * 3 * sizeof(int), 0) != hipSuccess ||
+             hipHostMalloc((void**)&e->htres, (size_t)d->max_slots * sizeof(double), 0) != hipSuccess) {
+    st = fail(FCGNO_E_HIP, "hipHostMalloc failed");
+  }
+  if (st != FCGNO_OK) {
+    if (e->hflags) (void)hipHostFree(e->hflags);
+    if (e->pool) (void)hipFree(e->pool);
+    for (hipStream_t ls : e->lanes) (void)hipStreamDestroy(ls);
+    (void)hipEventDestroy(e->ready);
+    delete e;
+    return st;
   }
   e->free_[0] = bytes;
-  if (hipHostMalloc((void**)&e->hflags, (size_t)d->max_slots * 3 * sizeof(int), 0) != hipSuccess ||
-      hipHostMalloc((void**)&e->htres, (size_t)d->max_slots * sizeof(double), 0) != hipSuccess) {
-    if (e->hflags) (void)hipHostFree(e->hflags);
-    (void)hipFree(e->pool);
-    delete e;
-    return fail(FCGNO_E_HIP, "hipHostMalloc failed");
-  }
   *out = e;
   return FCGNO_OK;
 }
@@ -1162,6 +1246,9 @@ extern "C" fcgno_status fcgno_engine_submit(fcgno_engine* e, int32_t N, const do
 
 extern "C" fcgno_status fcgno_engine_step(fcgno_engine* e, int32_t* n_active, int32_t* n_queued) {
   if (!e) return fail(FCGNO_E_INVALID, "null engine");
+  // the caller's prior work on its stream (inputs of new requests) comes first
+  HIPCHK(hipEventRecord(e->ready, e->s));
+  for (hipStream_t ls : e->lanes) HIPCHK(hipStreamWaitEvent(ls, e->ready, 0));
   // 1. admission: scan the queue in arrival order, admit what fits now
   for (auto it = e->queue.begin(); it != e->queue.end();) {
     if ((int)e->active.size() >= e->d.max_slots) break;
@@ -1197,7 +1284,7 @@ extern "C" fcgno_status fcgno_engine_step(fcgno_engine* e, int32_t* n_active, in
       g.dirty = false;
     }
     const SysDev* table = (const SysDev*)(base + g.table);
-    KrylovLaunch KL{table, G, g.N, e->d.m_max, e->s};
+    KrylovLaunch KL{table, G, g.N, e->d.m_max, g.s};
     NOLaunch NL{};
     if (e->d.op != PID) NL = group_no(e, g, table, G);
     for (int i = 0; i < K; ++i) {
@@ -1206,14 +1293,14 @@ extern "C" fcgno_status fcgno_engine_step(fcgno_engine* e, int32_t* n_active, in
       launch_dir(KL);
       launch_update(KL);
     }
-    launch_export(table, G, (int*)(base + g.flags), (double*)(base + g.tres), e->s);
+    launch_export(table, G, (int*)(base + g.flags), (double*)(base + g.tres), g.s);
     g.hoff = ho;
     HIPCHK(hipMemcpyAsync(e->hflags + 3 * ho, base + g.flags, (size_t)G * 3 * sizeof(int), hipMemcpyDeviceToHost,
-                          e->s));
+                          g.s));
     ho += G;
   }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(e->s));
+  for (hipStream_t ls : e->lanes) HIPCHK(hipStreamSynchronize(ls));
   // 3. true residual of the requests that stopped, then release them
   bool any = false;
   std::map<int, std::vector<int64_t>> fin;
@@ -1231,18 +1318,18 @@ extern "C" fcgno_status fcgno_engine_step(fcgno_engine* e, int32_t* n_active, in
     fcgno_status st = upload_table(e, g, g.ftable, kv.second);
     if (st != FCGNO_OK) return st;
     const SysDev* ft = (const SysDev*)(base + g.ftable);
-    KrylovLaunch KF{ft, F, g.N, e->d.m_max, e->s};
+    KrylovLaunch KF{ft, F, g.N, e->d.m_max, g.s};
     launch_residual(KF, 1);
-    launch_export(ft, F, (int*)(base + g.flags), (double*)(base + g.tres), e->s);
+    launch_export(ft, F, (int*)(base + g.flags), (double*)(base + g.tres), g.s);
     HIPCHK(hipMemcpyAsync(e->hflags + 3 * ho, base + g.flags, (size_t)F * 3 * sizeof(int), hipMemcpyDeviceToHost,
-                          e->s));
-    HIPCHK(hipMemcpyAsync(e->htres + ho, base + g.tres, (size_t)F * sizeof(double), hipMemcpyDeviceToHost, e->s));
+                          g.s));
+    HIPCHK(hipMemcpyAsync(e->htres + ho, base + g.tres, (size_t)F * sizeof(double), hipMemcpyDeviceToHost, g.s));
     ho += F;
     any = true;
   }
   if (any) {
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(e->s));
+    for (hipStream_t ls : e->lanes) HIPCHK(hipStreamSynchronize(ls));
     for (auto& kv : fin) {
       EngGroup& g = e->groups.at(kv.first);
       for (size_t b = 0; b < kv.second.size(); ++b) {
@@ -1277,8 +1364,11 @@ extern "C" int32_t fcgno_engine_poll(fcgno_engine* e, fcgno_engine_result* out, 
 
 extern "C" void fcgno_engine_destroy(fcgno_engine* e) {
   if (!e) return;
-  if (e->s) (void)hipStreamSynchronize(e->s);
-  else (void)hipDeviceSynchronize();
+  for (hipStream_t ls : e->lanes) {
+    (void)hipStreamSynchronize(ls);
+    (void)hipStreamDestroy(ls);
+  }
+  if (e->ready) (void)hipEventDestroy(e->ready);
   (void)hipHostFree(e->hflags);
   (void)hipHostFree(e->htres);
   (void)hipFree(e->pool);

@@ -19,7 +19,8 @@ struct LossArgs {
   double* gw;              // [B][N][N] out: A (w - e)
   double* part;            // [B][nb][2]
   double* loss;            // [B] out: ||w-e||_A / ||e||_A
-  double* gscale;          // [B] out: 1 / (B ||w-e||_A ||e||_A)
+  double* gscale;          // [B] out: 1 / (B ||w-e|| ||e||)
+  int kind;                // 0: energy norm (Notay), 1: Euclidean (L2)
 };
 
 struct BwdArgs {

@@ -64,7 +64,8 @@ __device__ __forceinline__ double apply_A(const double* __restrict__ k, const do
   return ((kE + kW + kN + kS) * c - kE * e - kW * w - kN * n - kS * s) * (h1 * h1);
 }
 
-// pass 0: dvec = w - e into gw;   pass 1: gw <- A (w - e), partials (d, Ad), (e, Ae)
+// pass 0: dvec = w - e;  pass 1: gw <- A (w - e), partials (d, Ad), (e, Ae)
+// (kind 1, the Euclidean loss: gw <- w - e, partials (d, d), (e, e))
 __global__ __launch_bounds__(256) void k_loss(LossArgs a, int pass) {
   __shared__ double lds[4];
   const int b = blockIdx.y;
@@ -80,6 +81,11 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a, int pass) {
     if (p >= n) break;
     if (pass == 0) {
       dv[p] = w[p] - e[p];
+    } else if (a.kind == 1) {
+      const double d = dv[p];
+      gw[p] = d;
+      s0 += d * d;
+      s1 += e[p] * e[p];
     } else {
       const int i = p / N, j = p - i * N;
       const double ad = apply_A(k, dv, N, i, j);
@@ -98,7 +104,7 @@ __global__ __launch_bounds__(256) void k_loss(LossArgs a, int pass) {
   }
 }
 
-// per system: loss_b = ||d||_A / ||e||_A, scale_b = 1 / (B ||d||_A ||e||_A)
+// per system: loss_b = ||d|| / ||e||, scale_b = 1 / (B ||d|| ||e||) in the loss's norm
 __global__ __launch_bounds__(256) void k_loss_fin(LossArgs a) {
   __shared__ double lds[4];
   const int b = blockIdx.x;

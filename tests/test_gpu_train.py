@@ -211,3 +211,57 @@ def test_krylov_samples_match_oracle(dev):
         Ae = oracle.stencil_apply(k[b], e[b]).numpy()
         rel = np.linalg.norm(Ae - r[b]) / np.linalg.norm(r[b, -1])
         assert rel < 1e-7
+
+
+def test_l2_loss_and_gradient(dev):
+    N, B = 24, 3
+    k, w, e = _data(N, B, 95)
+    wt = torch.from_numpy(w).requires_grad_(True)
+    L = oracle.l2_loss(wt, torch.from_numpy(e))
+    L.backward()
+    kd, wd, ed = [torch.from_numpy(a).to(dev) for a in (k, w, e)]
+    loss, gw = fc.energy_loss(kd, wd, ed, kind="l2")
+    assert abs(loss.mean().item() - L.item()) <= 1e-13 * L.item()
+    rel = torch.linalg.vector_norm(gw.cpu() - wt.grad) / torch.linalg.vector_norm(wt.grad)
+    assert rel < 1e-12
+
+
+def test_train_step_l2_matches_oracle_adamw(dev):
+    N, B, C, M, L = 16, 4, 16, 3, 2
+    k, f, u0 = _data(N, B, 510)
+    rs, es = [], []
+    for b in range(B):
+        rr, ee = oracle.krylov_samples(k[b], f[b], u0[b], 3)
+        rs.append(rr[-1].numpy()); es.append(ee[-1].numpy())
+    r, e = np.stack(rs), np.stack(es)
+    blob = synth.init_weights(23, C, M, L)
+    kt = torch.from_numpy(k)
+    val, gref = _oracle_grad(blob, C, M, L, lambda w: oracle.l2_loss(
+        oracle.no_apply(w, kt, torch.from_numpy(r)), torch.from_numpy(e)))
+    th1, _, _ = oracle.adamw_step(blob, gref, np.zeros_like(blob), np.zeros_like(blob), 1, lr=1e-3, wd=1e-2)
+    model = fc.Model(blob, C, M, L)
+    opt = fc.Optim(model, lr=1e-3, weight_decay=1e-2)
+    kd, rd, ed = [torch.from_numpy(a).to(dev) for a in (k, r, e)]
+    loss = fc.train_step(model, opt, kd, rd, ed, op="fp64", loss="l2")
+    assert abs(loss - val) <= 1e-12 * val
+    got = model.get_weights()
+    ok = np.abs(gref) > 1e-6
+    assert np.max(np.abs(got[ok] - th1[ok])) < 1e-12
+    opt.close()
+    model.close()
+
+
+def test_residual_samples_match_oracle(dev):
+    """Random right-hand sides: r = f - A u exactly, e = A^-1 f - u against a
+    sparse direct solve."""
+    N, B = 24, 3
+    k, f, _ = _data(N, B, 930)
+    u = synth.rng(12).standard_normal((B, N, N))
+    kd, fd, ud = [torch.from_numpy(a).to(dev) for a in (k, f, u)]
+    r, e = fc.residual_samples(kd, fd, ud)
+    r, e = r.cpu().numpy(), e.cpu().numpy()
+    for b in range(B):
+        rr = f[b] - oracle.stencil_apply(k[b], u[b]).numpy()
+        ee = oracle.exact_solve(k[b], f[b]) - u[b]
+        assert np.linalg.norm(r[b] - rr) <= 1e-13 * np.linalg.norm(rr)
+        assert np.linalg.norm(e[b] - ee) <= 1e-8 * np.linalg.norm(ee)
