@@ -20,6 +20,9 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   notay_loss / l2_loss         pinned: closed-form values on eigenvectors
   loss gradients (autograd)    pinned: central finite differences
   jacobi / sgs                 pinned: Table 1 iteration counts (statistical)
+  sgs / rb_sgs                 pinned: the textbook SGS matrix (D+L) D^-1 (D+U) on
+                               tiny grids, k-step error propagation, symmetry,
+                               red-black colouring and point-sweep form
   adamw_step                   pinned: hand-computed first steps
   Theorem 1's gamma            not used; parity unpinned (not computed)
 """

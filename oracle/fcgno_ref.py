@@ -31,7 +31,7 @@ __all__ = [
     "stencil_apply", "assemble", "window_size", "fcg", "FCGResult",
     "NOWeights", "unpack_weights", "pack_weights", "no_apply", "no_features",
     "energy_norm", "notay_loss", "l2_loss", "krylov_samples", "exact_solve",
-    "jacobi_precond", "sgs_precond", "adamw_step", "gelu",
+    "jacobi_precond", "sgs_precond", "red_black_order", "rb_sgs_precond", "adamw_step", "gelu",
 ]
 
 SYS_OK, SYS_NOT_CONVERGED, SYS_BREAKDOWN, SYS_NONFINITE = 0, 1, 2, 3
@@ -226,6 +226,38 @@ def sgs_precond(k, steps: int):
             x = x + spla.spsolve_triangular(Lo, b - A @ x, lower=True)
             x = x + spla.spsolve_triangular(Up, b - A @ x, lower=False)
         return torch.from_numpy(x.reshape(z.shape))
+    return apply
+
+
+def red_black_order(N: int) -> np.ndarray:
+    """Unknowns of the N x N grid (row-major index i*N + j) reordered red first:
+    red = i + j even, black = i + j odd, each colour in row-major order."""
+    i, j = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    idx = (i * N + j).reshape(-1)
+    colour = ((i + j) % 2).reshape(-1)
+    return np.concatenate([idx[colour == 0], idx[colour == 1]])
+
+
+def rb_sgs_precond(k, steps: int):
+    """Symmetric Gauss-Seidel(k) of Sec. 3.3.1 applied to the red-black reordered
+    matrix P A P^T (red points first): the same two half steps with the lower
+    and upper triangles of the reordered matrix, mapped back to grid order."""
+    A = assemble(k)
+    N = _t(k).shape[-1] - 2
+    perm = red_black_order(N)
+    Ap = A[perm][:, perm].tocsr()
+    Lo = sp.tril(Ap, format="csr")
+    Up = sp.triu(Ap, format="csr")
+
+    def apply(z):
+        b = z.numpy().reshape(-1)[perm]
+        x = np.zeros_like(b)
+        for _ in range(steps):
+            x = x + spla.spsolve_triangular(Lo, b - Ap @ x, lower=True)
+            x = x + spla.spsolve_triangular(Up, b - Ap @ x, lower=False)
+        out = np.empty_like(x)
+        out[perm] = x
+        return torch.from_numpy(out.reshape(z.shape))
     return apply
 
 

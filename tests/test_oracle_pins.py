@@ -132,6 +132,87 @@ def test_fcg_jacobi_is_pcg():
     assert np.max(np.abs(np.array(res.hist) - ref) / np.array(ref)) < 1e-10
 
 
+def _red_black_by_hand(N):
+    reds = [i * N + j for i in range(N) for j in range(N) if (i + j) % 2 == 0]
+    blacks = [i * N + j for i in range(N) for j in range(N) if (i + j) % 2 == 1]
+    return np.array(reds + blacks)
+
+
+@pytest.mark.parametrize("ordering", ["lexicographic", "red-black"])
+@pytest.mark.parametrize("steps", [1, 3])
+def test_sgs_is_textbook_symmetric_gauss_seidel(ordering, steps):
+    """Saad, Sec. 4.1: one SGS step from x = 0 applies M^-1 with
+    M = (D + L) D^-1 (D + U) in the ordering used (L, U strict triangles), and
+    k steps leave the error propagator (I - M^-1 A)^k, so
+    B_k = (I - (I - M^-1 A)^k) A^-1.  Dense matrices on a small grid."""
+    N = 6
+    k, _, _ = synth.diffusion_system(41, N)
+    A = oracle.assemble(k).toarray()
+    n = N * N
+    perm = np.arange(n) if ordering == "lexicographic" else _red_black_by_hand(N)
+    Ap = A[np.ix_(perm, perm)]
+    D = np.diag(np.diag(Ap))
+    Lo, Up = np.tril(Ap, -1), np.triu(Ap, 1)
+    Mp = (D + Lo) @ np.linalg.inv(D) @ (D + Up)
+    E = np.eye(n) - np.linalg.solve(Mp, Ap)
+    Bp = (np.eye(n) - np.linalg.matrix_power(E, steps)) @ np.linalg.inv(Ap)
+    Bmat = np.empty_like(Bp)
+    Bmat[np.ix_(perm, perm)] = Bp
+    B = (oracle.sgs_precond if ordering == "lexicographic" else oracle.rb_sgs_precond)(k, steps)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        z = rng.standard_normal((N, N))
+        got = B(torch.from_numpy(z)).numpy().reshape(-1)
+        want = Bmat @ z.reshape(-1)
+        assert np.max(np.abs(got - want)) <= 1e-10 * np.max(np.abs(want))
+    assert np.max(np.abs(Bmat - Bmat.T)) <= 1e-9 * np.max(np.abs(Bmat))
+
+
+@pytest.mark.parametrize("steps", [1, 2, 4])
+def test_rb_sgs_is_alternating_colour_sweeps(steps):
+    """In red-black order points of one colour couple only to the other, so a
+    symmetric step red, black, black, red repeats its black half sweep and the
+    next step's red one repeats the last: k steps are 2k + 1 point sweeps
+    alternating red, black, ..., red, each setting x_p = (z_p - sum_q a_pq x_q) / a_pp."""
+    N = 7
+    k, _, _ = synth.diffusion_system(43, N)
+    A = oracle.assemble(k).toarray()
+    z = np.random.default_rng(5).standard_normal((N, N))
+    x = np.zeros(N * N)
+    zf = z.reshape(-1)
+    for h in range(2 * steps + 1):
+        colour = h % 2
+        for i in range(N):
+            for j in range(N):
+                if (i + j) % 2 != colour:
+                    continue
+                p = i * N + j
+                acc = zf[p]
+                for q in range(N * N):
+                    if q != p:
+                        acc -= A[p, q] * x[q]
+                x[p] = acc / A[p, p]
+    got = oracle.rb_sgs_precond(k, steps)(torch.from_numpy(z)).numpy().reshape(-1)
+    assert np.max(np.abs(got - x)) <= 1e-12 * np.max(np.abs(x))
+
+
+def test_fcg_rb_sgs_is_pcg():
+    """Red-black SGS is SPD and linear: FCG equals textbook preconditioned CG."""
+    k, f, u0 = synth.diffusion_system(7, 20)
+    A = lambda v: oracle.stencil_apply(k, v).numpy()
+    Bs = oracle.rb_sgs_precond(k, 2)
+    B = lambda v: Bs(torch.from_numpy(v)).numpy()
+    u = u0.copy(); r = f - A(u); z = B(r); p = z.copy(); rz = np.sum(r * z)
+    r0 = np.linalg.norm(r); ref = [1.0]
+    for _ in range(12):
+        Ap = A(p); a = rz / np.sum(p * Ap)
+        u += a * p; r -= a * Ap; z = B(r)
+        rz_new = np.sum(r * z); p = z + (rz_new / rz) * p; rz = rz_new
+        ref.append(np.linalg.norm(r) / r0)
+    res = oracle.fcg(k, f, u0, Bs, m_max=5, max_iter=12, tol=0.0)
+    assert np.max(np.abs(np.array(res.hist) - ref) / np.array(ref)) < 1e-8
+
+
 def _dst_poisson_inverse(N, kappa):
     """A^-1 for constant k via the type-I sine transform (closed-form eigenbasis)."""
     h = 1.0 / (N + 1)
