@@ -55,6 +55,9 @@ def parse():
                    help="also train with the Euclidean loss and with random-residual samples (Sec. 3.3) "
                         "and compare FCG iteration counts")
     p.add_argument("--ablation-steps", type=int, default=6000)
+    p.add_argument("--classical", default="",
+                   help="comma-separated grids: time FCG with CG, Jacobi(4), red-black SGS(1) and SGS(4) "
+                        "next to the neural operator on the workload's systems at those sizes (Table 1)")
     p.add_argument("--log", default=None, help="progress log file (default: stderr)")
     return p.parse_args()
 
@@ -169,6 +172,44 @@ def ablation(fc, torch, dev, C, M, L, steps, logf):
         out[name] = {"training": info, "fcg": evaluate(model, "fp32")}
         log(f"ablation {name}: {out[name]['fcg']}", logf)
         model.close()
+    return out
+
+
+def classical(fc, torch, dev, model, grids, B, main_op, logf):
+    """Table 1 on the GPU with wall clock: FCG (m = 5, tol 1e-6) preconditioned
+    by nothing (CG), Jacobi(4), red-black symmetric Gauss-Seidel(1) and (4),
+    and the neural operator, on the benchmark's systems (k = exp(GRF),
+    contrast 10..1e3) at each grid; one warm-up solve then two timed ones."""
+    import synth
+    out = {}
+    methods = [("CG", "identity", 1), ("Jacobi(4)", "jacobi", 4), ("SGS-RB(1)", "sgs_rb", 1),
+               ("SGS-RB(4)", "sgs_rb", 4), (f"NO({main_op})", main_op, 1)]
+    for N in grids:
+        k, f, u0, _ = synth.batch(2, B, N, (10.0, 1000.0))
+        kd, fd, u0d = [torch.from_numpy(a).to(dev) for a in (k, f, u0)]
+        row = {}
+        for name, op, steps in methods:
+            mdl = model if op in ("fp64", "fp32", "bf16") else None
+            max_iter = 40 * N
+            ws = torch.empty(fc.solve_workspace_bytes(mdl, N, B, op, 5, max_iter, 1e-6, steps),
+                             dtype=torch.uint8, device=dev)
+            u = u0d.clone()
+            fc.solve(mdl, kd, fd, u, op=op, m_max=5, max_iter=max_iter, rtol=1e-6, hist=False,
+                     workspace=ws, precond_steps=steps)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                u = u0d.clone()
+                o = fc.solve(mdl, kd, fd, u, op=op, m_max=5, max_iter=max_iter, rtol=1e-6, hist=False,
+                             workspace=ws, precond_steps=steps)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 2
+            ok = o["status"] == 0
+            row[name] = {"iters_median": float(np.median(o["iters"])), "iters_max": int(o["iters"].max()),
+                         "converged": int(ok.sum()), "of": B, "ms_per_batch": round(dt * 1e3, 2),
+                         "ms_per_iteration": round(dt * 1e3 / max(int(o["iters"].max()), 1), 4)}
+            log(f"classical N={N} {name}: {row[name]}", logf)
+        out[str(N)] = row
     return out
 
 
@@ -446,6 +487,10 @@ def main():
     if args.ablation:
         abl = ablation(fc, torch, dev, C, M, L, args.ablation_steps, logf)
 
+    classic = None
+    if args.classical:
+        classic = classical(fc, torch, dev, model, [int(g) for g in args.classical.split(",")], B, main_op, logf)
+
     serve = None
     if args.serve_requests > 0:
         serve = serving(fc, torch, dev, model, args.serve_requests, logf)
@@ -475,6 +520,7 @@ def main():
         "training": train_info,
         "serving": serve,
         "ablation": abl,
+        "classical": classic,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -69,6 +69,10 @@ enum {
     FCGNO_OP_FP32 = 1,      /* float32 matrix cores */
     FCGNO_OP_BF16 = 2,      /* bfloat16 inputs on matrix cores, float32 accumulation */
     FCGNO_OP_IDENTITY = 3,  /* B = I: FCG is then conjugate gradients (Fig. 2a) */
+    /* classical preconditioners of the comparison in Table 1 (no model):
+     * precond_steps sweeps from x_0 = 0 on A x = r */
+    FCGNO_OP_JACOBI = 4,    /* x <- x + D^-1 (r - A x) */
+    FCGNO_OP_SGS_RB = 5,    /* symmetric Gauss-Seidel in red-black order: red, black, black, red */
 };
 
 /* training loss: the energy-norm (Notay) loss of Sec. 2.4, or the Euclidean
@@ -118,6 +122,7 @@ typedef struct {
     double rtol;        /* stop at the first i with ||r_i||_2/||r_0||_2 <= rtol, > 0 */
     int32_t op;         /* FCGNO_OP_* */
     int32_t check_every;/* host polls convergence every this many iterations (0 = auto) */
+    int32_t precond_steps; /* JACOBI / SGS_RB: sweeps per application, 1..1000 (ignored otherwise) */
 } fcgno_solve_desc;
 
 /* Workspace bytes fcgno_solve needs for this model and descriptor

@@ -13,7 +13,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfcgno.so")
 
-OP = {"fp64": 0, "fp32": 1, "bf16": 2, "identity": 3}
+OP = {"fp64": 0, "fp32": 1, "bf16": 2, "identity": 3, "jacobi": 4, "sgs_rb": 5}
+# operators that take no model
+MODEL_FREE = ("identity", "jacobi", "sgs_rb")
 SYS_OK, SYS_NOT_CONVERGED, SYS_BREAKDOWN, SYS_NONFINITE = 0, 1, 2, 3
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "BREAKDOWN", 3: "NONFINITE"}
 
@@ -24,7 +26,7 @@ class Arch(ctypes.Structure):
 
 class SolveDesc(ctypes.Structure):
     _fields_ = [("n", c_int32), ("batch", c_int32), ("m_max", c_int32), ("max_iter", c_int32),
-                ("rtol", c_double), ("op", c_int32), ("check_every", c_int32)]
+                ("rtol", c_double), ("op", c_int32), ("check_every", c_int32), ("precond_steps", c_int32)]
 
 
 class EngineDesc(ctypes.Structure):
@@ -196,21 +198,24 @@ class Model:
             pass
 
 
-def solve_workspace_bytes(model, n, batch, op="bf16", m_max=5, max_iter=300, rtol=1e-6):
-    d = SolveDesc(n, batch, m_max, max_iter, rtol, OP[op], 0)
-    return int(lib().fcgno_solve_workspace_bytes(model.handle if model else None, ctypes.byref(d)))
+def solve_workspace_bytes(model, n, batch, op="bf16", m_max=5, max_iter=300, rtol=1e-6, precond_steps=1):
+    d = SolveDesc(n, batch, m_max, max_iter, rtol, OP[op], 0, precond_steps)
+    h = model.handle if (model is not None and op not in MODEL_FREE) else None
+    return int(lib().fcgno_solve_workspace_bytes(h, ctypes.byref(d)))
 
 
 def solve(model, k, f, u, op="bf16", m_max=5, max_iter=300, rtol=1e-6, r_out=None, hist=True,
-          check_every=0, workspace=None, stream=None):
+          check_every=0, workspace=None, stream=None, precond_steps=1):
     """Run Algorithm 1 on a batch: k [B][N+2][N+2], f [B][N][N], u [B][N][N]
-    (in: u0, out: u_iter), all float64 device tensors.  Returns a dict with
-    numpy arrays iters, status, true_rel_res and (if hist) hist [B][max_iter+1]."""
+    (in: u0, out: u_iter), all float64 device tensors.  op: a neural-operator
+    precision, "identity" (CG) or a classical preconditioner ("jacobi",
+    "sgs_rb") applied precond_steps times.  Returns a dict with numpy arrays
+    iters, status, true_rel_res and (if hist) hist [B][max_iter+1]."""
     B, N = f.shape[0], f.shape[-1]
     if tuple(k.shape) != (B, N + 2, N + 2) or tuple(u.shape) != (B, N, N):
         raise FcgnoError("shape mismatch: k [B][N+2][N+2], f and u [B][N][N]")
-    d = SolveDesc(N, B, m_max, max_iter, rtol, OP[op], check_every)
-    h = model.handle if (model is not None and op != "identity") else None
+    d = SolveDesc(N, B, m_max, max_iter, rtol, OP[op], check_every, precond_steps)
+    h = model.handle if (model is not None and op not in MODEL_FREE) else None
     nbytes = lib().fcgno_solve_workspace_bytes(h, ctypes.byref(d))
     if nbytes == 0:
         raise FcgnoError("invalid solve descriptor: " + lib().fcgno_last_error().decode(errors="replace"))

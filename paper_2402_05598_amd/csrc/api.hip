@@ -229,7 +229,7 @@ constexpr int KIND_SOLVE = 0, KIND_APPLY = 1, KIND_TRAIN = 2;
 struct Plan {
   size_t total = 0;
   size_t sysdev = 0, state = 0, counter = 0, hist = 0, part = 0;
-  size_t r = 0, w = 0, P = 0, S = 0;
+  size_t r = 0, w = 0, P = 0, S = 0, tmp = 0;
   size_t act = 0, logk = 0, Gr = 0, Gp = 0, Hc = 0, Vc = 0, Wh = 0, Vp = 0;
   size_t E64 = 0, Eacc = 0, T = 0, TT = 0;
   size_t n_part_blocks = 0, gp_bytes_per_sys = 0, vp_bytes_per_sys = 0, wh_bytes_per_sys = 0;
@@ -274,8 +274,9 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
     p.P = cv.take((size_t)B * (m_max + 1) * n * 8);
     p.S = cv.take((size_t)B * (m_max + 1) * n * 8);
     p.w = op != PID ? cv.take((size_t)B * n * 8) : 0;
+    p.tmp = op == PJAC ? cv.take((size_t)B * n * 8) : 0;
   }
-  if (op != PID && m) {
+  if (is_no(op) && m) {
     const int C = m->arch.width, M = m->arch.modes, L = m->arch.layers;
     const int MP = round16(2 * M), NP = round16(N);
     const int nyt = NP / 16;
@@ -398,8 +399,10 @@ fcgno_status check_desc(const fcgno_model* m, const fcgno_solve_desc* d) {
   if (d->m_max < 1 || d->m_max > MAXW) return fail(FCGNO_E_INVALID, "m_max must be in 1..32");
   if (d->max_iter < 1) return fail(FCGNO_E_INVALID, "max_iter must be >= 1");
   if (!(d->rtol > 0.0) || !std::isfinite(d->rtol)) return fail(FCGNO_E_INVALID, "rtol must be > 0");
-  if (d->op < 0 || d->op > PID) return fail(FCGNO_E_INVALID, "unknown op precision");
-  if (d->op != PID) {
+  if (d->op < 0 || d->op > PSGS) return fail(FCGNO_E_INVALID, "unknown op");
+  if ((d->op == PJAC || d->op == PSGS) && (d->precond_steps < 1 || d->precond_steps > 1000))
+    return fail(FCGNO_E_INVALID, "precond_steps must be in 1..1000 for JACOBI and SGS_RB");
+  if (is_no(d->op)) {
     if (!m) return fail(FCGNO_E_INVALID, "operator precision needs a model");
     if (!arch_ok_for(m, d->n)) return fail(FCGNO_E_INVALID, "need 2*modes <= n");
   }
@@ -452,14 +455,15 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
     sd.hist = (decltype(sd.hist))((double*)(base + p.hist) + (size_t)b * (d->max_iter + 1));
     sd.part = (decltype(sd.part))((double*)(base + p.part) + (size_t)b * p.n_part_blocks * NQ);
     sd.n_active = (decltype(sd.n_active))(counter);
+    if (op == PJAC) sd.tmp = (decltype(sd.tmp))((double*)(base + p.tmp) + (size_t)b * n);
   }
-  if (op != PID) fill_no(m, p, base, N, B, op, h);
+  if (is_no(op)) fill_no(m, p, base, N, B, op, h);
   const SysDev* sysdev = (const SysDev*)(base + p.sysdev);
   HIPCHK(hipMemcpyAsync(base + p.sysdev, h.data(), B * sizeof(SysDev), hipMemcpyHostToDevice, s));
   KrylovLaunch KL{sysdev, B, N, d->m_max, s};
   launch_init_state(KL, d->max_iter, d->rtol);
   NOLaunch NL{};
-  if (op != PID) {
+  if (is_no(op)) {
     NL = make_no(m, p, base, sysdev, N, B, op, s);
     fcgno_status os = operator_setup(m, p, base, NL, N, B, op, s);
     if (os != FCGNO_OK) return os;
@@ -471,7 +475,9 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
   while (it < d->max_iter) {
     const int end = std::min(d->max_iter, it + K);
     for (; it < end; ++it) {
-      if (op != PID) launch_no_apply(NL);
+      if (is_no(op)) launch_no_apply(NL);
+      else if (op == PJAC) launch_jacobi(KL, d->precond_steps);
+      else if (op == PSGS) launch_rbsgs(KL, d->precond_steps);
       launch_wdots(KL);
       launch_dir(KL);
       launch_update(KL);
@@ -1178,7 +1184,7 @@ extern "C" size_t fcgno_engine_request_bytes(const fcgno_model* m, const fcgno_e
 extern "C" fcgno_status fcgno_engine_create(const fcgno_model* m, const fcgno_engine_desc* d, void* stream,
                                             fcgno_engine** out) {
   if (!d || !out) return fail(FCGNO_E_INVALID, "null argument");
-  if (d->op < 0 || d->op > PID) return fail(FCGNO_E_INVALID, "unknown op precision");
+  if (d->op < 0 || d->op > PID) return fail(FCGNO_E_INVALID, "the engine takes FP64, FP32, BF16 or IDENTITY");
   if (d->op != PID && !m) return fail(FCGNO_E_INVALID, "operator precision needs a model");
   if (d->m_max < 1 || d->m_max > MAXW) return fail(FCGNO_E_INVALID, "m_max must be in 1..32");
   if (d->max_slots < 1 || d->budget_bytes < 4096) return fail(FCGNO_E_INVALID, "need max_slots >= 1 and a budget");

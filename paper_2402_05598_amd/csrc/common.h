@@ -14,7 +14,10 @@ constexpr int TILE_I = 16;      // stencil tile rows (x1)
 constexpr int TILE_J = 64;      // stencil tile columns (x2, contiguous)
 constexpr int TPW = 32;         // 16-point column tiles per wave in the layer kernel
 
-enum Prec { P64 = 0, P32 = 1, PBF = 2, PID = 3 };
+enum Prec { P64 = 0, P32 = 1, PBF = 2, PID = 3, PJAC = 4, PSGS = 5 };
+
+// neural-operator precisions (the others are identity and classical sweeps)
+__host__ __device__ inline bool is_no(int op) { return op == P64 || op == P32 || op == PBF; }
 
 // Device memory reached through pointers that the kernels read from memory
 // (the per-system tables) is declared in the global address space for the
@@ -74,6 +77,7 @@ struct SysDev {
   GLOBAL void* Vc;          // [C][2M][M] complex, accumulate precision: constant part of layer-0 spectrum
   GLOBAL void* Wh;          // [M][C][MP] complex, accumulate precision: mixed spectrum of the current layer (zero past 2M)
   GLOBAL void* Vp;          // [M][XS][C][2M] complex, accumulate precision: per-chunk forward spectra
+  GLOBAL double* tmp;       // [N^2] second iterate of the Jacobi sweeps
 };
 
 // Per-N tables shared by the systems of one launch.
@@ -185,6 +189,10 @@ void launch_rnorm(const KrylovLaunch& L);                 // snorm from r (opera
 void launch_wdots(const KrylovLaunch& L);
 void launch_dir(const KrylovLaunch& L);
 void launch_update(const KrylovLaunch& L);
+// classical preconditioners: w = x_steps of Jacobi / red-black symmetric
+// Gauss-Seidel on A x = r from x_0 = 0 (active systems)
+void launch_jacobi(const KrylovLaunch& L, int steps);
+void launch_rbsgs(const KrylovLaunch& L, int steps);
 void launch_record(const KrylovLaunch& L, int it, int m, double* rec_r, double* rec_e, const double* ustar);
 // flags[3b..3b+2] = {active, status, iters}, tres[b] = true relative residual
 void launch_export(const SysDev* sys, int nsys, int* flags, double* tres, hipStream_t s);

@@ -364,6 +364,65 @@ __global__ __launch_bounds__(256) void k_record(const SysDev* sys, int N, int it
   rec_e[o] = ustar[(size_t)blockIdx.y * n + p] - sd.u[p];
 }
 
+// ---- classical preconditioners (the comparison of Table 1) ----------------
+
+// sum of the off-diagonal couplings of point (i, j) times x, and the
+// diagonal of A there (zero Dirichlet values outside)
+__device__ __forceinline__ void offsum_diag(const GLOBAL double* __restrict__ k, const GLOBAL double* __restrict__ x,
+                                            int N, int i, int j, bool use_x, double& off, double& diag) {
+  const int K = N + 2;
+  const double kc = k[(i + 1) * K + (j + 1)];
+  const double kE = 0.5 * (kc + k[(i + 2) * K + (j + 1)]);
+  const double kW = 0.5 * (kc + k[(i)*K + (j + 1)]);
+  const double kN = 0.5 * (kc + k[(i + 1) * K + (j + 2)]);
+  const double kS = 0.5 * (kc + k[(i + 1) * K + (j)]);
+  const double h1 = (double)(N + 1);
+  diag = (kE + kW + kN + kS) * (h1 * h1);
+  off = 0.0;
+  if (use_x) {
+    const int p = i * N + j;
+    const double e = (i + 1 < N) ? x[p + N] : 0.0;
+    const double wv = (i > 0) ? x[p - N] : 0.0;
+    const double n = (j + 1 < N) ? x[p + 1] : 0.0;
+    const double sv = (j > 0) ? x[p - 1] : 0.0;
+    off = (kE * e + kW * wv + kN * n + kS * sv) * (h1 * h1);
+  }
+}
+
+// One Jacobi sweep x_out = x_in + D^-1 (r - A x_in) = D^-1 (r + offsum(x_in));
+// first: x_in = 0.  to_w: write w (else the second iterate tmp).
+__global__ __launch_bounds__(256) void k_jacobi(const SysDev* sys, int N, int to_w, int first) {
+  const SysDev sd = sys[blockIdx.y];
+  if (!sd.st->active) return;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= N * N) return;
+  const int i = p / N, j = p - i * N;
+  const GLOBAL double* xin = to_w ? sd.tmp : sd.w;
+  GLOBAL double* xout = to_w ? sd.w : sd.tmp;
+  double off, diag;
+  offsum_diag(sd.k, xin, N, i, j, !first, off, diag);
+  xout[p] = (sd.r[p] + off) / diag;
+}
+
+// Half sweep of red-black Gauss-Seidel in place on w: the points of one
+// colour ((i + j) & 1 == color) get D^-1 (r + offsum(w)), their neighbours
+// being of the other colour; first: the other colour is x_0 = 0.  One thread
+// per point of the colour: row i, pair q covers columns 2q and 2q + 1.
+__global__ __launch_bounds__(256) void k_rbgs(const SysDev* sys, int N, int color, int first) {
+  const SysDev sd = sys[blockIdx.y];
+  if (!sd.st->active) return;
+  const int H = (N + 1) >> 1;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= N * H) return;
+  const int i = t / H;
+  const int j = 2 * (t - i * H) + ((i + color) & 1);
+  if (j >= N) return;
+  const int p = i * N + j;
+  double off, diag;
+  offsum_diag(sd.k, sd.w, N, i, j, !first, off, diag);
+  sd.w[p] = (sd.r[p] + off) / diag;
+}
+
 // Per-system summary for the host: {active, status, iters} and the true residual.
 __global__ __launch_bounds__(64) void k_export(const SysDev* sys, int nsys, int* flags, double* tres) {
   const int b = blockIdx.x * 64 + threadIdx.x;
@@ -376,6 +435,25 @@ __global__ __launch_bounds__(64) void k_export(const SysDev* sys, int nsys, int*
 }
 
 // ---- launchers ------------------------------------------------------------
+
+void launch_jacobi(const KrylovLaunch& L, int steps) {
+  const dim3 g((L.N * L.N + 255) / 256, L.nsys);
+  // steps alternate between w and tmp so that the last one lands in w
+  for (int s = 1; s <= steps; ++s)
+    hipLaunchKernelGGL(k_jacobi, g, dim3(256), 0, L.stream, L.sys, L.N, ((steps - s) % 2) == 0 ? 1 : 0,
+                       s == 1 ? 1 : 0);
+}
+
+void launch_rbsgs(const KrylovLaunch& L, int steps) {
+  const int H = (L.N + 1) >> 1;
+  const dim3 g((L.N * H + 255) / 256, L.nsys);
+  // A symmetric step sweeps red, black, black, red.  Points of one colour
+  // couple only to the other, so the repeated black sweep and the next step's
+  // first red sweep recompute identical values: k steps are the 2k + 1
+  // alternating half sweeps red, black, ..., red.
+  for (int h = 0; h < 2 * steps + 1; ++h)
+    hipLaunchKernelGGL(k_rbgs, g, dim3(256), 0, L.stream, L.sys, L.N, h & 1, h == 0 ? 1 : 0);
+}
 
 void launch_export(const SysDev* sys, int nsys, int* flags, double* tres, hipStream_t s) {
   hipLaunchKernelGGL(k_export, dim3((nsys + 63) / 64), dim3(64), 0, s, sys, nsys, flags, tres);

@@ -41,3 +41,18 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(b, "_lib", None)
     with pytest.raises(b.FcgnoError):
         b.lib()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_classical_preconditioner_descriptors():
+    """JACOBI and SGS_RB take no model and need 1..1000 sweeps (host-side checks only)."""
+    import paper_2402_05598_amd._binding as b
+    assert b.solve_workspace_bytes(None, 32, 2, op="jacobi", precond_steps=4) > 0
+    assert b.solve_workspace_bytes(None, 33, 1, op="sgs_rb", precond_steps=1) > 0
+    for op in ("jacobi", "sgs_rb"):
+        assert b.solve_workspace_bytes(None, 32, 2, op=op, precond_steps=0) == 0
+        assert b.solve_workspace_bytes(None, 32, 2, op=op, precond_steps=1001) == 0
+    # the Jacobi ping-pong iterate costs one more grid per system than SGS
+    extra = (b.solve_workspace_bytes(None, 32, 2, op="jacobi", precond_steps=4)
+             - b.solve_workspace_bytes(None, 32, 2, op="sgs_rb", precond_steps=4))
+    assert extra >= 2 * 32 * 32 * 8
