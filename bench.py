@@ -58,6 +58,9 @@ def parse():
     p.add_argument("--classical", default="",
                    help="comma-separated grids: time FCG with CG, Jacobi(4), red-black SGS(1) and SGS(4) "
                         "next to the neural operator on the workload's systems at those sizes (Table 1)")
+    p.add_argument("--cross-res", action="store_true",
+                   help="Table 4: train at 32^2 and 64^2 (and fine-tune the 64^2 operator at 128^2), count "
+                        "iterations to 1e-3, 1e-6 and 1e-12 at grids 64..1024")
     p.add_argument("--log", default=None, help="progress log file (default: stderr)")
     return p.parse_args()
 
@@ -85,16 +88,22 @@ def layer_bytes_per_launch(N, B, C, M, esize, asize, S):
     return B * (N * N * per_point + N * per_row)
 
 
-def train_operator(fc, torch, dev, C, M, L, steps, logf, loss="energy", sampling="krylov"):
-    """Energy-norm training on conjugate-gradient Krylov samples of 64 x 64
-    systems (AdamW, lr 3e-4 halved every quarter of the run, weight decay
-    1e-2).  loss="l2" and sampling="random" give the two alternatives of the
-    ablation in Sec. 3.3 (random samples: u ~ N(0, I), f ~ GRF per sample,
-    r = f - A u, e = A^-1 f - u).  Returns the model and a summary."""
+def train_operator(fc, torch, dev, C, M, L, steps, logf, loss="energy", sampling="krylov", Nt=64, Bs=256,
+                   m_iter=400, init=None, lr=3e-4):
+    """Energy-norm training on conjugate-gradient Krylov samples of Nt x Nt
+    systems (default 64, 256 systems, CG iterations 1..400; AdamW, lr halved
+    every quarter of the run, weight decay 1e-2).  loss="l2" and
+    sampling="random" give the two alternatives of the ablation in Sec. 3.3
+    (random samples: u ~ N(0, I), f ~ GRF per sample, r = f - A u,
+    e = A^-1 f - u).  init: a weight blob to start from (fine-tuning).
+    Returns the model and a summary."""
     import synth
-    Nt, Bs, m_iter, mb = 64, 256, 400, 64
-    blob = synth.init_weights(3, C, M, L)
-    blob[blob.size - C - 1:] *= 1e-3   # start the projection near zero: w ~ 0 has loss 1
+    mb = 64
+    if init is None:
+        blob = synth.init_weights(3, C, M, L)
+        blob[blob.size - C - 1:] *= 1e-3   # start the projection near zero: w ~ 0 has loss 1
+    else:
+        blob = np.array(init, dtype=np.float64)
     model = fc.Model(blob, C, M, L)
     if steps <= 0:
         return model, None
@@ -114,7 +123,6 @@ def train_operator(fc, torch, dev, C, M, L, steps, logf, loss="energy", sampling
         m_iter = per
     torch.cuda.synchronize()
     log(f"{sampling} samples {tuple(r.shape)} in {time.perf_counter() - t0:.2f}s", logf)
-    lr = 3e-4
     opt = fc.Optim(model, lr=lr, weight_decay=1e-2)
     ws = fc.train_workspace(model, Nt, mb, "fp32", dev)
     g = torch.Generator(device=dev)
@@ -210,6 +218,61 @@ def classical(fc, torch, dev, model, grids, B, main_op, logf):
                          "ms_per_iteration": round(dt * 1e3 / max(int(o["iters"].max()), 1), 4)}
             log(f"classical N={N} {name}: {row[name]}", logf)
         out[str(N)] = row
+    return out
+
+
+def cross_resolution(fc, torch, dev, C, M, L, main_op, logf, model64=None, info64=None):
+    """Sec. 3.4 (Table 4): an operator trained on a coarse grid preconditions
+    FCG on finer ones.  Operators trained at 32^2 and 64^2 (16000 steps each,
+    the 64^2 one reused when given) and the 64^2 one fine-tuned at 128^2
+    (4000 steps, lr 1e-4); 16 held-out systems per test grid (k = exp(GRF),
+    contrast 10..1e3), m = 5, at most max(2N, 300) iterations; the first
+    iteration reaching each relative residual (median over the systems, those
+    that never reach it counted at the limit) and how many reach it."""
+    import synth
+    grids = (64, 128, 256, 512, 1024)
+    tests = {}
+    for N in grids:
+        k, f, u0, _ = synth.batch(5, 16, N, (10.0, 1000.0))
+        tests[N] = [torch.from_numpy(a).to(dev) for a in (k, f, u0)]
+
+    def evaluate(model, op):
+        res = {}
+        for N, (kd, fd, ud) in tests.items():
+            u = ud.clone()
+            mi = max(2 * N, 300)
+            o = fc.solve(model, kd, fd, u, op=op, m_max=5, max_iter=mi, rtol=1e-12)
+            row = {"max_iter": mi}
+            for tol in (1e-3, 1e-6, 1e-12):
+                first = []
+                for b in range(o["hist"].shape[0]):
+                    idx = np.nonzero(o["hist"][b] <= tol)[0]
+                    first.append(int(idx[0]) if idx.size else -1)
+                first = np.array(first)
+                ok = first >= 0
+                row[f"{tol:g}"] = {"reached": int(ok.sum()), "of": int(ok.size),
+                                   "median": float(np.median(np.where(ok, first, mi)))}
+            res[str(N)] = row
+        return res
+    out = {"cg": evaluate(None, "identity")}
+    log(f"cross-res cg: {out['cg']}", logf)
+    m32, i32 = train_operator(fc, torch, dev, C, M, L, 16000, logf, Nt=32)
+    out["train32"] = {"training": i32, "fcg": evaluate(m32, main_op)}
+    m32.close()
+    own = model64 is None
+    if own:
+        model64, i64 = train_operator(fc, torch, dev, C, M, L, 16000, logf, Nt=64)
+    else:
+        i64 = info64
+    out["train64"] = {"training": i64, "fcg": evaluate(model64, main_op)}
+    mft, ift = train_operator(fc, torch, dev, C, M, L, 4000, logf, Nt=128, Bs=128, init=model64.get_weights(),
+                              lr=1e-4)
+    out["train64_finetune128"] = {"training": ift, "fcg": evaluate(mft, main_op)}
+    mft.close()
+    if own:
+        model64.close()
+    for name in ("train32", "train64", "train64_finetune128"):
+        log(f"cross-res {name}: {out[name]['fcg']}", logf)
     return out
 
 
@@ -487,6 +550,12 @@ def main():
     if args.ablation:
         abl = ablation(fc, torch, dev, C, M, L, args.ablation_steps, logf)
 
+    xres = None
+    if args.cross_res:
+        xres = cross_resolution(fc, torch, dev, C, M, L, main_op, logf,
+                                model64=model if train_info and train_info.get("grid") == 64 else None,
+                                info64=train_info)
+
     classic = None
     if args.classical:
         classic = classical(fc, torch, dev, model, [int(g) for g in args.classical.split(",")], B, main_op, logf)
@@ -521,6 +590,7 @@ def main():
         "serving": serve,
         "ablation": abl,
         "classical": classic,
+        "cross_resolution": xres,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -60,7 +60,10 @@ def _data(N, B, seed):
     return np.stack(k), np.stack(f), np.stack(u0)
 
 
-@pytest.mark.parametrize("N,C,M,L", [(16, 16, 4, 2), (24, 16, 3, 4), (20, 32, 5, 1)])
+# (72, ...) and (130, ...) take the segmented-row path of the backward (more
+# points per row than a block holds), with ragged last segments
+@pytest.mark.parametrize("N,C,M,L", [(16, 16, 4, 2), (24, 16, 3, 4), (20, 32, 5, 1), (72, 16, 4, 2),
+                                     (130, 16, 5, 2)])
 def test_op_backward_matches_oracle_fp64(dev, N, C, M, L):
     print(f"backward N={N} C={C} M={M} L={L}", flush=True)
     B = 2
@@ -152,8 +155,10 @@ def test_train_step_matches_oracle_adamw(dev):
     model.close()
 
 
-def test_fp32_gradient_close_to_fp64(dev):
-    N, B, C, M, L = 32, 2, 32, 6, 4
+@pytest.mark.parametrize("N", [32, 136])
+def test_fp32_gradient_close_to_fp64(dev, N):
+    print(f"fp32 vs fp64 gradient N={N}", flush=True)
+    B, C, M, L = 2, 32, 6, 4
     k, r, _ = _data(N, B, 700)
     g = synth.rng(8).standard_normal((B, N, N))
     blob = synth.init_weights(31, C, M, L)
