@@ -17,6 +17,9 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
                                energy identity, finite termination, Table 1
   no_apply                     pinned: brute-force explicit-sum operator on tiny
                                grids, exact homogeneity, B(0) = 0
+  sine-basis layer             pinned: analysis equals scipy's DST-I, the layer
+                               with weights 1/lambda inverts constant-k A on the
+                               kept sine modes and drops the others
   notay_loss / l2_loss         pinned: closed-form values on eigenvectors
   loss gradients (autograd)    pinned: central finite differences
   jacobi / sgs                 pinned: Table 1 iteration counts (statistical)

@@ -32,6 +32,7 @@ __all__ = [
     "NOWeights", "unpack_weights", "pack_weights", "no_apply", "no_features",
     "energy_norm", "notay_loss", "l2_loss", "krylov_samples", "exact_solve",
     "jacobi_precond", "sgs_precond", "red_black_order", "rb_sgs_precond", "adamw_step", "gelu",
+    "sine_matrix",
 ]
 
 SYS_OK, SYS_NOT_CONVERGED, SYS_BREAKDOWN, SYS_NONFINITE = 0, 1, 2, 3
@@ -281,6 +282,7 @@ class NOWeights:
     b: list                    # L x [C]
     W_P: torch.Tensor          # [C]
     b_P: torch.Tensor          # [1]
+    basis: str = "fourier"     # "fourier" or "sine" (the spectral layers' basis)
 
     def params(self):
         out = [self.W_L, self.b_L]
@@ -290,8 +292,11 @@ class NOWeights:
 
 
 def unpack_weights(blob, C: int, M: int, L: int = 4, Cin: int = 4,
-                   requires_grad: bool = False) -> NOWeights:
-    """Blob order (float64): W_L, b_L, then per layer Re R, Im R, W, b, then W_P, b_P."""
+                   requires_grad: bool = False, basis: str = "fourier") -> NOWeights:
+    """Blob order (float64): W_L, b_L, then per layer Re R, Im R, W, b, then W_P, b_P.
+    basis "sine": the layers use the sine basis (only Re R takes part)."""
+    if basis not in ("fourier", "sine"):
+        raise ValueError("basis must be 'fourier' or 'sine'")
     v = _t(blob).clone()
     o = 0
 
@@ -310,7 +315,7 @@ def unpack_weights(blob, C: int, M: int, L: int = 4, Cin: int = 4,
         W.append(take(C * C, (C, C))); b.append(take(C, (C,)))
     W_P = take(C, (C,)); b_P = take(1, (1,))
     assert o == v.numel(), "weight blob size does not match the architecture"
-    w = NOWeights(C, M, L, Cin, W_L, b_L, R, W, b, W_P, b_P)
+    w = NOWeights(C, M, L, Cin, W_L, b_L, R, W, b, W_P, b_P, basis)
     if requires_grad:
         for p in w.params():
             p.requires_grad_(True)
@@ -357,6 +362,26 @@ def _spectral(v, Rl, M):
     return torch.fft.irfft2(out, s=(N, N))
 
 
+def sine_matrix(P: int, N: int) -> torch.Tensor:
+    """S[p][x] = sin(pi (p+1)(x+1) / (N+1)), p < P: the first P discrete sine
+    (DST-I) modes on the N interior points, which vanish on the boundary."""
+    p = torch.arange(P, dtype=_f64)[:, None] + 1.0
+    x = torch.arange(N, dtype=_f64)[None, :] + 1.0
+    return torch.sin(math.pi * p * x / (N + 1))
+
+
+def _spectral_sine(v, Rl, M):
+    """Sine-basis layer (the Dirichlet-matched alternative to the FFT named in
+    Sec. 2.4.2 and Sec. 5): truncated DST-I analysis with 2M modes along x and
+    M along y, per-mode real mixing W^[o] = sum_c V^[c] Re R[c][o], synthesis
+    with the inverse DST-I normalisation (2/(N+1))^2.  ``v``: [..., C, N, N]."""
+    N = v.shape[-1]
+    Sx, Sy = sine_matrix(2 * M, N), sine_matrix(M, N)
+    vh = torch.einsum("ax,...cxy,qy->...caq", Sx, v, Sy)
+    wh = torch.einsum("...caq,coaq->...oaq", vh, Rl.real)
+    return (2.0 / (N + 1)) ** 2 * torch.einsum("ax,...oaq,qy->...oxy", Sx, wh, Sy)
+
+
 def no_apply(w: NOWeights, k, r, return_acts: bool = False):
     """B(r; theta) = s * NO(phi(r / s, k)), s = ||r||_2 / sqrt(n); B(0) = 0.
     ``r``: [..., N, N], ``k``: [..., N+2, N+2]."""
@@ -370,7 +395,7 @@ def no_apply(w: NOWeights, k, r, return_acts: bool = False):
     v = torch.einsum("cf,...fxy->...cxy", w.W_L, phi) + w.b_L[:, None, None]
     acts = [v]
     for l in range(w.L):
-        y = _spectral(v, w.R[l], w.M)
+        y = _spectral(v, w.R[l], w.M) if w.basis == "fourier" else _spectral_sine(v, w.R[l], w.M)
         z = y + torch.einsum("oc,...cxy->...oxy", w.W[l], v) + w.b[l][:, None, None]
         v = gelu(z)
         acts.append(v)

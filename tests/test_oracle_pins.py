@@ -371,6 +371,42 @@ def test_no_matches_explicit_dft_sums(N, C, M):
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+def test_sine_matrix_is_scipy_dst1():
+    """scipy's DST-I: y_k = 2 sum_n x_n sin(pi (k+1)(n+1) / (N+1))."""
+    for N, P in [(7, 4), (16, 16), (33, 10)]:
+        x = synth.rng(N).standard_normal(N)
+        want = scipy.fft.dst(x, type=1)[:P] / 2.0
+        got = oracle.sine_matrix(P, N).numpy() @ x
+        assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("N,M,kappa", [(12, 3, 1.0), (17, 4, 2.5)])
+def test_sine_layer_inverts_constant_k_poisson_on_kept_modes(N, M, kappa):
+    """With one channel and weights 1/lambda_pq (the eigenvalues of constant-k
+    A on sin(p pi x) sin(q pi y)), the sine-basis layer maps a combination of
+    the kept modes (p <= 2M along x, q <= M along y) to A^-1 of it, and drops
+    modes outside the kept set."""
+    h = 1.0 / (N + 1)
+    lam = lambda p, q: 4 * kappa / h**2 * (np.sin(p * np.pi * h / 2)**2 + np.sin(q * np.pi * h / 2)**2)
+    R = np.zeros((1, 1, 2 * M, M))
+    for a in range(2 * M):
+        for q in range(M):
+            R[0, 0, a, q] = 1.0 / lam(a + 1, q + 1)
+    Rc = torch.complex(torch.from_numpy(R), torch.from_numpy(np.random.default_rng(1).standard_normal(R.shape)))
+    g = synth.rng(N + M)
+    r = np.zeros((N, N)); want = np.zeros((N, N))
+    for p, q in [(1, 1), (2 * M, 1), (1, M), (3, 2), (2 * M, M)]:
+        c = g.standard_normal()
+        r += c * _sine_mode(N, p, q); want += c / lam(p, q) * _sine_mode(N, p, q)
+    got = oracle.fcgno_ref._spectral_sine(torch.from_numpy(r)[None], Rc, M)[0].numpy()
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    k = np.full((N + 2, N + 2), kappa)
+    assert np.max(np.abs(oracle.stencil_apply(k, got).numpy() - r)) <= 1e-10 * np.max(np.abs(r))
+    for p, q in [(2 * M + 1, 1), (1, M + 1)]:
+        out = oracle.fcgno_ref._spectral_sine(torch.from_numpy(_sine_mode(N, p, q))[None], Rc, M)[0]
+        assert torch.max(torch.abs(out)) <= 1e-12
+
+
 def test_no_homogeneity_and_zero():
     N = 16
     w = _random_no(C=8, M=4)
