@@ -61,6 +61,8 @@ def parse():
     p.add_argument("--cross-res", action="store_true",
                    help="Table 4: train at 32^2 and 64^2 (and fine-tune the 64^2 operator at 128^2), count "
                         "iterations to 1e-3, 1e-6 and 1e-12 at grids 64..1024")
+    p.add_argument("--sine", action="store_true",
+                   help="with --cross-res: also train sine-basis operators at 32^2 and 64^2")
     p.add_argument("--log", default=None, help="progress log file (default: stderr)")
     return p.parse_args()
 
@@ -89,13 +91,14 @@ def layer_bytes_per_launch(N, B, C, M, esize, asize, S):
 
 
 def train_operator(fc, torch, dev, C, M, L, steps, logf, loss="energy", sampling="krylov", Nt=64, Bs=256,
-                   m_iter=400, init=None, lr=3e-4):
+                   m_iter=400, init=None, lr=3e-4, basis="fourier"):
     """Energy-norm training on conjugate-gradient Krylov samples of Nt x Nt
     systems (default 64, 256 systems, CG iterations 1..400; AdamW, lr halved
     every quarter of the run, weight decay 1e-2).  loss="l2" and
     sampling="random" give the two alternatives of the ablation in Sec. 3.3
     (random samples: u ~ N(0, I), f ~ GRF per sample, r = f - A u,
     e = A^-1 f - u).  init: a weight blob to start from (fine-tuning).
+    basis: the spectral layers' basis ("fourier" or "sine").
     Returns the model and a summary."""
     import synth
     mb = 64
@@ -104,7 +107,7 @@ def train_operator(fc, torch, dev, C, M, L, steps, logf, loss="energy", sampling
         blob[blob.size - C - 1:] *= 1e-3   # start the projection near zero: w ~ 0 has loss 1
     else:
         blob = np.array(init, dtype=np.float64)
-    model = fc.Model(blob, C, M, L)
+    model = fc.Model(blob, C, M, L, basis=basis)
     if steps <= 0:
         return model, None
     k, f, u0, _ = synth.batch(3, Bs, Nt, (10.0, 1000.0))
@@ -146,7 +149,7 @@ def train_operator(fc, torch, dev, C, M, L, steps, logf, loss="energy", sampling
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     opt.close()
-    return model, {"grid": Nt, "systems": Bs, "sampling": sampling, "loss": loss,
+    return model, {"grid": Nt, "systems": Bs, "sampling": sampling, "loss": loss, "basis": basis,
                    "samples_per_system": m_iter, "batch": mb, "steps": steps,
                    "seconds": round(dt, 2), "loss_first": round(losses[0], 4),
                    "loss_last50": round(float(np.mean(losses[-50:])), 4)}
@@ -221,7 +224,7 @@ def classical(fc, torch, dev, model, grids, B, main_op, logf):
     return out
 
 
-def cross_resolution(fc, torch, dev, C, M, L, main_op, logf, model64=None, info64=None):
+def cross_resolution(fc, torch, dev, C, M, L, main_op, logf, model64=None, info64=None, sine=False):
     """Sec. 3.4 (Table 4): an operator trained on a coarse grid preconditions
     FCG on finer ones.  Operators trained at 32^2 and 64^2 (16000 steps each,
     the 64^2 one reused when given) and the 64^2 one fine-tuned at 128^2
@@ -271,7 +274,15 @@ def cross_resolution(fc, torch, dev, C, M, L, main_op, logf, model64=None, info6
     mft.close()
     if own:
         model64.close()
-    for name in ("train32", "train64", "train64_finetune128"):
+    names = ["train32", "train64", "train64_finetune128"]
+    if sine:
+        # the same recipe with sine-basis (DST-I) spectral layers
+        for Nt in (32, 64):
+            ms, inf = train_operator(fc, torch, dev, C, M, L, 16000, logf, Nt=Nt, basis="sine")
+            out[f"train{Nt}_sine"] = {"training": inf, "fcg": evaluate(ms, main_op)}
+            ms.close()
+            names.append(f"train{Nt}_sine")
+    for name in names:
         log(f"cross-res {name}: {out[name]['fcg']}", logf)
     return out
 
@@ -554,7 +565,7 @@ def main():
     if args.cross_res:
         xres = cross_resolution(fc, torch, dev, C, M, L, main_op, logf,
                                 model64=model if train_info and train_info.get("grid") == 64 else None,
-                                info64=train_info)
+                                info64=train_info, sine=args.sine)
 
     classic = None
     if args.classical:

@@ -87,7 +87,19 @@ typedef struct {
     int32_t width;        /* C in {16, 32} */
     int32_t modes;        /* M, 1 <= M <= 16; every solve needs 2M <= N */
     int32_t in_channels;  /* must be 4: [r/s, log k, x1, x2] */
+    int32_t basis;        /* FCGNO_BASIS_*: the spectral layers' analysis/synthesis basis */
 } fcgno_arch;
+
+/* Basis of the spectral layers (Sec. 2.4.2 leaves the basis open; Sec. 5 names
+ * other bases).  FOURIER: the FFT modes kx in {0..M-1} U {N-M..N-1},
+ * ky in {0..M-1}, complex mixing.  SINE: the discrete sine (DST-I) modes
+ * sin(pi p (x+1)/(N+1)), p = 1..2M along x and 1..M along y, which vanish on
+ * the Dirichlet boundary; the mixing uses the real parts of the same weights
+ * (the imaginary parts take no part and receive zero gradient). */
+enum {
+    FCGNO_BASIS_FOURIER = 0,
+    FCGNO_BASIS_SINE = 1,
+};
 
 typedef struct fcgno_model fcgno_model;
 
@@ -97,7 +109,7 @@ size_t fcgno_weight_count(const fcgno_arch* arch);
 /* Create a model from a host float64 blob (Sec. 2.4.2, the spectral layers
  * u <- S L A u).  The library copies the weights to the current device in
  * float64, float32 and bfloat16 and owns those copies.  Errors: E_INVALID
- * (null pointer, n_weights mismatch, unsupported width or modes), E_HIP. */
+ * (null pointer, n_weights mismatch, unsupported width, modes or basis), E_HIP. */
 fcgno_status fcgno_model_create(const fcgno_arch* arch, const double* weights_host,
                                 size_t n_weights, fcgno_model** out);
 

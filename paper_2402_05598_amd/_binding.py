@@ -21,7 +21,11 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "BREAKDOWN", 3: "NONFINITE"}
 
 
 class Arch(ctypes.Structure):
-    _fields_ = [("layers", c_int32), ("width", c_int32), ("modes", c_int32), ("in_channels", c_int32)]
+    _fields_ = [("layers", c_int32), ("width", c_int32), ("modes", c_int32), ("in_channels", c_int32),
+                ("basis", c_int32)]
+
+
+BASIS = {"fourier": 0, "sine": 1}
 
 
 class SolveDesc(ctypes.Structure):
@@ -164,8 +168,9 @@ def weight_count(C, M, L=4, Cin=4):
 class Model:
     """Operator weights resident on the current device (library-owned)."""
 
-    def __init__(self, weights, C, M, L=4, Cin=4):
-        self.arch = Arch(L, C, M, Cin)
+    def __init__(self, weights, C, M, L=4, Cin=4, basis="fourier"):
+        self.arch = Arch(L, C, M, Cin, BASIS[basis])
+        self.basis = basis
         w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
         self.n_weights = w.size
         h = ctypes.c_void_p()

@@ -164,6 +164,7 @@ extern "C" fcgno_status fcgno_model_create(const fcgno_arch* arch, const double*
   if (arch->in_channels != 4) return fail(FCGNO_E_INVALID, "in_channels must be 4");
   if (arch->width != 16 && arch->width != 32) return fail(FCGNO_E_INVALID, "width must be 16 or 32");
   if (arch->modes < 1 || arch->modes > 16) return fail(FCGNO_E_INVALID, "modes must be in 1..16");
+  if (arch->basis != B_FOURIER && arch->basis != B_SINE) return fail(FCGNO_E_INVALID, "unknown basis");
   if (arch->layers < 1 || arch->layers > 64) return fail(FCGNO_E_INVALID, "layers must be in 1..64");
   if (n_weights != fcgno_weight_count(arch)) return fail(FCGNO_E_INVALID, "weight count mismatch");
   for (size_t i = 0; i < n_weights; ++i)
@@ -301,8 +302,8 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
     const int XS = (N + 63) / 64;
     p.vp_bytes_per_sys = (size_t)M * XS * C * 2 * M * 2 * asz;
     p.Vp = cv.take((size_t)B * p.vp_bytes_per_sys);
-    p.E64 = cv.take((size_t)N * 2 * 8);
-    p.Eacc = cv.take((size_t)N * 2 * asz);
+    p.E64 = cv.take((size_t)tw_period(m->arch.basis, N) * 2 * 8);
+    p.Eacc = cv.take((size_t)tw_period(m->arch.basis, N) * 2 * asz);
     p.T = cv.take((size_t)NP * MP * esz);
     p.TT = cv.take((size_t)MP * NP * esz);
     if (kind == KIND_TRAIN) {
@@ -365,6 +366,7 @@ NOLaunch make_no(const fcgno_model* m, const Plan& p, char* base, const SysDev* 
   L.L = m->arch.layers;
   L.S = p.S_seg;
   L.prec = op;
+  L.basis = m->arch.basis;
   L.tab.E64 = (const double*)(base + p.E64);
   L.tab.Eacc = base + p.Eacc;
   L.tab.T = base + p.T;
@@ -734,10 +736,11 @@ fcgno_status operator_backward(const fcgno_model* m, const Plan& p, char* base, 
   const int XS = (N + 63) / 64;
   for (int l = L - 1; l >= 0; --l) {
     // spectral adjoint of layer l from the row partials of dz_l
-    SpecArgs sa{sysdev, N, p.Sb, M, 0, XS, B, NL.tab.Eacc, NL.tab.E64, m->Rmix[op][l], m->WL0[op], nullptr, 0, 1};
+    SpecArgs sa{sysdev, N, p.Sb, M, 0, XS, B, NL.tab.Eacc, NL.tab.E64, m->Rmix[op][l], m->WL0[op], nullptr, 0, 1,
+                NL.basis};
     launch_spec_fwd(NL, sa);
     BSpecArgs ba{};
-    ba.N = N; ba.M = M; ba.B = B; ba.XS = XS;
+    ba.N = N; ba.M = M; ba.B = B; ba.XS = XS; ba.basis = NL.basis;
     ba.Vp = base + p.Vp;
     ba.vp_sys = p.vp_bytes_per_sys / asz;
     ba.R = m->Rmix[op][l];
@@ -1047,8 +1050,8 @@ size_t group_bytes(const fcgno_model* m, int op, int N, int slots, EngGroup* g) 
   const int MP = m && op != PID ? round16(2 * m->arch.modes) : 16, NP = round16(N);
   const int esz = op_esize(op == PID ? P64 : op), asz = acc_esize(op == PID ? P64 : op);
   EngGroup t;
-  t.E64 = cv.take((size_t)N * 16);
-  t.Eacc = cv.take((size_t)N * 2 * asz);
+  t.E64 = cv.take((size_t)tw_period(m ? m->arch.basis : B_FOURIER, N) * 16);
+  t.Eacc = cv.take((size_t)tw_period(m ? m->arch.basis : B_FOURIER, N) * 2 * asz);
   t.T = cv.take((size_t)NP * MP * esz);
   t.TT = cv.take((size_t)MP * NP * esz);
   t.table = cv.take((size_t)slots * sizeof(SysDev));
@@ -1076,6 +1079,7 @@ NOLaunch group_no(const fcgno_engine* e, const EngGroup& g, const SysDev* table,
   L.L = m->arch.layers;
   L.S = ((round16(g.N) / 16) + TPW - 1) / TPW;
   L.prec = op;
+  L.basis = m->arch.basis;
   L.tab.E64 = (const double*)(base + g.E64);
   L.tab.Eacc = base + g.Eacc;
   L.tab.T = base + g.T;

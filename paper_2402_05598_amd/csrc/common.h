@@ -81,10 +81,29 @@ struct SysDev {
 };
 
 // Per-N tables shared by the systems of one launch.
+// Spectral bases of the operator layers.
+enum Basis { B_FOURIER = 0, B_SINE = 1 };
+
+// Entries of the x-direction twiddle table: N (Fourier, angles 2 pi m / N) or
+// 2N + 2 (sine, angles pi m / (N + 1)).
+__host__ __device__ inline int tw_period(int basis, int N) { return basis == B_SINE ? 2 * N + 2 : N; }
+
+// Twiddle-table index of kept x-mode a (< 2M) at row x.  Fourier: kx_a x mod N
+// with kx_a = a for a < M, N - 2M + a otherwise.  Sine: (a + 1)(x + 1) mod
+// (2N + 2), whose table entry holds sin(pi (a+1)(x+1)/(N+1)) in the cosine
+// slot and zero in the sine slot, so that the complex transforms reduce to
+// real DST-I sums.  All products stay below 2^32 for N <= 2^15.
+__device__ __forceinline__ unsigned tw_index(int basis, int N, int M, int a, int x) {
+  if (basis == B_SINE) return ((unsigned)(a + 1) * (unsigned)(x + 1)) % (unsigned)(2 * N + 2);
+  const int kv = a < M ? a : N - 2 * M + a;
+  return ((unsigned)kv * (unsigned)x) % (unsigned)N;
+}
+
 struct Tables {
-  const double* E64;  // [N] (cos, sin)(2 pi m / N), float64 interleaved
+  const double* E64;  // [tw_period] Fourier: (cos, sin)(2 pi m / N); sine: (sin(pi m/(N+1)), 0)
   const void* Eacc;   // same in accumulate precision
-  const void* T;      // [N][MP] op precision: T[y][2q] = cos(2 pi q y/N), T[y][2q+1] = sin(...)
+  const void* T;      // [N][MP] op precision: Fourier T[y][2q] = cos(2 pi q y/N), T[y][2q+1] = sin(...);
+                      // sine T[y][2q] = sin(pi (q+1)(y+1)/(N+1)), T[y][2q+1] = 0
   const void* TT;     // [MP][N] transpose of T
 };
 
@@ -203,6 +222,7 @@ struct NOLaunch {
   int N, C, M, MP, L;   // MP = 2M rounded up to 16
   int S;                // column segments per row in the layer kernel
   int prec;             // P64, P32, PBF
+  int basis;            // B_FOURIER or B_SINE
   Tables tab;
   // model weights in the op / accumulate precisions
   const void* const* Wfrag;   // [L] op precision [C][KWP_l]
@@ -232,7 +252,8 @@ struct SpecArgs {
   const void* WL0;   // [C] accumulate precision
   void* Vsave;       // training: V^ of this layer, [sys][M][C][2M] complex (nullable)
   size_t vs_sys;     // elements per system in Vsave
-  int unit_scale;    // synthesis without the N^-2 g_ky factor (backward pass)
+  int unit_scale;    // synthesis without the normalisation factor (backward pass)
+  int basis;         // B_FOURIER or B_SINE (set from NOLaunch::basis)
 };
 
 void launch_tables(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT);

@@ -95,19 +95,26 @@ struct Vec {
 };
 
 // ---------------------------------------------------------------------------
-// Tables: E64/Eacc[m] = (cos, sin)(2 pi m / N); T[y][2q], T[y][2q+1] = cos, sin
-// of 2 pi q y / N for q < M, zero elsewhere (and for y >= N); TT = T^T.
+// Tables.  Fourier: E64/Eacc[m] = (cos, sin)(2 pi m / N); T[y][2q], T[y][2q+1]
+// = cos, sin of 2 pi q y / N for q < M.  Sine: E64/Eacc[m] = (sin(pi m/(N+1)),
+// 0) for m < 2N + 2; T[y][2q] = sin(pi (q+1)(y+1)/(N+1)), T[y][2q+1] = 0.
+// Zero elsewhere (and for y >= N); TT = T^T.
 // ---------------------------------------------------------------------------
 template <int PREC>
-__global__ void k_tables(int N, int M, double* E64, void* Eacc, void* T, void* TT) {
+__global__ void k_tables(int N, int M, int basis, double* E64, void* Eacc, void* T, void* TT) {
   using M_ = Mf<PREC>;
   using in_t = typename M_::in_t;
   using acc_t = typename M_::acc_t;
   const int MP = round16(2 * M), NP = round16(N);
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < N) {
+  if (t < tw_period(basis, N)) {
     double s, c;
-    sincospi(2.0 * (double)t / (double)N, &s, &c);
+    if (basis == B_SINE) {
+      sincospi((double)t / (double)(N + 1), &c, &s);   // c = sin(pi t/(N+1)) in the cosine slot
+      s = 0.0;
+    } else {
+      sincospi(2.0 * (double)t / (double)N, &s, &c);
+    }
     E64[2 * t] = c;
     E64[2 * t + 1] = s;
     ((acc_t*)Eacc)[2 * t] = (acc_t)c;
@@ -118,10 +125,16 @@ __global__ void k_tables(int N, int M, double* E64, void* Eacc, void* T, void* T
     double v = 0.0;
     if (y < N && k < 2 * M) {
       const int q = k >> 1;
-      const int m = (int)(((long long)q * y) % N);
       double s, c;
-      sincospi(2.0 * (double)m / (double)N, &s, &c);
-      v = (k & 1) ? s : c;
+      if (basis == B_SINE) {
+        const int m = (int)(((long long)(q + 1) * (y + 1)) % (2 * N + 2));
+        sincospi((double)m / (double)(N + 1), &s, &c);
+        v = (k & 1) ? 0.0 : s;
+      } else {
+        const int m = (int)(((long long)q * y) % N);
+        sincospi(2.0 * (double)m / (double)N, &s, &c);
+        v = (k & 1) ? s : c;
+      }
     }
     ((in_t*)T)[y * MP + k] = M_::cvt((acc_t)v);
     ((in_t*)TT)[k * NP + y] = M_::cvt((acc_t)v);
@@ -153,7 +166,7 @@ __device__ __forceinline__ double row_field(const SysDev& sd, int N, int x, int 
 }
 
 template <int FIELD>
-__global__ __launch_bounds__(256) void k_rowdft(const SysDev* sys, int N, int M, const double* E64,
+__global__ __launch_bounds__(256) void k_rowdft(const SysDev* sys, int N, int M, int basis, const double* E64,
                                                double* out_base, size_t out_sys_stride) {
   const SysDev sd = sys[blockIdx.y];
   if (FIELD == 0 && !sd.st->active) return;
@@ -161,21 +174,39 @@ __global__ __launch_bounds__(256) void k_rowdft(const SysDev* sys, int N, int M,
   if (x >= N) return;
   const int lane = threadIdx.x & 63;
   const int MP = round16(2 * M);
-  // harmonics q = 0..15 of e^{2 pi i y / N} by complex-multiplication recurrence
   double acc[32];
 #pragma unroll
   for (int q = 0; q < 32; ++q) acc[q] = 0.0;
-  for (int y = lane; y < N; y += 64) {
-    const double v = row_field<FIELD>(sd, N, x, y);
-    const double c1 = E64[2 * y], s1 = E64[2 * y + 1];
-    double c = 1.0, sn = 0.0;
+  if (basis == B_SINE) {
+    // sin(pi (q+1)(y+1)/(N+1)), q = 0..15, by the same rotation recurrence
+    // started at the first harmonic; the odd (imaginary) columns stay zero
+    for (int y = lane; y < N; y += 64) {
+      const double v = row_field<FIELD>(sd, N, x, y);
+      double s1, c1;
+      sincospi((double)(y + 1) / (double)(N + 1), &s1, &c1);
+      double c = c1, sn = s1;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      acc[2 * q] += v * c;
-      acc[2 * q + 1] += v * sn;
-      const double cn = c * c1 - sn * s1;
-      sn = sn * c1 + c * s1;
-      c = cn;
+      for (int q = 0; q < 16; ++q) {
+        acc[2 * q] += v * sn;
+        const double cn = c * c1 - sn * s1;
+        sn = sn * c1 + c * s1;
+        c = cn;
+      }
+    }
+  } else {
+    // harmonics q = 0..15 of e^{2 pi i y / N} by complex-multiplication recurrence
+    for (int y = lane; y < N; y += 64) {
+      const double v = row_field<FIELD>(sd, N, x, y);
+      const double c1 = E64[2 * y], s1 = E64[2 * y + 1];
+      double c = 1.0, sn = 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        acc[2 * q] += v * c;
+        acc[2 * q + 1] += v * sn;
+        const double cn = c * c1 - sn * s1;
+        sn = sn * c1 + c * s1;
+        c = cn;
+      }
     }
   }
   double* out = (FIELD == 0 ? sd.Gr : out_base + out_sys_stride * blockIdx.y) + (size_t)x * MP;
@@ -189,8 +220,8 @@ __global__ __launch_bounds__(256) void k_rowdft(const SysDev* sys, int N, int M,
 // Per-solve constant part of the layer-0 spectrum:
 // Vc[c][a][ky] = sum_{f=1..3} W_L[c][f] DFT(phi_f) + b_L[c] DFT(1).
 template <int PREC>
-__global__ __launch_bounds__(256) void k_vconst(const SysDev* sys, int N, int M, int C, const double* E64,
-                                               const double* Gf, size_t gf_sys_stride,
+__global__ __launch_bounds__(256) void k_vconst(const SysDev* sys, int N, int M, int C, int basis,
+                                               const double* E64, const double* Gf, size_t gf_sys_stride,
                                                const double* WL, const double* bL) {
   using acc_t = typename Mf<PREC>::acc_t;
   __shared__ double Fr[4][32], Fi[4][32];
@@ -201,10 +232,13 @@ __global__ __launch_bounds__(256) void k_vconst(const SysDev* sys, int N, int M,
   const double* G = Gf + gf_sys_stride * blockIdx.y;
   for (int job = wv; job < 4 * twoM; job += 4) {
     const int f = job / twoM, a = job - f * twoM;
-    const int kv = a < M ? a : N - twoM + a;
+    // twiddle index tw_index(basis, N, M, a, x), stepped by 64 rows at a time
+    const int P = tw_period(basis, N);
+    const int kv = basis == B_SINE ? a + 1 : (a < M ? a : N - twoM + a);
+    const int xo = basis == B_SINE ? 1 : 0;
     double sr = 0.0, si = 0.0;
-    int idx = (int)(((long long)kv * lane) % N);
-    const int step = (int)(((long long)kv * 64) % N);
+    int idx = (int)(((long long)kv * (lane + xo)) % P);
+    const int step = (int)(((long long)kv * 64) % P);
     for (int x = lane; x < N; x += 64) {
       const double gc = G[((size_t)f * N + x) * MP + 2 * ky];
       const double gs = G[((size_t)f * N + x) * MP + 2 * ky + 1];
@@ -212,7 +246,7 @@ __global__ __launch_bounds__(256) void k_vconst(const SysDev* sys, int N, int M,
       sr += gc * c - gs * s;
       si -= gc * s + gs * c;
       idx += step;
-      if (idx >= N) idx -= N;
+      if (idx >= P) idx -= P;
     }
     sr = wave_sum(sr);
     si = wave_sum(si);
@@ -270,8 +304,7 @@ __global__ __launch_bounds__(256) void k_spec_fwd(SpecArgs a) {
   acc_t* Vp = (acc_t*)sd.Vp + ((size_t)(ky * a.XS + xs) * C) * twoM * 2;
   for (int q = t; q < twoM * SX; q += 256) {
     const int kx = q / SX, xl = q - kx * SX;
-    const int kv = kx < M ? kx : N - twoM + kx;
-    const int idx = (int)(((unsigned)kv * (unsigned)(x0 + xl)) % (unsigned)N);   // N^2 < 2^32
+    const int idx = (int)tw_index(a.basis, N, M, kx, x0 + xl);
     Er_[kx][xl] = E[2 * idx];
     Ei_[kx][xl] = -E[2 * idx + 1];
   }
@@ -424,8 +457,7 @@ __global__ __launch_bounds__(512) void k_spec_inv(SpecArgs a) {
   const int t = threadIdx.x, nt = blockDim.x;
   for (int q = t; q < SR * MP; q += nt) {
     const int xl = q / MP, kx = q - xl * MP;
-    const int kv = kx < M ? kx : N - twoM + kx;
-    const int idx = (int)(((unsigned)kv * (unsigned)(x0 + xl)) % (unsigned)N);   // N^2 < 2^32
+    const int idx = kx < twoM ? (int)tw_index(a.basis, N, M, kx, x0 + xl) : 0;
     Er_[xl][kx] = kx < twoM ? E[2 * idx] : (acc_t)0;
     Ei_[xl][kx] = kx < twoM ? E[2 * idx + 1] : (acc_t)0;
   }
@@ -441,7 +473,10 @@ __global__ __launch_bounds__(512) void k_spec_inv(SpecArgs a) {
       wr[kx] = Wh[2 * kx];
       wi[kx] = Wh[2 * kx + 1];
     }
-    const acc_t sc = a.unit_scale ? (acc_t)1 : (acc_t)((ky == 0 ? 1.0 : 2.0) * scale);
+    // inverse normalisation: Fourier N^-2 g_ky (g_0 = 1, else 2), sine (2/(N+1))^2
+    const acc_t sc = a.unit_scale ? (acc_t)1
+                     : a.basis == B_SINE ? (acc_t)(4.0 / ((double)(N + 1) * (double)(N + 1)))
+                                         : (acc_t)((ky == 0 ? 1.0 : 2.0) * scale);
     for (int xl = 0; xl < nx; ++xl) {
       acc_t hr = 0, hi = 0;
 #pragma unroll
@@ -769,8 +804,9 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
 
 template <int PREC>
 static void tables_p(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT) {
-  const int n = std::max(L.N, round16(L.N) * L.MP);
-  hipLaunchKernelGGL(k_tables<PREC>, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.N, L.M, E64, Eacc, T, TT);
+  const int n = std::max(tw_period(L.basis, L.N), round16(L.N) * L.MP);
+  hipLaunchKernelGGL(k_tables<PREC>, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.N, L.M, L.basis, E64, Eacc,
+                     T, TT);
 }
 
 void launch_tables(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT) {
@@ -786,11 +822,11 @@ static void setup_p(const NOLaunch& L, double* scratch) {
   hipLaunchKernelGGL(k_logk<PREC>, dim3((n + 255) / 256, L.nsys), dim3(256), 0, L.stream, L.sys, L.N);
   const dim3 rg((L.N + 3) / 4, L.nsys);
   const size_t fs = (size_t)L.N * L.MP;
-  hipLaunchKernelGGL(k_rowdft<1>, rg, dim3(256), 0, L.stream, L.sys, L.N, L.M, L.tab.E64, scratch + 0 * fs, stride);
-  hipLaunchKernelGGL(k_rowdft<2>, rg, dim3(256), 0, L.stream, L.sys, L.N, L.M, L.tab.E64, scratch + 1 * fs, stride);
-  hipLaunchKernelGGL(k_rowdft<3>, rg, dim3(256), 0, L.stream, L.sys, L.N, L.M, L.tab.E64, scratch + 2 * fs, stride);
-  hipLaunchKernelGGL(k_rowdft<4>, rg, dim3(256), 0, L.stream, L.sys, L.N, L.M, L.tab.E64, scratch + 3 * fs, stride);
-  hipLaunchKernelGGL(k_vconst<PREC>, dim3(L.M, L.nsys), dim3(256), 0, L.stream, L.sys, L.N, L.M, L.C,
+  hipLaunchKernelGGL(k_rowdft<1>, rg, dim3(256), 0, L.stream, L.sys, L.N, L.M, L.basis, L.tab.E64, scratch + 0 * fs, stride);
+  hipLaunchKernelGGL(k_rowdft<2>, rg, dim3(256), 0, L.stream, L.sys, L.N, L.M, L.basis, L.tab.E64, scratch + 1 * fs, stride);
+  hipLaunchKernelGGL(k_rowdft<3>, rg, dim3(256), 0, L.stream, L.sys, L.N, L.M, L.basis, L.tab.E64, scratch + 2 * fs, stride);
+  hipLaunchKernelGGL(k_rowdft<4>, rg, dim3(256), 0, L.stream, L.sys, L.N, L.M, L.basis, L.tab.E64, scratch + 3 * fs, stride);
+  hipLaunchKernelGGL(k_vconst<PREC>, dim3(L.M, L.nsys), dim3(256), 0, L.stream, L.sys, L.N, L.M, L.C, L.basis,
                      L.tab.E64, scratch, stride, L.WL, L.bL);
 }
 
@@ -840,12 +876,12 @@ static void apply_pc(const NOLaunch& L) {
   {
     ProfScope ps(PK_ROWDFT, L.stream);
     hipLaunchKernelGGL(k_rowdft<0>, dim3((L.N + 3) / 4, L.nsys), dim3(256), 0, L.stream, L.sys, L.N, L.M,
-                       L.tab.E64, (double*)nullptr, (size_t)0);
+                       L.basis, L.tab.E64, (double*)nullptr, (size_t)0);
   }
   for (int l = 0; l < L.L; ++l) {
     const int XS = (L.N + SX - 1) / SX;
     SpecArgs sa{L.sys, L.N, L.S, L.M, l == 0 ? 1 : 0, XS, L.nsys, L.tab.Eacc, L.tab.E64, L.Rmix[l], L.WL0,
-                L.vsave ? (char*)L.vsave + L.vs_layer * l * L.acc_bytes : nullptr, L.vs_sys, 0};
+                L.vsave ? (char*)L.vsave + L.vs_layer * l * L.acc_bytes : nullptr, L.vs_sys, 0, L.basis};
     {
       ProfScope ps(PK_SPECTRAL, L.stream);
       constexpr int SR = SynthRows<PREC>::SR;

@@ -58,6 +58,7 @@ struct BSpecArgs {
   size_t wh_sys;
   const void* Vsave;   // [B][M][C][2M] complex: V^ of this layer
   size_t vs_sys;
+  int basis;           // B_FOURIER or B_SINE
 };
 
 struct DeriveArgs {

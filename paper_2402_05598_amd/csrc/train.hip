@@ -323,7 +323,9 @@ __global__ __launch_bounds__(256) void k_bspec_mix(BSpecArgs a) {
   const int M = a.M, twoM = 2 * M, MP = round16_t(twoM);
   const int t = threadIdx.x;
   const acc_t* Vp = (const acc_t*)a.Vp + (size_t)b * a.vp_sys + (size_t)ky * a.XS * C * twoM * 2;
-  const acc_t sc = (acc_t)((ky == 0 ? 1.0 : 2.0) / ((double)a.N * (double)a.N));
+  // adjoint of the synthesis normalisation: Fourier N^-2 g_ky, sine (2/(N+1))^2
+  const acc_t sc = a.basis == B_SINE ? (acc_t)(4.0 / ((double)(a.N + 1) * (double)(a.N + 1)))
+                                     : (acc_t)((ky == 0 ? 1.0 : 2.0) / ((double)a.N * (double)a.N));
   acc_t* Gh = (acc_t*)a.Gh + (size_t)b * a.gh_sys + (size_t)ky * C * twoM * 2;
   for (int q = t; q < C * twoM; q += 256) {
     const int o = q / twoM, kx = q - o * twoM;

@@ -1,0 +1,134 @@
+"""The sine-basis (DST-I) operator through the C ABI against the oracle's
+sine-basis layers: operator outputs at several shapes and precisions (ragged
+tiles, several 64-row chunks, 2M = N), the FP64 backward against the oracle's
+autograd gradient (the imaginary spectral weights take no part and get zero
+gradient), and FP64 FCG residual histories up to the rounding horizon."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from _parity import shadow_horizon
+
+pytestmark = pytest.mark.gpu
+
+fc = pytest.importorskip("paper_2402_05598_amd")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _batch(seeds, N):
+    ks, fs, us = [], [], []
+    for s in seeds:
+        k, f, u0, _ = synth.system(s, N, (10.0, 1000.0))
+        ks.append(k); fs.append(f); us.append(u0)
+    return np.stack(ks), np.stack(fs), np.stack(us)
+
+
+def _blob(seed, C, M, L=4):
+    wb = synth.init_weights(seed, C, M, L)
+    wb[C * 4 + C:] *= 2.0   # a larger spectral part, so that the sine modes matter
+    return wb
+
+
+@pytest.mark.parametrize("N,C,M", [(32, 16, 8), (50, 32, 12), (24, 16, 12), (130, 16, 5)])
+def test_sine_precond_apply_matches_oracle(dev, N, C, M):
+    print(f"sine precond N={N} C={C} M={M}", flush=True)
+    k, f, _ = _batch([N * 5 + 1, N * 5 + 2], N)
+    wb = _blob(N + C, C, M)
+    w = oracle.unpack_weights(wb, C, M, basis="sine")
+    ref = oracle.no_apply(w, torch.from_numpy(k), torch.from_numpy(f)).numpy()
+    # the Fourier operator with the same weights differs: the basis is in effect
+    four = oracle.no_apply(oracle.unpack_weights(wb, C, M), torch.from_numpy(k), torch.from_numpy(f)).numpy()
+    assert np.linalg.norm(four - ref) > 1e-3 * np.linalg.norm(ref)
+    model = fc.Model(wb, C, M, basis="sine")
+    kt, ft = torch.from_numpy(k).to(dev), torch.from_numpy(f).to(dev)
+    for op, tol in (("fp64", 1e-12), ("fp32", 2e-5), ("bf16", 3e-2)):
+        got = fc.precond_apply(model, kt, ft, op=op).cpu().numpy()
+        for b in range(2):
+            rel = np.linalg.norm(got[b] - ref[b]) / np.linalg.norm(ref[b])
+            print(f"  {op} b={b} rel={rel:.3e}", flush=True)
+            assert rel < tol, (op, b, rel)
+    model.close()
+
+
+def _oracle_grad_sine(blob, C, M, L, fn):
+    t = torch.from_numpy(np.asarray(blob, dtype=np.float64)).clone()
+    o = 0
+    leaves = []
+
+    def take(n, shape):
+        nonlocal o
+        x = t[o:o + n].reshape(shape).clone().requires_grad_(True)
+        o += n
+        leaves.append(x)
+        return x
+    WL = take(C * 4, (C, 4)); bL = take(C, (C,))
+    R, W, b = [], [], []
+    nR = C * C * 2 * M * M
+    for _ in range(L):
+        re = take(nR, (C, C, 2 * M, M)); im = take(nR, (C, C, 2 * M, M))
+        R.append(torch.complex(re, im)); W.append(take(C * C, (C, C))); b.append(take(C, (C,)))
+    WP = take(C, (C,)); bP = take(1, (1,))
+    w = oracle.NOWeights(C, M, L, 4, WL, bL, R, W, b, WP, bP, "sine")
+    fn(w).backward()
+    return np.concatenate([(x.grad if x.grad is not None else torch.zeros_like(x)).reshape(-1).numpy()
+                           for x in leaves])
+
+
+@pytest.mark.parametrize("N,C,M,L", [(20, 16, 4, 2), (72, 16, 5, 2), (40, 32, 6, 3)])
+def test_sine_backward_matches_oracle_fp64(dev, N, C, M, L):
+    print(f"sine backward N={N} C={C} M={M} L={L}", flush=True)
+    B = 2
+    k, r, _ = _batch([70 + N, 71 + N], N)
+    g = synth.rng(9).standard_normal((B, N, N))
+    blob = _blob(N + L, C, M, L)
+    kt = torch.from_numpy(k)
+    gref = _oracle_grad_sine(blob, C, M, L,
+                             lambda w: torch.sum(torch.from_numpy(g) * oracle.no_apply(w, kt, torch.from_numpy(r))))
+    model = fc.Model(blob, C, M, L, basis="sine")
+    kd, rd, gd = [torch.from_numpy(a).to(dev) for a in (k, r, g)]
+    _, ws = fc.op_forward(model, kd, rd, "fp64")
+    ggpu = fc.op_backward(model, kd, rd, gd, ws, "fp64").cpu().numpy()
+    rel = np.linalg.norm(ggpu - gref) / np.linalg.norm(gref)
+    print(f"  grad rel err {rel:.2e}", flush=True)
+    assert rel < 1e-11
+    # the imaginary spectral weights receive exactly zero gradient
+    o = C * 4 + C
+    nR = C * C * 2 * M * M
+    for _ in range(L):
+        assert np.count_nonzero(ggpu[o + nR:o + 2 * nR]) == 0
+        o += 2 * nR + C * C + C
+    model.close()
+
+
+@pytest.mark.parametrize("N", [32, 45])
+def test_sine_fcg_fp64_matches_oracle(dev, N):
+    """FCG with the FP64 sine-basis operator: residual histories to 1e-10 up to
+    the rounding horizon, then the same stopping iteration."""
+    C, M = 16, 8
+    k, f, u0, _ = synth.system(N + 11, N)
+    wb = synth.init_weights(N + 3, C, M)
+    w = oracle.unpack_weights(wb, C, M, basis="sine")
+    B = lambda r: oracle.no_apply(w, torch.from_numpy(k), r)
+    ref, H = shadow_horizon(k, f, u0, B, 5, 400, 1e-6)
+    model = fc.Model(wb, C, M, basis="sine")
+    kt, ft, ut = [torch.from_numpy(a)[None].to(dev).contiguous() for a in (k, f, u0)]
+    out = fc.solve(model, kt, ft, ut, op="fp64", m_max=5, max_iter=400, rtol=1e-6)
+    n = min(H, ref.iters) + 1
+    got = out["hist"][0, :n]
+    rel = np.max(np.abs(got - np.array(ref.hist[:n])) / np.array(ref.hist[:n]))
+    print(f"sine fcg N={N} iters gpu={out['iters'][0]} oracle={ref.iters} status {out['status'][0]}/{ref.status} "
+          f"H={H} rel={rel:.2e}", flush=True)
+    assert H >= 5
+    assert rel < 1e-10
+    assert out["status"][0] == ref.status
+    if H >= ref.iters:
+        assert int(out["iters"][0]) == ref.iters
+    model.close()
