@@ -763,23 +763,25 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
   using full_t = std::integral_constant<bool, true>;
   using part_t = std::integral_constant<bool, false>;
   // Tiles t0 .. tf-1 hold 16 points each; at most one partial tile (the
-  // row's last, when 16 does not divide N) follows.  Full tiles keep two
-  // tiles in flight per wave: they alternate between two register sets, each
-  // refilled two tiles ahead of its use.
+  // row's last, when 16 does not divide N) follows.  Full tiles rotate
+  // through DEPTH register sets, each refilled DEPTH tiles ahead of its use:
+  // four for the inner bfloat16 layer (measured faster: its loads are the
+  // largest share of its time), two elsewhere (more sets cost more than they
+  // hide there).
+  constexpr int DEPTH = (PREC == PBF && !FEAT && !PROJ) ? 4 : 2;
   const int tf = min(t1, N >> 4);
-  TileIn ta, tb;
-  if (t0 < tf) load_tile(t0, ta, full_t{});
-  if (t0 + 1 < tf) load_tile(t0 + 1, tb, full_t{});
-  for (int t = t0; t < tf; t += 2) {
-    {
-      const TileIn cur = ta;
-      if (t + 2 < tf) load_tile(t + 2, ta, full_t{});
-      process(t, cur, full_t{});
-    }
-    if (t + 1 < tf) {
-      const TileIn cur = tb;
-      if (t + 3 < tf) load_tile(t + 3, tb, full_t{});
-      process(t + 1, cur, full_t{});
+  TileIn ring[DEPTH];
+#pragma unroll
+  for (int i = 0; i < DEPTH; ++i)
+    if (t0 + i < tf) load_tile(t0 + i, ring[i], full_t{});
+  for (int t = t0; t < tf; t += DEPTH) {
+#pragma unroll
+    for (int i = 0; i < DEPTH; ++i) {
+      if (t + i < tf) {
+        const TileIn cur = ring[i];
+        if (t + i + DEPTH < tf) load_tile(t + i + DEPTH, ring[i], full_t{});
+        process(t + i, cur, full_t{});
+      }
     }
   }
   if (tf < t1) {
