@@ -37,7 +37,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--n", type=int, default=512)
     p.add_argument("--batch", type=int, default=16)
-    p.add_argument("--train-steps", type=int, default=16000)
+    p.add_argument("--train-steps", type=int, default=48000)
     p.add_argument("--weights", default=None, help="load trained weights (.npy) instead of training")
     p.add_argument("--save-weights", default=None)
     p.add_argument("--ops", default="bf16,fp32,fp64", help="first one is the reported value")
@@ -564,7 +564,8 @@ def main():
     xres = None
     if args.cross_res:
         xres = cross_resolution(fc, torch, dev, C, M, L, main_op, logf,
-                                model64=model if train_info and train_info.get("grid") == 64 else None,
+                                model64=model if train_info and train_info.get("grid") == 64
+                                and train_info.get("steps") == 16000 else None,
                                 info64=train_info, sine=args.sine)
 
     classic = None

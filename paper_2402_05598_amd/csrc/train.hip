@@ -370,6 +370,7 @@ __global__ __launch_bounds__(256) void k_dR(BSpecArgs a, double* grad_re, double
   for (int q = t; q < C * C; q += 256) {
     const int c = q / C, o = q - c * C;
     double sr = 0.0, si = 0.0;
+#pragma unroll 8
     for (int b = 0; b < a.B; ++b) {
       const acc_t* G = (const acc_t*)a.Gh + (size_t)b * a.gh_sys + (size_t)ky * C * twoM * 2;
       const acc_t* V = (const acc_t*)a.Vsave + (size_t)b * a.vs_sys + (size_t)ky * C * twoM * 2;
@@ -396,7 +397,9 @@ __global__ __launch_bounds__(256) void k_reduce1(const acc_t* part, int nblk, in
   const int c = blockIdx.x * 64 + cl;
   const int q0 = blockIdx.y * qchunk, q1 = min(nblk, q0 + qchunk);
   double s = 0.0;
+  // unrolled so that the loads issue together; the sum keeps its order
   if (c < count)
+#pragma unroll 8
     for (int q = q0 + rg; q < q1; q += 4) s += (double)part[(size_t)q * count + c];
   lds[rg][cl] = s;
   __syncthreads();
@@ -408,6 +411,7 @@ __global__ __launch_bounds__(256) void k_reduce2(const double* stage, int nq, in
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= count) return;
   double s = 0.0;
+#pragma unroll 16
   for (int q = 0; q < nq; ++q) s += stage[(size_t)q * count + i];
   out[i] = s;
 }
