@@ -1,0 +1,94 @@
+"""Parity at the benchmark's full sizes, on sampled systems the oracle computes
+whole: the operator (width 32, 12 modes, 4 layers) on 512x512 x 16 systems in
+every precision and on 128x128 and 256x256 x 64 systems in FP32, and the first
+FCG iterations of the 512x512 x 16 batch in the launch configuration the
+benchmark times (m = 5, check every 4 iterations): FP64 residual histories to
+1e-10, the BF16 and FP32 operator's to their operator tolerance, the returned
+true residual recomputed on the CPU, and one system solved alone equal to the
+same system inside the batch."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+fc = pytest.importorskip("paper_2402_05598_amd")
+
+C, M, L = 32, 12, 4
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def weights():
+    wb = synth.init_weights(21, C, M, L)
+    return wb, oracle.unpack_weights(wb, C, M, L)
+
+
+@pytest.mark.parametrize("N,B,ops,sample", [(512, 16, ("fp64", "fp32", "bf16"), (0, 15)),
+                                            (128, 64, ("fp32",), (0, 37, 63)),
+                                            (256, 64, ("fp32",), (5, 63))])
+def test_operator_full_size_sampled(dev, weights, N, B, ops, sample):
+    print(f"full-size operator N={N} B={B}", flush=True)
+    wb, w = weights
+    k, f, _, _ = synth.batch(2, B, N, (10.0, 1000.0))
+    model = fc.Model(wb, C, M, L)
+    kd, fd = torch.from_numpy(k).to(dev), torch.from_numpy(f).to(dev)
+    refs = {b: oracle.no_apply(w, torch.from_numpy(k[b]), torch.from_numpy(f[b])).numpy() for b in sample}
+    for op in ops:
+        got = fc.precond_apply(model, kd, fd, op=op).cpu().numpy()
+        tol = {"fp64": 1e-12, "fp32": 2e-5, "bf16": 3e-2}[op]
+        for b in sample:
+            rel = np.linalg.norm(got[b] - refs[b]) / np.linalg.norm(refs[b])
+            print(f"  {op} b={b} rel={rel:.2e}", flush=True)
+            assert rel < tol, (op, b, rel)
+        assert np.all(np.isfinite(got))
+    model.close()
+
+
+def test_fcg_full_size_first_iterations(dev, weights):
+    """512x512 x 16, the benchmark's batch: 6 iterations (past one window
+    restart of m = 5) with check_every 4 as the benchmark runs it."""
+    N, B, its = 512, 16, 6
+    wb, w = weights
+    k, f, u0, _ = synth.batch(2, B, N, (10.0, 1000.0))
+    model = fc.Model(wb, C, M, L)
+    kd, fd = torch.from_numpy(k).to(dev), torch.from_numpy(f).to(dev)
+    sample = (3, 12)
+    refs = {}
+    for b in sample:
+        kt = torch.from_numpy(k[b])
+        refs[b] = oracle.fcg(k[b], f[b], u0[b], lambda r, kt=kt: oracle.no_apply(w, kt, r), m_max=5,
+                             max_iter=its, tol=1e-300)
+    for op, tol in (("fp64", 1e-10), ("fp32", 1e-4), ("bf16", 5e-2)):
+        print(f"full-size fcg op={op}", flush=True)
+        u = torch.from_numpy(u0).to(dev)
+        out = fc.solve(model, kd, fd, u, op=op, m_max=5, max_iter=its, rtol=1e-300, check_every=4)
+        assert np.all(out["iters"] == its)
+        for b in sample:
+            h = out["hist"][b, :its + 1]
+            hr = np.asarray(refs[b].hist)
+            rel = np.max(np.abs(h - hr) / hr)
+            print(f"  b={b} rel hist diff {rel:.2e}", flush=True)
+            assert rel < tol, (op, b, rel)
+            ub = u[b].cpu().numpy()
+            r0 = np.linalg.norm(f[b] - oracle.stencil_apply(k[b], u0[b]).numpy())
+            true = np.linalg.norm(f[b] - oracle.stencil_apply(k[b], ub).numpy()) / r0
+            assert abs(out["true_rel_res"][b] - true) <= 1e-9 * true
+        if op == "bf16":
+            # a system alone equals the same system inside the batch
+            b = sample[0]
+            u1 = torch.from_numpy(u0[b:b + 1]).to(dev)
+            one = fc.solve(model, kd[b:b + 1].contiguous(), fd[b:b + 1].contiguous(), u1, op=op, m_max=5,
+                           max_iter=its, rtol=1e-300, check_every=4)
+            assert torch.equal(u1[0], u[b])
+            assert np.array_equal(one["hist"][0], out["hist"][b])
+    model.close()
