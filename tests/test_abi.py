@@ -56,3 +56,24 @@ def test_classical_preconditioner_descriptors():
     extra = (b.solve_workspace_bytes(None, 32, 2, op="jacobi", precond_steps=4)
              - b.solve_workspace_bytes(None, 32, 2, op="sgs_rb", precond_steps=4))
     assert extra >= 2 * 32 * 32 * 8
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_solve_descriptor_validation():
+    """Empty and out-of-range descriptors are refused before any device work
+    (workspace size 0 and the reason in fcgno_last_error)."""
+    import paper_2402_05598_amd._binding as b
+    ok = dict(n=32, batch=2, op="identity", m_max=5, max_iter=100, rtol=1e-6)
+    assert b.solve_workspace_bytes(None, **{**ok, "n": 32}) > 0
+    bad = [dict(n=0), dict(batch=0), dict(m_max=0), dict(m_max=33), dict(max_iter=0), dict(rtol=0.0),
+           dict(rtol=-1.0), dict(rtol=float("nan")), dict(op="bf16"), dict(op="fp64")]
+    for d in bad:
+        assert b.solve_workspace_bytes(None, **{**ok, **d}) == 0, d
+    # the iteration history and window storage grow with max_iter and m_max
+    a = b.solve_workspace_bytes(None, **ok)
+    assert b.solve_workspace_bytes(None, **{**ok, "max_iter": 1000}) > a
+    assert b.solve_workspace_bytes(None, **{**ok, "m_max": 20}) > a
+    lib = b.lib()
+    d = b.SolveDesc(32, 2, 5, 100, 1e-6, 99, 0, 1)
+    assert lib.fcgno_solve_workspace_bytes(None, ctypes.byref(d)) == 0
+    assert b"unknown op" in lib.fcgno_last_error()
