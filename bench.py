@@ -63,6 +63,9 @@ def parse():
                         "iterations to 1e-3, 1e-6 and 1e-12 at grids 64..1024")
     p.add_argument("--sine", action="store_true",
                    help="with --cross-res: also train sine-basis operators at 32^2 and 64^2")
+    p.add_argument("--streams", type=int, default=4,
+                   help="also time the main operator with the batch split over this many streams "
+                        "(reported under comparison; 0 or 1 to skip)")
     p.add_argument("--log", default=None, help="progress log file (default: stderr)")
     return p.parse_args()
 
@@ -287,7 +290,7 @@ def cross_resolution(fc, torch, dev, C, M, L, main_op, logf, model64=None, info6
     return out
 
 
-def time_solves(fc, torch, model, kd, fd, u0d, op, steps, warmup, args, prof_kernels=None):
+def time_solves(fc, torch, model, kd, fd, u0d, op, steps, warmup, args, prof_kernels=None, streams=0):
     B = fd.shape[0]
     N = fd.shape[-1]
     ws = torch.empty(fc.solve_workspace_bytes(model, N, B, op, 5, args.max_iter, args.rtol),
@@ -296,7 +299,7 @@ def time_solves(fc, torch, model, kd, fd, u0d, op, steps, warmup, args, prof_ker
     outs = []
     for w in range(warmup):
         fc.solve(model, kd, fd, us[w], op=op, m_max=5, max_iter=args.max_iter, rtol=args.rtol,
-                 hist=False, workspace=ws)
+                 hist=False, workspace=ws, streams=streams)
     torch.cuda.synchronize()
     if prof_kernels:
         fc.profile_reset()
@@ -307,7 +310,7 @@ def time_solves(fc, torch, model, kd, fd, u0d, op, steps, warmup, args, prof_ker
     for s in range(steps):
         ts = time.perf_counter()
         outs.append(fc.solve(model, kd, fd, us[warmup + s], op=op, m_max=5, max_iter=args.max_iter,
-                             rtol=args.rtol, hist=False, workspace=ws))
+                             rtol=args.rtol, hist=False, workspace=ws, streams=streams))
         lat.append(time.perf_counter() - ts)   # the call returns after the batch completed
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
@@ -502,6 +505,19 @@ def main():
 
     main_op = ops[0]
     R = results[main_op]
+    if args.streams > 1:
+        # the same solves with the batch split over several streams (identical bits)
+        total, lat, outs, ulast, _ = time_solves(fc, torch, model, kd, fd, u0d, main_op, max(1, min(args.steps, 3)),
+                                                 1, args, None, streams=args.streams)
+        iters = np.concatenate([o["iters"] for o in outs])
+        status = np.concatenate([o["status"] for o in outs])
+        results[f"{main_op}_streams{args.streams}"] = {"seconds": total, "steps": len(outs), "lat": lat, "iters": iters,
+                                                       "status": status,
+                                                       "tres": np.concatenate([o["true_rel_res"] for o in outs]),
+                                                       "u": ulast}
+        assert np.array_equal(iters[-B:], R["iters"][-B:]) and torch.equal(ulast, R["u"]), \
+            "sub-batched solve differs from the single-stream solve"
+        log(f"op={main_op} streams={args.streams}: {len(outs)} solves in {total:.3f}s", logf)
     ms_per_step = R["seconds"] / R["steps"] * 1e3
     # solves that reached the tolerance, per second of the timed steps
     value = float((R["status"] == 0).sum()) / R["seconds"]

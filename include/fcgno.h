@@ -135,6 +135,11 @@ typedef struct {
     int32_t op;         /* FCGNO_OP_* */
     int32_t check_every;/* host polls convergence every this many iterations (0 = auto) */
     int32_t precond_steps; /* JACOBI / SGS_RB: sweeps per application, 1..1000 (ignored otherwise) */
+    int32_t streams;    /* 0 or 1: every launch on the caller's stream.  2..8: the batch is split
+                         * into that many contiguous sub-batches (at most one per system) that run
+                         * on library-owned streams forked from and joined back to the caller's
+                         * stream, so that one sub-batch's latency-bound kernels overlap another's
+                         * bandwidth-bound ones; results are bit-identical to one stream */
 } fcgno_solve_desc;
 
 /* Workspace bytes fcgno_solve needs for this model and descriptor

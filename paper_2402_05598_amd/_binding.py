@@ -30,7 +30,8 @@ BASIS = {"fourier": 0, "sine": 1}
 
 class SolveDesc(ctypes.Structure):
     _fields_ = [("n", c_int32), ("batch", c_int32), ("m_max", c_int32), ("max_iter", c_int32),
-                ("rtol", c_double), ("op", c_int32), ("check_every", c_int32), ("precond_steps", c_int32)]
+                ("rtol", c_double), ("op", c_int32), ("check_every", c_int32), ("precond_steps", c_int32),
+                ("streams", c_int32)]
 
 
 class EngineDesc(ctypes.Structure):
@@ -210,16 +211,18 @@ def solve_workspace_bytes(model, n, batch, op="bf16", m_max=5, max_iter=300, rto
 
 
 def solve(model, k, f, u, op="bf16", m_max=5, max_iter=300, rtol=1e-6, r_out=None, hist=True,
-          check_every=0, workspace=None, stream=None, precond_steps=1):
+          check_every=0, workspace=None, stream=None, precond_steps=1, streams=0):
     """Run Algorithm 1 on a batch: k [B][N+2][N+2], f [B][N][N], u [B][N][N]
     (in: u0, out: u_iter), all float64 device tensors.  op: a neural-operator
     precision, "identity" (CG) or a classical preconditioner ("jacobi",
-    "sgs_rb") applied precond_steps times.  Returns a dict with numpy arrays
-    iters, status, true_rel_res and (if hist) hist [B][max_iter+1]."""
+    "sgs_rb") applied precond_steps times.  streams > 1 splits the batch into
+    that many sub-batches on library-owned streams (same bits, overlapped
+    kernels).  Returns a dict with numpy arrays iters, status, true_rel_res
+    and (if hist) hist [B][max_iter+1]."""
     B, N = f.shape[0], f.shape[-1]
     if tuple(k.shape) != (B, N + 2, N + 2) or tuple(u.shape) != (B, N, N):
         raise FcgnoError("shape mismatch: k [B][N+2][N+2], f and u [B][N][N]")
-    d = SolveDesc(N, B, m_max, max_iter, rtol, OP[op], check_every, precond_steps)
+    d = SolveDesc(N, B, m_max, max_iter, rtol, OP[op], check_every, precond_steps, streams)
     h = model.handle if (model is not None and op not in MODEL_FREE) else None
     nbytes = lib().fcgno_solve_workspace_bytes(h, ctypes.byref(d))
     if nbytes == 0:

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -227,6 +228,8 @@ namespace {
 
 constexpr int KIND_SOLVE = 0, KIND_APPLY = 1, KIND_TRAIN = 2;
 
+constexpr int MAX_SUB = 8;   // sub-batches (streams) of one solve
+
 struct Plan {
   size_t total = 0;
   size_t sysdev = 0, state = 0, counter = 0, hist = 0, part = 0;
@@ -267,7 +270,7 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
   p.n_part_blocks = part_blocks(N);
   p.sysdev = cv.take((size_t)B * sizeof(SysDev));
   p.state = cv.take((size_t)B * sizeof(SysState));
-  p.counter = cv.take(sizeof(int));
+  p.counter = cv.take(MAX_SUB * sizeof(int));   // one active-system count per sub-batch
   p.part = cv.take((size_t)B * p.n_part_blocks * NQ * sizeof(double));
   if (kind == KIND_SOLVE) {
     p.hist = cv.take((size_t)B * (max_iter + 1) * sizeof(double));
@@ -404,6 +407,7 @@ fcgno_status check_desc(const fcgno_model* m, const fcgno_solve_desc* d) {
   if (d->op < 0 || d->op > PSGS) return fail(FCGNO_E_INVALID, "unknown op");
   if ((d->op == PJAC || d->op == PSGS) && (d->precond_steps < 1 || d->precond_steps > 1000))
     return fail(FCGNO_E_INVALID, "precond_steps must be in 1..1000 for JACOBI and SGS_RB");
+  if (d->streams < 0 || d->streams > MAX_SUB) return fail(FCGNO_E_INVALID, "streams must be in 0..8");
   if (is_no(d->op)) {
     if (!m) return fail(FCGNO_E_INVALID, "operator precision needs a model");
     if (!arch_ok_for(m, d->n)) return fail(FCGNO_E_INVALID, "need 2*modes <= n");
@@ -427,6 +431,43 @@ struct Record {
   const double* ustar;
 };
 
+// Library-owned streams for sub-batched solves: created on first use on each
+// device (non-blocking, default priority) and kept until the process ends.
+std::mutex g_sub_mutex;
+std::map<int, std::vector<hipStream_t>> g_sub_streams;
+
+fcgno_status sub_streams(int count, std::vector<hipStream_t>& out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_sub_mutex);
+  std::vector<hipStream_t>& v = g_sub_streams[dev];
+  while ((int)v.size() < count) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+      return fail(FCGNO_E_HIP, "stream creation failed");
+    v.push_back(st);
+  }
+  out.assign(v.begin(), v.begin() + count);
+  return FCGNO_OK;
+}
+
+// Events of one fork/join, destroyed on every return path.
+struct EventSet {
+  std::vector<hipEvent_t> ev;
+  fcgno_status make(int count) {
+    for (int i = 0; i < count; ++i) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+        return fail(FCGNO_E_HIP, "event creation failed");
+      ev.push_back(e);
+    }
+    return FCGNO_OK;
+  }
+  ~EventSet() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
 fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const double* k, const double* f,
                         double* u, double* r_out, int32_t* iters, int32_t* sys_status, double* rel_hist,
                         double* true_rel_res, void* ws, size_t ws_bytes, void* stream, const Record* rec) {
@@ -443,7 +484,13 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
   std::vector<SysDev> h(B);
   SysState* st = (SysState*)(base + p.state);
   int* counter = (int*)(base + p.counter);
+  // sub-batch g holds systems [b0[g], b0[g+1]) and counts its active systems in counter[g]
+  const int G = rec ? 1 : std::max(1, std::min(d->streams, B));
+  std::vector<int> b0(G + 1);
+  for (int g = 0; g <= G; ++g) b0[g] = (int)(((long long)g * B) / G);
+  int grp = 0;
   for (int b = 0; b < B; ++b) {
+    while (b >= b0[grp + 1]) ++grp;
     SysDev& sd = h[b];
     std::memset(&sd, 0, sizeof(SysDev));
     sd.k = (decltype(sd.k))(k + (size_t)b * (N + 2) * (N + 2));
@@ -456,14 +503,17 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
     sd.st = (decltype(sd.st))(st + b);
     sd.hist = (decltype(sd.hist))((double*)(base + p.hist) + (size_t)b * (d->max_iter + 1));
     sd.part = (decltype(sd.part))((double*)(base + p.part) + (size_t)b * p.n_part_blocks * NQ);
-    sd.n_active = (decltype(sd.n_active))(counter);
+    sd.n_active = (decltype(sd.n_active))(counter + grp);
     if (op == PJAC) sd.tmp = (decltype(sd.tmp))((double*)(base + p.tmp) + (size_t)b * n);
   }
   if (is_no(op)) fill_no(m, p, base, N, B, op, h);
   const SysDev* sysdev = (const SysDev*)(base + p.sysdev);
   HIPCHK(hipMemcpyAsync(base + p.sysdev, h.data(), B * sizeof(SysDev), hipMemcpyHostToDevice, s));
   KrylovLaunch KL{sysdev, B, N, d->m_max, s};
-  launch_init_state(KL, d->max_iter, d->rtol);
+  for (int g = 0; g < G; ++g) {
+    KrylovLaunch KLg{sysdev + b0[g], b0[g + 1] - b0[g], N, d->m_max, s};
+    launch_init_state(KLg, d->max_iter, d->rtol);
+  }
   NOLaunch NL{};
   if (is_no(op)) {
     NL = make_no(m, p, base, sysdev, N, B, op, s);
@@ -472,23 +522,94 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
   }
   launch_residual(KL, 0);
   HIPCHK(hipGetLastError());
+  // iterations: each sub-batch on its own stream (the caller's when G == 1)
+  std::vector<hipStream_t> ss(G, s);
+  EventSet events;
+  if (G > 1) {
+    fcgno_status es = sub_streams(G, ss);
+    if (es == FCGNO_OK) es = events.make(G + 1);
+    if (es != FCGNO_OK) return es;
+    HIPCHK(hipEventRecord(events.ev[G], s));
+    for (int g = 0; g < G; ++g) HIPCHK(hipStreamWaitEvent(ss[g], events.ev[G], 0));
+  }
+  std::vector<KrylovLaunch> KLs(G);
+  std::vector<NOLaunch> NLs(G, NL);
+  std::vector<int> nact(G), hn(G);
+  for (int g = 0; g < G; ++g) {
+    KLs[g] = KrylovLaunch{sysdev + b0[g], b0[g + 1] - b0[g], N, d->m_max, ss[g]};
+    NLs[g].sys = sysdev + b0[g];
+    NLs[g].nsys = b0[g + 1] - b0[g];
+    NLs[g].stream = ss[g];
+    nact[g] = b0[g + 1] - b0[g];
+  }
   const int K = d->check_every > 0 ? d->check_every : (N >= 256 ? 4 : 8);
-  int it = 0, nact = B;
+  // Sub-batches pay off while they keep many systems busy; once fewer than
+  // SUB_MIN_ACTIVE systems per sub-batch remain on average, the streams join
+  // and the rest of the solve runs as one launch sequence on the caller's
+  // stream (stopped systems leave their blocks at once, so this is exact).
+  constexpr int SUB_MIN_ACTIVE = 3;
+  bool split = G > 1;
+  NOLaunch NL1 = NL;
+  int it = 0;
   while (it < d->max_iter) {
     const int end = std::min(d->max_iter, it + K);
-    for (; it < end; ++it) {
-      if (is_no(op)) launch_no_apply(NL);
-      else if (op == PJAC) launch_jacobi(KL, d->precond_steps);
-      else if (op == PSGS) launch_rbsgs(KL, d->precond_steps);
-      launch_wdots(KL);
-      launch_dir(KL);
-      launch_update(KL);
-      if (rec && it < rec->m) launch_record(KL, it, rec->m, rec->rec_r, rec->rec_e, rec->ustar);
+    if (!split) {
+      for (int i = it; i < end; ++i) {
+        if (is_no(op)) launch_no_apply(NL1);
+        else if (op == PJAC) launch_jacobi(KL, d->precond_steps);
+        else if (op == PSGS) launch_rbsgs(KL, d->precond_steps);
+        launch_wdots(KL);
+        launch_dir(KL);
+        launch_update(KL);
+        if (rec && i < rec->m) launch_record(KL, i, rec->m, rec->rec_r, rec->rec_e, rec->ustar);
+      }
+      it = end;
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(hn.data(), counter, G * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      int total = 0;
+      for (int g = 0; g < G; ++g) total += std::max(hn[g], 0);
+      if (total <= 0) break;
+      continue;
     }
+    for (int g = 0; g < G; ++g) {
+      if (nact[g] <= 0) continue;
+      for (int i = it; i < end; ++i) {
+        if (is_no(op)) launch_no_apply(NLs[g]);
+        else if (op == PJAC) launch_jacobi(KLs[g], d->precond_steps);
+        else if (op == PSGS) launch_rbsgs(KLs[g], d->precond_steps);
+        launch_wdots(KLs[g]);
+        launch_dir(KLs[g]);
+        launch_update(KLs[g]);
+        if (rec && i < rec->m) launch_record(KLs[g], i, rec->m, rec->rec_r, rec->rec_e, rec->ustar);
+      }
+    }
+    it = end;
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(&nact, counter, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (nact <= 0) break;
+    for (int g = 0; g < G; ++g)
+      if (nact[g] > 0) HIPCHK(hipMemcpyAsync(&hn[g], counter + g, sizeof(int), hipMemcpyDeviceToHost, ss[g]));
+    int total = 0;
+    for (int g = 0; g < G; ++g) {
+      if (nact[g] <= 0) continue;
+      HIPCHK(hipStreamSynchronize(ss[g]));
+      nact[g] = hn[g];
+      total += std::max(nact[g], 0);
+    }
+    if (total <= 0) break;
+    if (total < SUB_MIN_ACTIVE * G) {
+      // join: the caller's stream continues after every sub-batch's work
+      for (int g = 0; g < G; ++g) {
+        HIPCHK(hipEventRecord(events.ev[g], ss[g]));
+        HIPCHK(hipStreamWaitEvent(s, events.ev[g], 0));
+      }
+      split = false;
+    }
+  }
+  if (split) {
+    for (int g = 0; g < G; ++g) {
+      HIPCHK(hipEventRecord(events.ev[g], ss[g]));
+      HIPCHK(hipStreamWaitEvent(s, events.ev[g], 0));
+    }
   }
   launch_residual(KL, 1);
   HIPCHK(hipGetLastError());

@@ -77,3 +77,12 @@ def test_solve_descriptor_validation():
     d = b.SolveDesc(32, 2, 5, 100, 1e-6, 99, 0, 1)
     assert lib.fcgno_solve_workspace_bytes(None, ctypes.byref(d)) == 0
     assert b"unknown op" in lib.fcgno_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_streams_field_range():
+    import paper_2402_05598_amd._binding as b
+    lib = b.lib()
+    for streams, ok in ((0, True), (1, True), (8, True), (9, False), (-1, False)):
+        d = b.SolveDesc(32, 4, 5, 100, 1e-6, b.OP["identity"], 0, 1, streams)
+        assert (lib.fcgno_solve_workspace_bytes(None, ctypes.byref(d)) > 0) == ok, streams
