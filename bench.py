@@ -489,9 +489,9 @@ def main():
     prof = None
     for j, op in enumerate(ops):
         steps = args.steps if j == 0 else max(1, min(args.steps, 2))
-        # only the roofline kernel carries events in the timed region (events
+        # only the layer kernel carries events in the timed region (events
         # around every kernel family cost about 8% of an iteration)
-        pk = ["layer"] if j == 0 else None
+        pk = ["layer"]
         total, lat, outs, ulast, pr = time_solves(fc, torch, model, kd, fd, u0d, op, steps,
                                                   args.warmup if j == 0 else 0, args, pk)
         if j == 0:
@@ -500,7 +500,7 @@ def main():
         status = np.concatenate([o["status"] for o in outs])
         tres = np.concatenate([o["true_rel_res"] for o in outs])
         results[op] = {"seconds": total, "steps": steps, "lat": lat, "iters": iters, "status": status,
-                       "tres": tres, "u": ulast}
+                       "tres": tres, "u": ulast, "prof": pr}
         log(f"op={op}: {steps} solves in {total:.3f}s, iters mean {iters.mean():.1f} max {iters.max()}, "
             f"status {np.bincount(status, minlength=4).tolist()}, true rel res max {tres.max():.2e}", logf)
 
@@ -558,7 +558,8 @@ def main():
     kinds = ["layer", "layer_feat", "layer_proj", "spectral", "rowdft", "wdots", "dir", "update"]
     fc.profile_reset()
     fc.profile_enable(True, kinds)
-    fc.solve(model, kd, fd, u0d.clone(), op=main_op, m_max=5, max_iter=args.max_iter, rtol=args.rtol, hist=False)
+    ob = fc.solve(model, kd, fd, u0d.clone(), op=main_op, m_max=5, max_iter=args.max_iter, rtol=args.rtol,
+                  hist=False)
     torch.cuda.synchronize()
     fc.profile_enable(False)
     per_kernel = {}
@@ -566,6 +567,39 @@ def main():
         n_, ms_ = fc.profile_read(name)
         per_kernel[name] = {"launches": n_, "avg_us": round(ms_ / max(n_, 1) * 1e3, 2)}
     per_kernel["note"] = "one untimed solve of the batch with events around every kernel family"
+    # Krylov kernels against HBM: algorithmic bytes per point of iteration i
+    # with window m_i (Algorithm 1) -- (w, s_k): 8(m_i + 1); direction and
+    # stencil: 8(m_i + 4); updates: 48 -- summed over every system's iterations
+    kry_bytes = {"wdots": 0, "dir": 0, "update": 0}
+    for itb in ob["iters"]:
+        for i in range(int(itb)):
+            mi = min(i, max(1, i % 6))
+            kry_bytes["wdots"] += 8 * (mi + 1)
+            kry_bytes["dir"] += 8 * (mi + 4)
+            kry_bytes["update"] += 48
+    krylov = {}
+    for name, bpp in kry_bytes.items():
+        n_, avg = per_kernel[name]["launches"], per_kernel[name]["avg_us"]
+        gbs = bpp * N * N / max(n_ * avg * 1e-6, 1e-30) / 1e9
+        krylov[name] = {"GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    per_kernel["krylov_hbm"] = krylov
+    # the operator against the matrix cores: algorithmic flops of an inner
+    # layer per point, y-synthesis 2(2M)C + bypass 2C^2 + next y-analysis 2(2M)C
+    flops_pt = 8 * M * C + 2 * C * C
+    mfma_peak = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
+    operator_util = {}
+    for op, Rr in results.items():
+        if op not in mfma_peak or "prof" not in Rr:
+            continue
+        n_l, ms_l = Rr["prof"]["layer"]
+        act = (L - 2) * int(Rr["iters"].sum()) / max(n_l, 1)
+        us = ms_l / max(n_l, 1) * 1e3
+        tf = flops_pt * N * N * act / (us * 1e-6) / 1e12
+        esz = {"bf16": 2, "fp32": 4, "fp64": 8}[op]
+        gbs = layer_bytes_per_launch(N, 1, C, M, esz, 8 if op == "fp64" else 4, S) * act / (us * 1e-6) / 1e9
+        operator_util[op] = {"inner_layer_avg_us": round(us, 2), "TFLOPs": round(tf, 1),
+                             "mfma_frac": round(tf / mfma_peak[op], 4), "GBs": round(gbs, 1),
+                             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "flops_per_point": flops_pt}
     comparison = {}
     ref = results.get("fp64")
     for op, Rr in results.items():
@@ -627,6 +661,7 @@ def main():
                        "per": "batched solve of all systems (each system's result is returned with the batch)"},
         "comparison": comparison,
         "kernels": per_kernel,
+        "operator_utilisation": operator_util,
         "training": train_info,
         "serving": serve,
         "ablation": abl,
