@@ -327,8 +327,8 @@ def serving(fc, torch, dev, model, n_req, logf):
     """Serving leg: requests with grids uniform over {64,...,1024}^2 (k
     contrast log-uniform in [10, 1e3], f ~ GRF, u0 ~ N(0, I)), BF16 operator,
     tol 1e-6, through the continuous-batching engine.  A closed-loop run (all
-    requests at t = 0) measures the saturation rate mu; an open-loop run with
-    Poisson arrivals at 0.7 mu measures latency under load."""
+    requests at t = 0) measures the saturation rate mu; open-loop runs with
+    Poisson arrivals at 0.5 mu and 0.9 mu measure latency under load."""
     import synth
     sizes = [64, 128, 256, 512, 1024]
     g = np.random.default_rng(4242)
@@ -370,28 +370,32 @@ def serving(fc, torch, dev, model, n_req, logf):
 
     t_closed, lat_c, conv_c, res_c = run(np.zeros(n_req))
     mu = n_req / t_closed
-    lam = 0.7 * mu
-    arr = np.cumsum(np.random.default_rng(4343).exponential(1.0 / lam, n_req))
-    arr -= arr[0]
-    t_open, lat_o, conv_o, _ = run(arr)
+    open_loop = {}
+    for load in (0.5, 0.9):
+        lam = load * mu
+        arr = np.cumsum(np.random.default_rng(4343).exponential(1.0 / lam, n_req))
+        arr -= arr[0]
+        t_open, lat_o, conv_o, _ = run(arr)
+        open_loop[f"{load:g}_mu"] = {"arrival_rate_per_sec": round(lam, 3), "seconds": round(t_open, 3),
+                                     "solves_per_sec": round(n_req / t_open, 3),
+                                     "converged_per_sec": round(float(conv_o.sum()) / t_open, 3),
+                                     "p50_ms": round(float(np.percentile(lat_o, 50)), 1),
+                                     "p99_ms": round(float(np.percentile(lat_o, 99)), 1)}
+        log(f"serving: open-loop at {lam:.2f}/s: {t_open:.2f}s p50 {np.percentile(lat_o, 50):.0f} ms "
+            f"p99 {np.percentile(lat_o, 99):.0f} ms", logf)
     by_n = {}
     for N in sizes:
         it = [res_c[i]["iters"] for i in range(n_req) if grids[i] == N]
         ok = [res_c[i]["status"] == 0 for i in range(n_req) if grids[i] == N]
         if it:
             by_n[str(N)] = {"requests": len(it), "converged": int(sum(ok)), "iters_median": float(np.median(it))}
-    log(f"serving: closed {t_closed:.2f}s mu={mu:.2f}/s; open-loop at {lam:.2f}/s: {t_open:.2f}s "
-        f"p50 {np.percentile(lat_o, 50):.0f} ms p99 {np.percentile(lat_o, 99):.0f} ms", logf)
+    log(f"serving: closed {t_closed:.2f}s mu={mu:.2f}/s", logf)
     return {"requests": n_req, "grids": sizes, "op": "bf16", "tol": 1e-6,
             "closed_loop": {"seconds": round(t_closed, 3), "solves_per_sec": round(mu, 3),
                             "converged_per_sec": round(float(conv_c.sum()) / t_closed, 3),
                             "p50_ms": round(float(np.percentile(lat_c, 50)), 1),
                             "p99_ms": round(float(np.percentile(lat_c, 99)), 1)},
-            "open_loop": {"arrival_rate_per_sec": round(lam, 3), "seconds": round(t_open, 3),
-                          "solves_per_sec": round(n_req / t_open, 3),
-                          "converged_per_sec": round(float(conv_o.sum()) / t_open, 3),
-                          "p50_ms": round(float(np.percentile(lat_o, 50)), 1),
-                          "p99_ms": round(float(np.percentile(lat_o, 99)), 1)},
+            "open_loop": open_loop,
             "by_grid": by_n}
 
 
