@@ -291,6 +291,50 @@ def cross_resolution(fc, torch, dev, C, M, L, main_op, logf, model64=None, info6
     return out
 
 
+def batched(fc, torch, dev, model, C, M, L, logf, steps=3):
+    """The batched configuration: 64 solves at 128^2 and at 256^2 (k = exp(GRF),
+    contrast 10..1e3), FP32 operator, FP64 Krylov, tol 1e-6, at most
+    max(2N, 300) iterations; one warm-up batch, then the timed batches."""
+    import synth
+    out = {}
+    for N in (128, 256):
+        k, f, u0, _ = synth.batch(1, 64, N, (10.0, 1000.0))
+        kd, fd, u0d = [torch.from_numpy(a).to(dev) for a in (k, f, u0)]
+        mi = max(2 * N, 300)
+        ws = torch.empty(fc.solve_workspace_bytes(model, N, 64, "fp32", 5, mi, 1e-6), dtype=torch.uint8, device=dev)
+        fc.solve(model, kd, fd, u0d.clone(), op="fp32", m_max=5, max_iter=mi, rtol=1e-6, hist=False, workspace=ws)
+        torch.cuda.synchronize()
+        fc.profile_reset()
+        fc.profile_enable(True, ["layer"])
+        lat, its, st = [], [], []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ts = time.perf_counter()
+            o = fc.solve(model, kd, fd, u0d.clone(), op="fp32", m_max=5, max_iter=mi, rtol=1e-6, hist=False,
+                         workspace=ws)
+            lat.append((time.perf_counter() - ts) * 1e3)
+            its.append(o["iters"])
+            st.append(o["status"])
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        fc.profile_enable(False)
+        n_l, ms_l = fc.profile_read("layer")
+        its, st = np.concatenate(its), np.concatenate(st)
+        act = (L - 2) * int(its.sum()) / max(n_l, 1)
+        us = ms_l / max(n_l, 1) * 1e3
+        tf = (8 * M * C + 2 * C * C) * N * N * act / (us * 1e-6) / 1e12
+        out[f"{N}x{N}x64"] = {"solves_per_sec": round(64 * steps / total, 2),
+                              "converged_per_sec": round(float((st == 0).sum()) / total, 2),
+                              "converged": int((st == 0).sum()), "of": int(st.size),
+                              "p50_ms": round(float(np.percentile(lat, 50)), 1),
+                              "p99_ms": round(float(np.percentile(lat, 99)), 1),
+                              "iters_median": float(np.median(its)), "iters_max": int(its.max()),
+                              "inner_layer_avg_us": round(us, 2), "inner_layer_TFLOPs": round(tf, 1),
+                              "inner_layer_mfma_frac": round(tf / 157.3, 4)}
+        log(f"batched {N}: {out[f'{N}x{N}x64']}", logf)
+    return out
+
+
 def time_solves(fc, torch, model, kd, fd, u0d, op, steps, warmup, args, prof_kernels=None, streams=0):
     B = fd.shape[0]
     N = fd.shape[-1]
@@ -624,6 +668,8 @@ def main():
             d["iters_diff_vs_fp64_op"] = (Rr["iters"][-B:] - ref["iters"][-B:]).tolist()
         comparison[op] = d
 
+    batch_cfg = batched(fc, torch, dev, model, C, M, L, logf)
+
     abl = None
     if args.ablation:
         abl = ablation(fc, torch, dev, C, M, L, args.ablation_steps, logf)
@@ -666,6 +712,7 @@ def main():
         "comparison": comparison,
         "kernels": per_kernel,
         "operator_utilisation": operator_util,
+        "batched_fp32": batch_cfg,
         "training": train_info,
         "serving": serve,
         "ablation": abl,
