@@ -495,7 +495,7 @@ def cpu_baseline(k, f, u0, blob, C, M, L, iters_needed, conv_frac, seconds, logf
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (this build has no "
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the library has no "
               "multi-GPU path; the batch of independent solves would shard by system).", file=sys.stderr)
         sys.exit(2)
     logf = open(args.log, "a") if args.log else None

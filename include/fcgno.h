@@ -143,7 +143,7 @@ typedef struct {
 } fcgno_solve_desc;
 
 /* Workspace bytes fcgno_solve needs for this model and descriptor
- * (model may be NULL when op is IDENTITY); 0 on invalid input. */
+ * (model may be NULL when op is IDENTITY, JACOBI or SGS_RB); 0 on invalid input. */
 size_t fcgno_solve_workspace_bytes(const fcgno_model* m, const fcgno_solve_desc* d);
 
 /* Solve, per system b, A_b u_b = f_b from u_b = u0_b.

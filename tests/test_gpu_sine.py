@@ -132,3 +132,34 @@ def test_sine_fcg_fp64_matches_oracle(dev, N):
     if H >= ref.iters:
         assert int(out["iters"][0]) == ref.iters
     model.close()
+
+
+def test_sine_engine_equals_solve(dev):
+    """The serving engine builds its per-grid tables in the model's basis: a
+    sine-basis request gives the same bits through the engine as through
+    fcgno_solve."""
+    C, M = 16, 6
+    model = fc.Model(_blob(77, C, M), C, M, basis="sine")
+    eng = fc.Engine(model, op="bf16", m_max=5, check_every=4, max_slots=4, budget_bytes=1 << 28)
+    jobs = {}
+    for i, N in enumerate((32, 48, 64)):
+        k, f, u0, _ = synth.system(900 + i, N, (10.0, 300.0))
+        kd, fd = torch.from_numpy(k).to(dev), torch.from_numpy(f).to(dev)
+        ue = torch.from_numpy(u0).to(dev)
+        jobs[eng.submit(kd, fd, ue, rtol=1e-6, max_iter=200)] = (kd, fd, u0, ue)
+    done = {}
+    steps = 0
+    while len(done) < len(jobs):
+        eng.step()
+        for r in eng.poll():
+            done[r["id"]] = r
+        steps += 1
+        assert steps < 1000
+    for jid, (kd, fd, u0, ue) in jobs.items():
+        us = torch.from_numpy(u0)[None].to(dev).contiguous()
+        out = fc.solve(model, kd[None].contiguous(), fd[None].contiguous(), us, op="bf16", m_max=5, max_iter=200,
+                       rtol=1e-6, hist=False)
+        assert int(out["iters"][0]) == done[jid]["iters"]
+        assert torch.equal(us[0], ue)
+    eng.close()
+    model.close()
