@@ -433,6 +433,8 @@ struct Record {
 
 // Library-owned streams for sub-batched solves: created on first use on each
 // device (non-blocking, default priority) and kept until the process ends.
+// Solves issued from several host threads on one device share them (their
+// sub-batches then run one after another on each stream).
 std::mutex g_sub_mutex;
 std::map<int, std::vector<hipStream_t>> g_sub_streams;
 
@@ -450,6 +452,17 @@ fcgno_status sub_streams(int count, std::vector<hipStream_t>& out) {
   out.assign(v.begin(), v.begin() + count);
   return FCGNO_OK;
 }
+
+// While a solve is forked, an early return (a failed HIP call) must not leave
+// work that reads the caller's buffers running on the library streams.
+struct ForkGuard {
+  const std::vector<hipStream_t>* ss = nullptr;
+  bool forked = false;
+  ~ForkGuard() {
+    if (forked)
+      for (hipStream_t st : *ss) (void)hipStreamSynchronize(st);
+  }
+};
 
 // Events of one fork/join, destroyed on every return path.
 struct EventSet {
@@ -525,11 +538,14 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
   // iterations: each sub-batch on its own stream (the caller's when G == 1)
   std::vector<hipStream_t> ss(G, s);
   EventSet events;
+  ForkGuard guard;
+  guard.ss = &ss;
   if (G > 1) {
     fcgno_status es = sub_streams(G, ss);
     if (es == FCGNO_OK) es = events.make(G + 1);
     if (es != FCGNO_OK) return es;
     HIPCHK(hipEventRecord(events.ev[G], s));
+    guard.forked = true;
     for (int g = 0; g < G; ++g) HIPCHK(hipStreamWaitEvent(ss[g], events.ev[G], 0));
   }
   std::vector<KrylovLaunch> KLs(G);
@@ -603,6 +619,7 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
         HIPCHK(hipStreamWaitEvent(s, events.ev[g], 0));
       }
       split = false;
+      guard.forked = false;
     }
   }
   if (split) {
@@ -610,6 +627,7 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
       HIPCHK(hipEventRecord(events.ev[g], ss[g]));
       HIPCHK(hipStreamWaitEvent(s, events.ev[g], 0));
     }
+    guard.forked = false;
   }
   launch_residual(KL, 1);
   HIPCHK(hipGetLastError());
