@@ -1,7 +1,7 @@
 // C ABI of libfcgno: model lifecycle, workspace planning, the FCG solve
-// driver (Algorithm 1), the standalone operator application and the training
-// entry points (forward with saved activations, hand-written backward, energy
-// loss, AdamW step).
+// driver (Algorithm 1), Krylov and residual samples, the standalone operator
+// application, error strings.  Training entry points are in train_api.hip,
+// the serving engine in serve.hip.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -13,85 +13,13 @@
 
 #include "common.h"
 #include "fcgno.h"
+#include "host.h"
 #include "prof.h"
 #include "train.h"
 
 using namespace fcgno;
+using namespace fcgno_host;
 
-namespace {
-
-thread_local std::string g_err;
-
-fcgno_status fail(fcgno_status s, const std::string& msg) {
-  g_err = msg;
-  return s;
-}
-
-#define HIPCHK(x)                                                                                    \
-  do {                                                                                               \
-    hipError_t e_ = (x);                                                                             \
-    if (e_ != hipSuccess) return fail(FCGNO_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-inline int round16(int v) { return (v + 15) & ~15; }
-inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-int op_esize(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
-int acc_esize(int prec) { return prec == P64 ? 8 : 4; }
-int kstep(int prec) { return prec == PBF ? 16 : 4; }
-
-struct Carver {
-  size_t n = 0;
-  size_t take(size_t bytes) {
-    size_t o = n;
-    n += align256(bytes);
-    return o;
-  }
-};
-
-// Offsets of the parameter groups in the float64 blob.
-struct BlobLayout {
-  size_t WL, bL, WP, bP, nR;
-  std::vector<size_t> Rre, Rim, W, b;
-  BlobLayout(int C, int M, int L) : Rre(L), Rim(L), W(L), b(L) {
-    nR = (size_t)C * C * 2 * M * M;
-    size_t o = 0;
-    WL = o; o += (size_t)C * 4;
-    bL = o; o += C;
-    for (int l = 0; l < L; ++l) {
-      Rre[l] = o; o += nR;
-      Rim[l] = o; o += nR;
-      W[l] = o; o += (size_t)C * C;
-      b[l] = o; o += C;
-    }
-    WP = o; o += C;
-    bP = o;
-  }
-};
-
-}  // namespace
-
-struct fcgno_model {
-  fcgno_arch arch{};
-  std::vector<double> w;       // host copy of the weights (refreshed lazily after training)
-  bool host_stale = false;
-  double* blob = nullptr;      // device float64 master weights, blob order
-  char* dev = nullptr;         // derived device arrays of every precision
-  size_t dev_bytes = 0;
-  int device = 0;
-  std::vector<const void*> Wfrag[3], bias[3], Rmix[3];
-  const void* WP[3] = {nullptr, nullptr, nullptr};
-  const void* WL0[3] = {nullptr, nullptr, nullptr};
-  DeriveArgs derive[3];
-};
-
-struct fcgno_optim {
-  size_t n = 0;
-  double lr = 1e-3, wd = 1e-2, b1 = 0.9, b2 = 0.999, eps = 1e-8;
-  long long t = 0;
-  double* m = nullptr;
-  double* v = nullptr;
-};
 
 extern "C" size_t fcgno_weight_count(const fcgno_arch* a) {
   if (!a || a->layers < 1 || a->width < 1 || a->modes < 1) return 0;
@@ -100,7 +28,7 @@ extern "C" size_t fcgno_weight_count(const fcgno_arch* a) {
 }
 
 // Lay out the derived arrays once; their contents come from the device blob.
-static fcgno_status alloc_derived(fcgno_model* m) {
+fcgno_status fcgno_host::alloc_derived(fcgno_model* m) {
   const int C = m->arch.width, M = m->arch.modes, L = m->arch.layers;
   Carver cv;
   struct Off { std::vector<size_t> Wf, bias, R; size_t WP, WL0; } off[3];
@@ -142,11 +70,11 @@ static fcgno_status alloc_derived(fcgno_model* m) {
 }
 
 // Derived arrays of every precision from the device blob (stream-ordered).
-static void derive_all(fcgno_model* m, hipStream_t s) {
+void fcgno_host::derive_all(fcgno_model* m, hipStream_t s) {
   for (int p = 0; p < 3; ++p) launch_derive(m->derive[p], p, s);
 }
 
-static fcgno_status upload_weights(fcgno_model* m) {
+fcgno_status fcgno_host::upload_weights(fcgno_model* m) {
   HIPCHK(hipMemcpy(m->blob, m->w.data(), m->w.size() * sizeof(double), hipMemcpyHostToDevice));
   derive_all(m, nullptr);
   HIPCHK(hipGetLastError());
@@ -155,9 +83,6 @@ static fcgno_status upload_weights(fcgno_model* m) {
   return FCGNO_OK;
 }
 
-static const double* dev_WL(const fcgno_model* m) { return m->blob; }
-static const double* dev_bL(const fcgno_model* m) { return m->blob + (size_t)m->arch.width * 4; }
-static const double* dev_bP(const fcgno_model* m) { return m->blob + m->w.size() - 1; }
 
 extern "C" fcgno_status fcgno_model_create(const fcgno_arch* arch, const double* weights_host,
                                            size_t n_weights, fcgno_model** out) {
@@ -187,7 +112,7 @@ extern "C" fcgno_status fcgno_model_create(const fcgno_arch* arch, const double*
   return FCGNO_OK;
 }
 
-static fcgno_status sync_host(const fcgno_model* mc) {
+fcgno_status fcgno_host::sync_host(const fcgno_model* mc) {
   fcgno_model* m = const_cast<fcgno_model*>(mc);
   if (!m->host_stale) return FCGNO_OK;
   HIPCHK(hipDeviceSynchronize());
@@ -224,25 +149,7 @@ extern "C" void fcgno_model_destroy(fcgno_model* m) {
 // ---------------------------------------------------------------------------
 // Workspace plans
 // ---------------------------------------------------------------------------
-namespace {
-
-constexpr int KIND_SOLVE = 0, KIND_APPLY = 1, KIND_TRAIN = 2;
-
-constexpr int MAX_SUB = 8;   // sub-batches (streams) of one solve
-
-struct Plan {
-  size_t total = 0;
-  size_t sysdev = 0, state = 0, counter = 0, hist = 0, part = 0;
-  size_t r = 0, w = 0, P = 0, S = 0, tmp = 0;
-  size_t act = 0, logk = 0, Gr = 0, Gp = 0, Hc = 0, Vc = 0, Wh = 0, Vp = 0;
-  size_t E64 = 0, Eacc = 0, T = 0, TT = 0;
-  size_t n_part_blocks = 0, gp_bytes_per_sys = 0, vp_bytes_per_sys = 0, wh_bytes_per_sys = 0;
-  int S_seg = 1, MP = 16, act_slots = 1;
-  // training
-  size_t z = 0, vsave = 0, tw = 0, gw = 0, dvec = 0, dzA = 0, dzB = 0, Gh = 0, gscale = 0, loss = 0, lpart = 0;
-  size_t pdW = 0, pdb = 0, pdWP = 0, pdbP = 0, pdWL = 0, pdbL = 0, grad = 0, rstage = 0;
-  int Sb = 1, nbs = 1, nblk = 1, loss_nb = 1;
-};
+namespace fcgno_host {
 
 size_t part_blocks(int N) {
   const size_t flat = ((size_t)N * N + FLAT_PTS - 1) / FLAT_PTS;
@@ -416,14 +323,14 @@ fcgno_status check_desc(const fcgno_model* m, const fcgno_solve_desc* d) {
   return FCGNO_OK;
 }
 
-}  // namespace
+}  // namespace fcgno_host
 
 extern "C" size_t fcgno_solve_workspace_bytes(const fcgno_model* m, const fcgno_solve_desc* d) {
   if (check_desc(m, d) != FCGNO_OK) return 0;
   return make_plan(m, d->n, d->batch, d->m_max, d->max_iter, d->op, KIND_SOLVE).total;
 }
 
-namespace {
+namespace fcgno_host {
 struct Record {
   int m;
   double* rec_r;
@@ -654,7 +561,7 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
   }
   return all_ok ? FCGNO_OK : FCGNO_NOT_CONVERGED;
 }
-}  // namespace
+}  // namespace fcgno_host
 
 extern "C" fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc* d, const double* k,
                                     const double* f, double* u, double* r_out, int32_t* iters,
@@ -747,7 +654,7 @@ extern "C" fcgno_status fcgno_residual_samples(int32_t N, int32_t B, int32_t max
 // ---------------------------------------------------------------------------
 // Operator application (and the training forward, which also saves z and V^)
 // ---------------------------------------------------------------------------
-namespace {
+namespace fcgno_host {
 
 fcgno_status operator_forward(const fcgno_model* m, const Plan& p, char* base, int N, int B, int op,
                               const double* k, const double* r, double* w, bool train, hipStream_t s) {
@@ -790,7 +697,7 @@ fcgno_status operator_forward(const fcgno_model* m, const Plan& p, char* base, i
   return FCGNO_OK;
 }
 
-}  // namespace
+}  // namespace fcgno_host
 
 extern "C" size_t fcgno_precond_workspace_bytes(const fcgno_model* m, int32_t n, int32_t batch, int32_t op) {
   if (!m || n < 1 || batch < 1 || op < 0 || op >= PID || !arch_ok_for(m, n)) return 0;
@@ -813,267 +720,6 @@ extern "C" fcgno_status fcgno_precond_apply(const fcgno_model* m, int32_t N, int
 // ---------------------------------------------------------------------------
 // Training
 // ---------------------------------------------------------------------------
-namespace {
-
-fcgno_status check_train(const fcgno_model* m, int N, int B, int op) {
-  if (!m) return fail(FCGNO_E_INVALID, "null model");
-  if (N < 1 || B < 1) return fail(FCGNO_E_INVALID, "n and batch must be >= 1");
-  if (op != P64 && op != P32) return fail(FCGNO_E_INVALID, "training runs in FP64 or FP32");
-  if (!arch_ok_for(m, N)) return fail(FCGNO_E_INVALID, "need 2*modes <= n");
-  return FCGNO_OK;
-}
-
-// Backward of the operator: upstream gradient gw [B][N^2] scaled per system by
-// gscale, with the forward state saved in the plan -> grad (float64 blob).
-fcgno_status operator_backward(const fcgno_model* m, const Plan& p, char* base, int N, int B, int op,
-                               const double* k, const double* r, const double* gw, const double* gscale,
-                               double* grad, hipStream_t s) {
-  const int C = m->arch.width, M = m->arch.modes, L = m->arch.layers, MP = p.MP;
-  const size_t n = (size_t)N * N;
-  const BlobLayout bl(C, M, L);
-  const SysDev* sysdev = (const SysDev*)(base + p.sysdev);
-  NOLaunch NL = make_no(m, p, base, sysdev, N, B, op, s);
-  NL.S = p.Sb;
-  const int asz = acc_esize(op);
-  BwdArgs a{};
-  a.N = N; a.M = M; a.MP = MP; a.L = L; a.nbs = p.nbs; a.S = p.Sb;
-  a.st = (const SysState*)(base + p.state);
-  a.gscale = gscale;
-  a.gw = gw;
-  a.r = r;
-  a.k = k;
-  a.z = base + p.z;
-  a.z_sys = n * C;
-  a.z_layer = (size_t)B * n * C;
-  a.act = base + p.act;
-  a.act_sys = n * C;
-  a.act_slot = (size_t)B * n * C;
-  a.Hcb = base + p.Hc;
-  a.hc_sys = (size_t)N * C * MP;
-  a.T = base + p.T;
-  a.blob = m->blob;
-  a.off_WP = bl.WP;
-  a.off_WL = bl.WL;
-  a.off_bL = bl.bL;
-  a.Gb = base + p.Gp;
-  a.gb_sys = p.gp_bytes_per_sys / asz;
-  a.pdW = base + p.pdW; a.pdb = base + p.pdb; a.pdWP = base + p.pdWP; a.pdbP = base + p.pdbP;
-  a.pdWL = base + p.pdWL; a.pdbL = base + p.pdbL;
-  void* dz[2] = {base + p.dzA, base + p.dzB};
-  double* rst = (double*)(base + p.rstage);
-  int cur = 0;
-  // start: projection, then the target layer L-1
-  a.mode = 0;
-  a.l = 0;
-  a.dz_in = nullptr;
-  a.dz_out = dz[cur];
-  launch_bwd(a, op, C, p.nblk, s);
-  launch_reduce(base + p.pdWP, op, p.nblk, C, grad + bl.WP, rst, s);
-  launch_reduce(base + p.pdbP, op, p.nblk, 1, grad + bl.bP, rst, s);
-  launch_reduce(base + p.pdW, op, p.nblk, C * C, grad + bl.W[L - 1], rst, s);
-  launch_reduce(base + p.pdb, op, p.nblk, C, grad + bl.b[L - 1], rst, s);
-  const int XS = (N + 63) / 64;
-  for (int l = L - 1; l >= 0; --l) {
-    // spectral adjoint of layer l from the row partials of dz_l
-    SpecArgs sa{sysdev, N, p.Sb, M, 0, XS, B, NL.tab.Eacc, NL.tab.E64, m->Rmix[op][l], m->WL0[op], nullptr, 0, 1,
-                NL.basis};
-    launch_spec_fwd(NL, sa);
-    BSpecArgs ba{};
-    ba.N = N; ba.M = M; ba.B = B; ba.XS = XS; ba.basis = NL.basis;
-    ba.Vp = base + p.Vp;
-    ba.vp_sys = p.vp_bytes_per_sys / asz;
-    ba.R = m->Rmix[op][l];
-    ba.Gh = base + p.Gh;
-    ba.gh_sys = (size_t)M * C * 2 * M * 2;
-    ba.Wh = base + p.Wh;
-    ba.wh_sys = p.wh_bytes_per_sys / asz;
-    ba.Vsave = base + p.vsave + (size_t)l * B * ba.gh_sys * asz;
-    ba.vs_sys = ba.gh_sys;
-    launch_bspec_mix(ba, op, C, s);
-    launch_dR(ba, op, C, grad + bl.Rre[l], grad + bl.Rim[l], s);
-    launch_spec_inv(NL, sa);
-    // dv_l, then the next target layer (or the lift)
-    a.mode = 1;
-    a.l = l;
-    a.off_W = bl.W[l];
-    a.dz_in = dz[cur];
-    a.dz_out = dz[1 - cur];
-    launch_bwd(a, op, C, p.nblk, s);
-    if (l >= 1) {
-      launch_reduce(base + p.pdW, op, p.nblk, C * C, grad + bl.W[l - 1], rst, s);
-      launch_reduce(base + p.pdb, op, p.nblk, C, grad + bl.b[l - 1], rst, s);
-    } else {
-      launch_reduce(base + p.pdWL, op, p.nblk, C * 4, grad + bl.WL, rst, s);
-      launch_reduce(base + p.pdbL, op, p.nblk, C, grad + bl.bL, rst, s);
-    }
-    cur = 1 - cur;
-  }
-  HIPCHK(hipGetLastError());
-  return FCGNO_OK;
-}
-
-}  // namespace
-
-extern "C" fcgno_status fcgno_optim_create(const fcgno_model* m, double lr, double weight_decay, double beta1,
-                                           double beta2, double eps, fcgno_optim** out) {
-  if (!m || !out) return fail(FCGNO_E_INVALID, "null argument");
-  if (!(lr > 0.0) || !(weight_decay >= 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
-      !(eps > 0.0))
-    return fail(FCGNO_E_INVALID, "invalid optimiser hyper-parameters");
-  fcgno_optim* o = new fcgno_optim();
-  o->n = m->w.size();
-  o->lr = lr; o->wd = weight_decay; o->b1 = beta1; o->b2 = beta2; o->eps = eps;
-  if (hipMalloc((void**)&o->m, o->n * 8) != hipSuccess || hipMalloc((void**)&o->v, o->n * 8) != hipSuccess ||
-      hipMemset(o->m, 0, o->n * 8) != hipSuccess || hipMemset(o->v, 0, o->n * 8) != hipSuccess) {
-    if (o->m) (void)hipFree(o->m);
-    if (o->v) (void)hipFree(o->v);
-    delete o;
-    return fail(FCGNO_E_HIP, "optimiser state allocation failed");
-  }
-  *out = o;
-  return FCGNO_OK;
-}
-
-extern "C" fcgno_status fcgno_optim_set_lr(fcgno_optim* o, double lr) {
-  if (!o || !(lr > 0.0)) return fail(FCGNO_E_INVALID, "invalid learning rate");
-  o->lr = lr;
-  return FCGNO_OK;
-}
-
-extern "C" void fcgno_optim_destroy(fcgno_optim* o) {
-  if (!o) return;
-  if (o->m) (void)hipFree(o->m);
-  if (o->v) (void)hipFree(o->v);
-  delete o;
-}
-
-extern "C" size_t fcgno_train_workspace_bytes(const fcgno_model* m, int32_t n, int32_t batch, int32_t op) {
-  if (check_train(m, n, batch, op) != FCGNO_OK) return 0;
-  return make_plan(m, n, batch, 1, 1, op, KIND_TRAIN).total;
-}
-
-extern "C" fcgno_status fcgno_op_forward(const fcgno_model* m, int32_t N, int32_t B, int32_t op, const double* k,
-                                         const double* r, double* w, void* ws, size_t ws_bytes, void* stream) {
-  fcgno_status cs = check_train(m, N, B, op);
-  if (cs != FCGNO_OK) return cs;
-  if (!k || !r || !w || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
-  const Plan p = make_plan(m, N, B, 1, 1, op, KIND_TRAIN);
-  if (ws_bytes < p.total) return fail(FCGNO_E_NOMEM, "workspace too small");
-  if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");
-  return operator_forward(m, p, (char*)ws, N, B, op, k, r, w, true, (hipStream_t)stream);
-}
-
-extern "C" fcgno_status fcgno_op_backward(const fcgno_model* m, int32_t N, int32_t B, int32_t op,
-                                          const double* k, const double* r, const double* grad_w,
-                                          double* grad_params, void* ws, size_t ws_bytes, void* stream) {
-  fcgno_status cs = check_train(m, N, B, op);
-  if (cs != FCGNO_OK) return cs;
-  if (!k || !r || !grad_w || !grad_params || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
-  const Plan p = make_plan(m, N, B, 1, 1, op, KIND_TRAIN);
-  if (ws_bytes < p.total) return fail(FCGNO_E_NOMEM, "workspace too small");
-  if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");
-  char* base = (char*)ws;
-  hipStream_t s = (hipStream_t)stream;
-  std::vector<double> ones(B, 1.0);
-  HIPCHK(hipMemcpyAsync(base + p.gscale, ones.data(), B * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(hipStreamSynchronize(s));
-  return operator_backward(m, p, base, N, B, op, k, r, grad_w, (const double*)(base + p.gscale), grad_params, s);
-}
-
-namespace {
-struct LossPlan {
-  size_t total, dvec, gw, part, gscale;
-  int nb;
-};
-LossPlan loss_plan(int N, int B) {
-  LossPlan lp{};
-  const size_t n = (size_t)N * N;
-  lp.nb = (int)((n + FLAT_PTS - 1) / FLAT_PTS);
-  Carver cv;
-  lp.dvec = cv.take(B * n * 8);
-  lp.gw = cv.take(B * n * 8);
-  lp.part = cv.take((size_t)B * lp.nb * 16);
-  lp.gscale = cv.take(B * 8);
-  lp.total = cv.n;
-  return lp;
-}
-}  // namespace
-
-extern "C" size_t fcgno_energy_loss_workspace_bytes(int32_t N, int32_t B) {
-  if (N < 1 || B < 1) return 0;
-  return loss_plan(N, B).total;
-}
-
-extern "C" fcgno_status fcgno_loss(int32_t kind, int32_t N, int32_t B, const double* k, const double* w,
-                                   const double* e, double* loss_dev, double* grad_w, void* ws, size_t ws_bytes,
-                                   void* stream) {
-  if (kind != FCGNO_LOSS_ENERGY && kind != FCGNO_LOSS_L2) return fail(FCGNO_E_INVALID, "unknown loss");
-  if (N < 1 || B < 1 || !k || !w || !e || !loss_dev || !ws) return fail(FCGNO_E_INVALID, "invalid argument");
-  const LossPlan lp = loss_plan(N, B);
-  if (ws_bytes < lp.total) return fail(FCGNO_E_NOMEM, "workspace too small");
-  if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");
-  char* base = (char*)ws;
-  hipStream_t s = (hipStream_t)stream;
-  double* gwbuf = grad_w ? grad_w : (double*)(base + lp.gw);
-  LossArgs la{N, B, lp.nb, k, w, e, (double*)(base + lp.dvec), gwbuf, (double*)(base + lp.part), loss_dev,
-              (double*)(base + lp.gscale), kind};
-  launch_loss(la, s);
-  if (grad_w) launch_scale_rows(grad_w, (const double*)(base + lp.gscale), B, (size_t)N * N, s);
-  HIPCHK(hipGetLastError());
-  return FCGNO_OK;
-}
-
-extern "C" fcgno_status fcgno_energy_loss(int32_t N, int32_t B, const double* k, const double* w, const double* e,
-                                          double* loss_dev, double* grad_w, void* ws, size_t ws_bytes,
-                                          void* stream) {
-  return fcgno_loss(FCGNO_LOSS_ENERGY, N, B, k, w, e, loss_dev, grad_w, ws, ws_bytes, stream);
-}
-
-extern "C" fcgno_status fcgno_train_step_loss(fcgno_model* m, fcgno_optim* opt, int32_t N, int32_t B, int32_t op,
-                                              int32_t loss_kind, const double* k, const double* r, const double* e,
-                                              double* loss_host, void* ws, size_t ws_bytes, void* stream) {
-  if (loss_kind != FCGNO_LOSS_ENERGY && loss_kind != FCGNO_LOSS_L2) return fail(FCGNO_E_INVALID, "unknown loss");
-  fcgno_status cs = check_train(m, N, B, op);
-  if (cs != FCGNO_OK) return cs;
-  if (!opt || !k || !r || !e || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
-  if (opt->n != m->w.size()) return fail(FCGNO_E_INVALID, "optimiser belongs to another architecture");
-  const Plan p = make_plan(m, N, B, 1, 1, op, KIND_TRAIN);
-  if (ws_bytes < p.total) return fail(FCGNO_E_NOMEM, "workspace too small");
-  if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");
-  char* base = (char*)ws;
-  hipStream_t s = (hipStream_t)stream;
-  double* w = (double*)(base + p.tw);
-  fcgno_status fs = operator_forward(m, p, base, N, B, op, k, r, w, true, s);
-  if (fs != FCGNO_OK) return fs;
-  LossArgs la{N, B, p.loss_nb, k, w, e, (double*)(base + p.dvec), (double*)(base + p.gw),
-              (double*)(base + p.lpart), (double*)(base + p.loss), (double*)(base + p.gscale), loss_kind};
-  launch_loss(la, s);
-  double* grad = (double*)(base + p.grad);
-  fs = operator_backward(m, p, base, N, B, op, k, r, (const double*)(base + p.gw),
-                         (const double*)(base + p.gscale), grad, s);
-  if (fs != FCGNO_OK) return fs;
-  opt->t += 1;
-  launch_adamw(m->blob, grad, opt->m, opt->v, opt->n, opt->lr, opt->wd, opt->b1, opt->b2, opt->eps, opt->t, s);
-  derive_all(m, s);
-  m->host_stale = true;
-  HIPCHK(hipGetLastError());
-  if (loss_host) {
-    std::vector<double> lb(B);
-    HIPCHK(hipMemcpyAsync(lb.data(), base + p.loss, B * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    double sum = 0.0;
-    for (int b = 0; b < B; ++b) sum += lb[b];
-    *loss_host = sum / B;
-  }
-  return FCGNO_OK;
-}
-
-extern "C" fcgno_status fcgno_train_step(fcgno_model* m, fcgno_optim* opt, int32_t N, int32_t B, int32_t op,
-                                         const double* k, const double* r, const double* e, double* loss_host,
-                                         void* ws, size_t ws_bytes, void* stream) {
-  return fcgno_train_step_loss(m, opt, N, B, op, FCGNO_LOSS_ENERGY, k, r, e, loss_host, ws, ws_bytes, stream);
-}
-
 extern "C" const char* fcgno_last_error(void) { return g_err.c_str(); }
 
 extern "C" const char* fcgno_status_string(fcgno_status s) {
@@ -1099,427 +745,3 @@ extern "C" const char* fcgno_status_string(fcgno_status s) {
 // system's arithmetic depends only on its own data and N, so its result is
 // the same bits alone and in any mix.
 // ---------------------------------------------------------------------------
-namespace {
-
-struct EngReq {
-  int64_t id = 0;
-  int N = 0, max_iter = 0;
-  double rtol = 0.0;
-  const double* k = nullptr;
-  const double* f = nullptr;
-  double* u = nullptr;
-  size_t off = 0, bytes = 0;
-  Plan p;
-  SysDev sd{};
-};
-
-struct EngGroup {
-  int N = 0;
-  size_t off = 0, bytes = 0;
-  size_t E64 = 0, Eacc = 0, T = 0, TT = 0, table = 0, ftable = 0, flags = 0, tres = 0;
-  std::vector<int64_t> members;
-  bool dirty = true;
-  size_t hoff = 0;           // this step's range in the engine's pinned export buffers
-  hipStream_t s = nullptr;   // the engine lane this group's work runs on
-};
-
-}  // namespace
-
-struct fcgno_engine {
-  const fcgno_model* m = nullptr;
-  fcgno_engine_desc d{};
-  hipStream_t s = nullptr;
-  char* pool = nullptr;
-  std::map<size_t, size_t> free_;       // offset -> size of free blocks
-  std::deque<EngReq> queue;
-  std::map<int64_t, EngReq> active;
-  std::map<int, EngGroup> groups;
-  std::vector<fcgno_engine_result> done;
-  int64_t next_id = 1;
-  int* hflags = nullptr;     // pinned host copies of the exported state, max_slots entries
-  double* htres = nullptr;
-  // Groups of different N run on separate streams (default priority), so a
-  // large group's bandwidth-bound launches and a small group's latency-bound
-  // ones overlap on the device; every step first waits for the caller's stream.
-  std::vector<hipStream_t> lanes;
-  hipEvent_t ready = nullptr;
-  int next_lane = 0;
-};
-
-namespace {
-
-bool pool_alloc(fcgno_engine* e, size_t bytes, size_t* off) {
-  bytes = align256(bytes);
-  for (auto it = e->free_.begin(); it != e->free_.end(); ++it) {
-    if (it->second >= bytes) {
-      *off = it->first;
-      const size_t rest = it->second - bytes;
-      const size_t roff = it->first + bytes;
-      e->free_.erase(it);
-      if (rest) e->free_[roff] = rest;
-      return true;
-    }
-  }
-  return false;
-}
-
-void pool_free(fcgno_engine* e, size_t off, size_t bytes) {
-  bytes = align256(bytes);
-  auto it = e->free_.emplace(off, bytes).first;
-  auto nx = std::next(it);
-  if (nx != e->free_.end() && it->first + it->second == nx->first) {
-    it->second += nx->second;
-    e->free_.erase(nx);
-  }
-  if (it != e->free_.begin()) {
-    auto pv = std::prev(it);
-    if (pv->first + pv->second == it->first) {
-      pv->second += it->second;
-      e->free_.erase(it);
-    }
-  }
-}
-
-size_t request_bytes(const fcgno_model* m, int op, int m_max, int N, int max_iter) {
-  return make_plan(op == PID ? nullptr : m, N, 1, m_max, max_iter, op, KIND_SOLVE).total;
-}
-
-size_t group_bytes(const fcgno_model* m, int op, int N, int slots, EngGroup* g) {
-  Carver cv;
-  const int MP = m && op != PID ? round16(2 * m->arch.modes) : 16, NP = round16(N);
-  const int esz = op_esize(op == PID ? P64 : op), asz = acc_esize(op == PID ? P64 : op);
-  EngGroup t;
-  t.E64 = cv.take((size_t)tw_period(m ? m->arch.basis : B_FOURIER, N) * 16);
-  t.Eacc = cv.take((size_t)tw_period(m ? m->arch.basis : B_FOURIER, N) * 2 * asz);
-  t.T = cv.take((size_t)NP * MP * esz);
-  t.TT = cv.take((size_t)MP * NP * esz);
-  t.table = cv.take((size_t)slots * sizeof(SysDev));
-  t.ftable = cv.take((size_t)slots * sizeof(SysDev));
-  t.flags = cv.take((size_t)slots * 3 * sizeof(int));
-  t.tres = cv.take((size_t)slots * sizeof(double));
-  if (g) {
-    g->E64 = t.E64; g->Eacc = t.Eacc; g->T = t.T; g->TT = t.TT;
-    g->table = t.table; g->ftable = t.ftable; g->flags = t.flags; g->tres = t.tres;
-  }
-  return cv.n;
-}
-
-NOLaunch group_no(const fcgno_engine* e, const EngGroup& g, const SysDev* table, int nsys) {
-  const fcgno_model* m = e->m;
-  const int op = e->d.op;
-  char* base = e->pool + g.off;
-  NOLaunch L{};
-  L.sys = table;
-  L.nsys = nsys;
-  L.N = g.N;
-  L.C = m->arch.width;
-  L.M = m->arch.modes;
-  L.MP = round16(2 * L.M);
-  L.L = m->arch.layers;
-  L.S = ((round16(g.N) / 16) + TPW - 1) / TPW;
-  L.prec = op;
-  L.basis = m->arch.basis;
-  L.tab.E64 = (const double*)(base + g.E64);
-  L.tab.Eacc = base + g.Eacc;
-  L.tab.T = base + g.T;
-  L.tab.TT = base + g.TT;
-  L.Wfrag = m->Wfrag[op].data();
-  L.bias = m->bias[op].data();
-  L.Rmix = m->Rmix[op].data();
-  L.WP = m->WP[op];
-  L.bP = dev_bP(m);
-  L.WL0 = m->WL0[op];
-  L.WL = dev_WL(m);
-  L.bL = dev_bL(m);
-  L.stream = g.s;
-  L.op_bytes = op_esize(op);
-  L.acc_bytes = acc_esize(op);
-  return L;
-}
-
-fcgno_status group_open(fcgno_engine* e, int N, EngGroup** out) {
-  auto it = e->groups.find(N);
-  if (it != e->groups.end()) {
-    *out = &it->second;
-    return FCGNO_OK;
-  }
-  EngGroup g;
-  g.N = N;
-  g.s = e->lanes[e->next_lane];
-  g.bytes = group_bytes(e->d.op == PID ? nullptr : e->m, e->d.op, N, e->d.max_slots, &g);
-  if (!pool_alloc(e, g.bytes, &g.off)) return FCGNO_E_NOMEM;
-  if (e->d.op != PID) {
-    const NOLaunch NL = group_no(e, g, nullptr, 0);
-    char* base = e->pool + g.off;
-    launch_tables(NL, (double*)(base + g.E64), base + g.Eacc, base + g.T, base + g.TT);
-  }
-  e->next_lane = (e->next_lane + 1) % (int)e->lanes.size();
-  auto res = e->groups.emplace(N, g);
-  *out = &res.first->second;
-  return FCGNO_OK;
-}
-
-void group_close(fcgno_engine* e, int N) {
-  auto it = e->groups.find(N);
-  if (it == e->groups.end()) return;
-  pool_free(e, it->second.off, it->second.bytes);
-  e->groups.erase(it);
-}
-
-// Set up one admitted request: state, operator inputs, r0 (all stream-ordered).
-fcgno_status admit(fcgno_engine* e, EngReq& q, EngGroup& g) {
-  const fcgno_model* m = e->d.op == PID ? nullptr : e->m;
-  const int N = q.N, op = e->d.op;
-  char* base = e->pool + q.off;
-  const size_t n = (size_t)N * N;
-  const Plan& p = q.p;
-  SysDev& sd = q.sd;
-  std::memset(&sd, 0, sizeof(SysDev));
-  sd.k = (decltype(sd.k))q.k;
-  sd.f = (decltype(sd.f))q.f;
-  sd.u = (decltype(sd.u))q.u;
-  sd.r = (decltype(sd.r))(base + p.r);
-  sd.w = op == PID ? sd.r : (decltype(sd.w))(base + p.w);
-  sd.P = (decltype(sd.P))(base + p.P);
-  sd.S = (decltype(sd.S))(base + p.S);
-  sd.st = (decltype(sd.st))(base + p.state);
-  sd.hist = (decltype(sd.hist))(base + p.hist);
-  sd.part = (decltype(sd.part))(base + p.part);
-  sd.n_active = (decltype(sd.n_active))(base + p.counter);
-  if (op != PID) {
-    std::vector<SysDev> h(1, sd);
-    fill_no(m, p, base, N, 1, op, h);
-    sd = h[0];
-  }
-  const SysDev* own = (const SysDev*)(base + p.sysdev);
-  HIPCHK(hipMemcpyAsync(base + p.sysdev, &sd, sizeof(SysDev), hipMemcpyHostToDevice, g.s));
-  KrylovLaunch KL{own, 1, N, e->d.m_max, g.s};
-  launch_init_state(KL, q.max_iter, q.rtol);
-  if (op != PID) {
-    HIPCHK(hipMemsetAsync(base + p.Hc, 0, (size_t)N * m->arch.width * p.MP * op_esize(op), g.s));
-    HIPCHK(hipMemsetAsync(base + p.Wh, 0, p.wh_bytes_per_sys, g.s));
-    NOLaunch NL = group_no(e, g, own, 1);
-    launch_no_setup(NL, (double*)(base + p.Gp));
-  }
-  launch_residual(KL, 0);
-  (void)n;
-  HIPCHK(hipGetLastError());
-  return FCGNO_OK;
-}
-
-fcgno_status upload_table(fcgno_engine* e, EngGroup& g, size_t where, const std::vector<int64_t>& ids) {
-  std::vector<SysDev> h;
-  h.reserve(ids.size());
-  for (int64_t id : ids) h.push_back(e->active.at(id).sd);
-  HIPCHK(hipMemcpyAsync(e->pool + g.off + where, h.data(), h.size() * sizeof(SysDev), hipMemcpyHostToDevice, g.s));
-  return FCGNO_OK;
-}
-
-}  // namespace
-
-extern "C" size_t fcgno_engine_request_bytes(const fcgno_model* m, const fcgno_engine_desc* d, int32_t n,
-                                             int32_t max_iter) {
-  if (!d || n < 1 || max_iter < 1 || d->m_max < 1 || d->m_max > MAXW) return 0;
-  if (d->op != PID && (!m || !arch_ok_for(m, n))) return 0;
-  return align256(request_bytes(m, d->op, d->m_max, n, max_iter));
-}
-
-extern "C" fcgno_status fcgno_engine_create(const fcgno_model* m, const fcgno_engine_desc* d, void* stream,
-                                            fcgno_engine** out) {
-  if (!d || !out) return fail(FCGNO_E_INVALID, "null argument");
-  if (d->op < 0 || d->op > PID) return fail(FCGNO_E_INVALID, "the engine takes FP64, FP32, BF16 or IDENTITY");
-  if (d->op != PID && !m) return fail(FCGNO_E_INVALID, "operator precision needs a model");
-  if (d->m_max < 1 || d->m_max > MAXW) return fail(FCGNO_E_INVALID, "m_max must be in 1..32");
-  if (d->max_slots < 1 || d->budget_bytes < 4096) return fail(FCGNO_E_INVALID, "need max_slots >= 1 and a budget");
-  fcgno_engine* e = new fcgno_engine();
-  e->m = m;
-  e->d = *d;
-  if (e->d.check_every <= 0) e->d.check_every = 8;
-  e->s = (hipStream_t)stream;
-  bool ok = hipEventCreateWithFlags(&e->ready, hipEventDisableTiming) == hipSuccess;
-  for (int i = 0; ok && i < 4; ++i) {
-    hipStream_t ls = nullptr;
-    ok = hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) == hipSuccess;
-    if (ok) e->lanes.push_back(ls);
-  }
-  if (!ok) {
-    for (hipStream_t ls : e->lanes) (void)hipStreamDestroy(ls);
-    if (e->ready) (void)hipEventDestroy(e->ready);
-    delete e;
-    return fail(FCGNO_E_HIP, "cannot create the engine's streams");
-  }
-  const size_t bytes = d->budget_bytes & ~(size_t)255;
-  fcgno_status st = FCGNO_OK;
-  if (hipMalloc((void**)&e->pool, bytes) != hipSuccess) {
-    e->pool = nullptr;
-    st = fail(FCGNO_E_NOMEM, "cannot allocate the engine pool");
-  } else if (hipHostMalloc((void**)&e->hflags, (size_t)d->max_slots * 3 * sizeof(int), 0) != hipSuccess ||
-             hipHostMalloc((void**)&e->htres, (size_t)d->max_slots * sizeof(double), 0) != hipSuccess) {
-    st = fail(FCGNO_E_HIP, "hipHostMalloc failed");
-  }
-  if (st != FCGNO_OK) {
-    if (e->hflags) (void)hipHostFree(e->hflags);
-    if (e->pool) (void)hipFree(e->pool);
-    for (hipStream_t ls : e->lanes) (void)hipStreamDestroy(ls);
-    (void)hipEventDestroy(e->ready);
-    delete e;
-    return st;
-  }
-  e->free_[0] = bytes;
-  *out = e;
-  return FCGNO_OK;
-}
-
-extern "C" fcgno_status fcgno_engine_submit(fcgno_engine* e, int32_t N, const double* k, const double* f, double* u,
-                                            double rtol, int32_t max_iter, int64_t* id_out) {
-  if (!e || !k || !f || !u || !id_out) return fail(FCGNO_E_INVALID, "null argument");
-  if (N < 1 || max_iter < 1 || !(rtol > 0.0) || !std::isfinite(rtol)) return fail(FCGNO_E_INVALID, "bad request");
-  if (e->d.op != PID && !arch_ok_for(e->m, N)) return fail(FCGNO_E_INVALID, "need 2*modes <= n");
-  EngReq q;
-  q.id = e->next_id++;
-  q.N = N;
-  q.max_iter = max_iter;
-  q.rtol = rtol;
-  q.k = k;
-  q.f = f;
-  q.u = u;
-  q.p = make_plan(e->d.op == PID ? nullptr : e->m, N, 1, e->d.m_max, max_iter, e->d.op, KIND_SOLVE);
-  q.bytes = q.p.total;
-  const size_t gb = group_bytes(e->d.op == PID ? nullptr : e->m, e->d.op, N, e->d.max_slots, nullptr);
-  if (align256(q.bytes) + align256(gb) > (e->d.budget_bytes & ~(size_t)255))
-    return fail(FCGNO_E_NOMEM, "request larger than the engine's HBM budget");
-  *id_out = q.id;
-  e->queue.push_back(q);
-  return FCGNO_OK;
-}
-
-extern "C" fcgno_status fcgno_engine_step(fcgno_engine* e, int32_t* n_active, int32_t* n_queued) {
-  if (!e) return fail(FCGNO_E_INVALID, "null engine");
-  // the caller's prior work on its stream (inputs of new requests) comes first
-  HIPCHK(hipEventRecord(e->ready, e->s));
-  for (hipStream_t ls : e->lanes) HIPCHK(hipStreamWaitEvent(ls, e->ready, 0));
-  // 1. admission: scan the queue in arrival order, admit what fits now
-  for (auto it = e->queue.begin(); it != e->queue.end();) {
-    if ((int)e->active.size() >= e->d.max_slots) break;
-    EngGroup* g = nullptr;
-    const bool had_group = e->groups.count(it->N) != 0;
-    if (group_open(e, it->N, &g) != FCGNO_OK) { ++it; continue; }
-    size_t off = 0;
-    if (!pool_alloc(e, it->bytes, &off)) {
-      if (!had_group && g->members.empty()) group_close(e, it->N);
-      ++it;
-      continue;
-    }
-    EngReq q = *it;
-    q.off = off;
-    it = e->queue.erase(it);
-    auto ins = e->active.emplace(q.id, q).first;
-    fcgno_status st = admit(e, ins->second, *g);
-    if (st != FCGNO_OK) return st;
-    g->members.push_back(q.id);
-    g->dirty = true;
-  }
-  // 2. advance every group by K iterations, then export the state summaries
-  const int K = e->d.check_every;
-  size_t ho = 0;
-  for (auto& kv : e->groups) {
-    EngGroup& g = kv.second;
-    const int G = (int)g.members.size();
-    if (G == 0) continue;
-    char* base = e->pool + g.off;
-    if (g.dirty) {
-      fcgno_status st = upload_table(e, g, g.table, g.members);
-      if (st != FCGNO_OK) return st;
-      g.dirty = false;
-    }
-    const SysDev* table = (const SysDev*)(base + g.table);
-    KrylovLaunch KL{table, G, g.N, e->d.m_max, g.s};
-    NOLaunch NL{};
-    if (e->d.op != PID) NL = group_no(e, g, table, G);
-    for (int i = 0; i < K; ++i) {
-      if (e->d.op != PID) launch_no_apply(NL);
-      launch_wdots(KL);
-      launch_dir(KL);
-      launch_update(KL);
-    }
-    launch_export(table, G, (int*)(base + g.flags), (double*)(base + g.tres), g.s);
-    g.hoff = ho;
-    HIPCHK(hipMemcpyAsync(e->hflags + 3 * ho, base + g.flags, (size_t)G * 3 * sizeof(int), hipMemcpyDeviceToHost,
-                          g.s));
-    ho += G;
-  }
-  HIPCHK(hipGetLastError());
-  for (hipStream_t ls : e->lanes) HIPCHK(hipStreamSynchronize(ls));
-  // 3. true residual of the requests that stopped, then release them
-  bool any = false;
-  std::map<int, std::vector<int64_t>> fin;
-  for (auto& kv : e->groups) {
-    EngGroup& g = kv.second;
-    for (size_t b = 0; b < g.members.size(); ++b)
-      if (e->hflags[3 * (g.hoff + b)] == 0) fin[kv.first].push_back(g.members[b]);
-  }
-  ho = 0;
-  for (auto& kv : fin) {
-    EngGroup& g = e->groups.at(kv.first);
-    char* base = e->pool + g.off;
-    const int F = (int)kv.second.size();
-    g.hoff = ho;
-    fcgno_status st = upload_table(e, g, g.ftable, kv.second);
-    if (st != FCGNO_OK) return st;
-    const SysDev* ft = (const SysDev*)(base + g.ftable);
-    KrylovLaunch KF{ft, F, g.N, e->d.m_max, g.s};
-    launch_residual(KF, 1);
-    launch_export(ft, F, (int*)(base + g.flags), (double*)(base + g.tres), g.s);
-    HIPCHK(hipMemcpyAsync(e->hflags + 3 * ho, base + g.flags, (size_t)F * 3 * sizeof(int), hipMemcpyDeviceToHost,
-                          g.s));
-    HIPCHK(hipMemcpyAsync(e->htres + ho, base + g.tres, (size_t)F * sizeof(double), hipMemcpyDeviceToHost, g.s));
-    ho += F;
-    any = true;
-  }
-  if (any) {
-    HIPCHK(hipGetLastError());
-    for (hipStream_t ls : e->lanes) HIPCHK(hipStreamSynchronize(ls));
-    for (auto& kv : fin) {
-      EngGroup& g = e->groups.at(kv.first);
-      for (size_t b = 0; b < kv.second.size(); ++b) {
-        const int64_t id = kv.second[b];
-        fcgno_engine_result r{};
-        r.id = id;
-        r.status = e->hflags[3 * (g.hoff + b) + 1];
-        r.iters = e->hflags[3 * (g.hoff + b) + 2];
-        r.true_rel_res = e->htres[g.hoff + b];
-        e->done.push_back(r);
-        EngReq& q = e->active.at(id);
-        pool_free(e, q.off, q.bytes);
-        e->active.erase(id);
-        g.members.erase(std::find(g.members.begin(), g.members.end(), id));
-        g.dirty = true;
-      }
-      if (g.members.empty()) group_close(e, kv.first);
-    }
-  }
-  if (n_active) *n_active = (int32_t)e->active.size();
-  if (n_queued) *n_queued = (int32_t)e->queue.size();
-  return FCGNO_OK;
-}
-
-extern "C" int32_t fcgno_engine_poll(fcgno_engine* e, fcgno_engine_result* out, int32_t max_results) {
-  if (!e || !out || max_results < 1) return 0;
-  const int32_t n = (int32_t)std::min<size_t>(e->done.size(), (size_t)max_results);
-  std::copy(e->done.begin(), e->done.begin() + n, out);
-  e->done.erase(e->done.begin(), e->done.begin() + n);
-  return n;
-}
-
-extern "C" void fcgno_engine_destroy(fcgno_engine* e) {
-  if (!e) return;
-  for (hipStream_t ls : e->lanes) {
-    (void)hipStreamSynchronize(ls);
-    (void)hipStreamDestroy(ls);
-  }
-  if (e->ready) (void)hipEventDestroy(e->ready);
-  (void)hipHostFree(e->hflags);
-  (void)hipHostFree(e->htres);
-  (void)hipFree(e->pool);
-  delete e;
-}
