@@ -462,12 +462,16 @@ def copy_bandwidth(torch, dev):
     return bw
 
 
-def cpu_baseline(k, f, u0, blob, C, M, L, iters_needed, conv_frac, seconds, logf):
+def cpu_baseline(k, f, u0, blob, C, M, L, iters_needed, conv_frac, seconds, logf, kb=None, fb=None,
+                 solutions=None):
     """The oracle (FP64 FCG with the FP64 operator) on system 0 of the batch,
     for as many iterations as fit in about ``seconds``; scaled to solves/sec
     with the iteration count the solve needs.  The oracle's time per
     iteration does not depend on the weight values; it runs with the seeded
-    initial weights."""
+    initial weights.  With ``solutions`` ({op: (u [B][N][N] device, status
+    [B])}), also the oracle's exact solution A^-1 f of two sampled systems
+    (those converged under every op, if any) and each op's relative error
+    against it, in the 2-norm and the energy norm."""
     import torch
     import oracle
     w = oracle.unpack_weights(blob, C, M, L)
@@ -485,8 +489,28 @@ def cpu_baseline(k, f, u0, blob, C, M, L, iters_needed, conv_frac, seconds, logf
     dt = time.perf_counter() - t0
     per_iter = dt / n_it
     log(f"cpu oracle: {n_it} iterations in {dt:.1f}s ({per_iter:.3f}s/iter)", logf)
+    accuracy = None
+    if solutions:
+        B = next(iter(solutions.values()))[1].shape[0]
+        ok_all = np.ones(B, dtype=bool)
+        for _, st in solutions.values():
+            ok_all &= st == 0
+        picks = [int(b) for b in np.nonzero(ok_all)[0][:2]] or [0, 1]
+        accuracy = {"systems": picks, "reference": "oracle exact solve A^-1 f (sparse direct, FP64)"}
+        for b in picks:
+            ustar = oracle.exact_solve(kb[b], fb[b])
+            kt_b = torch.from_numpy(kb[b])
+            en_star = float(oracle.energy_norm(kt_b, torch.from_numpy(ustar)))
+            for op, (u, st) in solutions.items():
+                ub = u[b].cpu().numpy()
+                d = ub - ustar
+                accuracy.setdefault(op, {})[str(b)] = {
+                    "status": int(st[b]),
+                    "rel_err_2": float(np.linalg.norm(d) / np.linalg.norm(ustar)),
+                    "rel_err_A": float(oracle.energy_norm(kt_b, torch.from_numpy(d))) / en_star}
+        log(f"accuracy vs oracle: {accuracy}", logf)
     return {"value": conv_frac / (per_iter * iters_needed), "unit": "solves/sec", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "accuracy_vs_oracle": accuracy,
             "sample": f"first {n_it} FCG iterations (FP64 operator, m=5) of system 0 of the batch, "
                       f"{per_iter:.3f} s/iteration, scaled by the {iters_needed} iterations the batch's "
                       f"FP64-operator solves took on average and by the fraction {conv_frac:.3f} of them "
@@ -698,8 +722,9 @@ def main():
         Rb = results.get("fp64", R)
         iters_needed = int(round(float(Rb["iters"].mean())))
         conv_frac = float((Rb["status"] == 0).mean())
+        sols = {op: (Rr["u"], Rr["status"][-B:]) for op, Rr in results.items() if op in ("bf16", "fp32", "fp64")}
         cpu = cpu_baseline(k[0], f[0], u0[0], synth.init_weights(3, C, M, L), C, M, L, iters_needed, conv_frac,
-                           args.cpu_seconds, logf)
+                           args.cpu_seconds, logf, kb=k, fb=f, solutions=sols)
 
     line = {
         "metric": "solves/sec to 1e-6 rel. residual, BF16-NO vs FP64 FCG-NO; p50/p99 latency",
