@@ -86,3 +86,26 @@ def test_streams_field_range():
     for streams, ok in ((0, True), (1, True), (8, True), (9, False), (-1, False)):
         d = b.SolveDesc(32, 4, 5, 100, 1e-6, b.OP["identity"], 0, 1, streams)
         assert (lib.fcgno_solve_workspace_bytes(None, ctypes.byref(d)) > 0) == ok, streams
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_status_strings_and_engine_footprint():
+    """Host-only entry points: every status has a name; the serving engine's
+    per-request footprint (the basis of admission) grows with the grid, the
+    iteration limit and the window, and is refused for invalid requests."""
+    import paper_2402_05598_amd._binding as b
+    lib = b.lib()
+    lib.fcgno_status_string.argtypes = [ctypes.c_int]
+    lib.fcgno_status_string.restype = ctypes.c_char_p
+    names = {s: lib.fcgno_status_string(s) for s in (0, 1, -1, -2, -3)}
+    assert all(names.values()) and len(set(names.values())) == 5
+    d = b.EngineDesc(b.OP["identity"], 5, 8, 16, 1 << 30)
+    f = lambda n, it: lib.fcgno_engine_request_bytes(None, ctypes.byref(d), n, it)
+    assert 0 < f(64, 300) < f(128, 300) < f(256, 300)
+    assert f(128, 300) < f(128, 3000)
+    d20 = b.EngineDesc(b.OP["identity"], 20, 8, 16, 1 << 30)
+    assert lib.fcgno_engine_request_bytes(None, ctypes.byref(d20), 128, 300) > f(128, 300)
+    assert f(0, 300) == 0 and f(64, 0) == 0
+    # a neural-operator request needs a model
+    dn = b.EngineDesc(b.OP["bf16"], 5, 8, 16, 1 << 30)
+    assert lib.fcgno_engine_request_bytes(None, ctypes.byref(dn), 64, 300) == 0
