@@ -156,7 +156,7 @@ def train_operator(fc, torch, dev, C, M, L, steps, logf, loss="energy", sampling
     opt.close()
     return model, {"grid": Nt, "systems": Bs, "lr": lr_first, "sampling": sampling, "loss": loss, "basis": basis,
                    "samples_per_system": m_iter, "batch": mb, "steps": steps,
-                   "seconds": round(dt, 2), "loss_first": round(losses[0], 4),
+                   "seconds": round(dt, 2), "steps_per_sec": round(steps / dt, 1), "loss_first": round(losses[0], 4),
                    "loss_last50": round(float(np.mean(losses[-50:])), 4)}
 
 
