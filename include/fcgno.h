@@ -226,12 +226,17 @@ fcgno_status fcgno_op_forward(const fcgno_model* m, int32_t n, int32_t batch, in
                               const double* k, const double* r, double* w,
                               void* ws, size_t ws_bytes, void* stream);
 
-/* Gradient of sum_b <grad_w_b, B(r_b)> with respect to the weights, written
- * to grad_params (device float64, blob order, every entry overwritten).
- * Must follow fcgno_op_forward with the same model, k, r and ws. */
+/* Gradient of L = sum_b <grad_w_b, B(r_b)> with respect to the weights,
+ * written to grad_params (device float64, blob order, every entry
+ * overwritten), and, if grad_r is not NULL, with respect to the input
+ * residuals: grad_r device [batch][N][N] float64 (B(r) = s NO(r/s),
+ * s = ||r||_2 / N, differentiated through s too; zero for r = 0, where B is
+ * not differentiable).  Must follow fcgno_op_forward with the same model, k,
+ * r and ws. */
 fcgno_status fcgno_op_backward(const fcgno_model* m, int32_t n, int32_t batch, int32_t op,
                                const double* k, const double* r, const double* grad_w,
-                               double* grad_params, void* ws, size_t ws_bytes, void* stream);
+                               double* grad_params, double* grad_r, void* ws, size_t ws_bytes,
+                               void* stream);
 
 /* Energy-norm loss per system, loss_dev[b] = ||w_b - e_b||_A / ||e_b||_A
  * (device [batch]), and if grad_w is not NULL the gradient of the batch mean,

@@ -89,7 +89,7 @@ def lib():
     L.fcgno_train_workspace_bytes.restype = c_size_t
     L.fcgno_op_forward.argtypes = [vp, c_int32, c_int32, c_int32, vp, vp, vp, vp, c_size_t, vp]
     L.fcgno_op_forward.restype = c_int32
-    L.fcgno_op_backward.argtypes = [vp, c_int32, c_int32, c_int32, vp, vp, vp, vp, vp, c_size_t, vp]
+    L.fcgno_op_backward.argtypes = [vp, c_int32, c_int32, c_int32, vp, vp, vp, vp, vp, vp, c_size_t, vp]
     L.fcgno_op_backward.restype = c_int32
     L.fcgno_energy_loss_workspace_bytes.argtypes = [c_int32, c_int32]
     L.fcgno_energy_loss_workspace_bytes.restype = c_size_t
@@ -340,15 +340,18 @@ def op_forward(model, k, r, op="fp64", workspace=None, stream=None):
     return w, ws
 
 
-def op_backward(model, k, r, grad_w, ws, op="fp64", stream=None):
-    """Gradient of sum <grad_w, B(r)> with respect to the weight blob (device float64)."""
+def op_backward(model, k, r, grad_w, ws, op="fp64", stream=None, input_grad=False):
+    """Gradient of sum <grad_w, B(r)> with respect to the weight blob (device
+    float64); with input_grad, also with respect to r: returns (g, g_r)."""
     B, N = r.shape[0], r.shape[-1]
     g = torch.empty(model.n_weights, dtype=torch.float64, device=r.device)
+    gr = torch.empty_like(r) if input_grad else None
     _check(lib().fcgno_op_backward(model.handle, N, B, OP[op], _dev_f64(k, "k"), _dev_f64(r, "r"),
                                    _dev_f64(grad_w.contiguous(), "grad_w"), _dev_f64(g, "grad"),
+                                   _dev_f64(gr, "grad_r") if input_grad else None,
                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
            "fcgno_op_backward")
-    return g
+    return (g, gr) if input_grad else g
 
 
 LOSS = {"energy": 0, "l2": 1}
@@ -482,7 +485,8 @@ class OperatorFunction(torch.autograd.Function):
     """w = B(r; theta) with the hand-written HIP backward for theta.
 
     ``weights`` is the float64 blob; it is loaded into ``model`` when it differs
-    from the model's current weights.  No gradient flows to k or r."""
+    from the model's current weights.  Gradients flow to the weights and to r
+    (not to k)."""
 
     @staticmethod
     def forward(ctx, weights, model, k, r, op="fp64"):
@@ -499,5 +503,8 @@ class OperatorFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_w):
         k, r = ctx.saved_tensors
-        g = op_backward(ctx.model, k, r, grad_w, ctx.ws, ctx.op)
-        return g.to(ctx.wdev), None, None, None, None
+        if ctx.needs_input_grad[3]:
+            g, gr = op_backward(ctx.model, k, r, grad_w, ctx.ws, ctx.op, input_grad=True)
+        else:
+            g, gr = op_backward(ctx.model, k, r, grad_w, ctx.ws, ctx.op), None
+        return g.to(ctx.wdev), None, None, gr, None

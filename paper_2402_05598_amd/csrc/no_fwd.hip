@@ -679,7 +679,13 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
 #pragma unroll
       for (int ob = 0; ob < NOB; ++ob)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) ot[M_::row(g, i) * (C + PADE) + ob * 16 + n16] = M_::cvt(acc[ob][i]);
+        for (int i = 0; i < 4; ++i) {
+          ot[M_::row(g, i) * (C + PADE) + ob * 16 + n16] = M_::cvt(acc[ob][i]);
+          // float32, width 16: the compiler merges these four stores into a
+          // paired LDS store with a wrong offset for the second row (seen in
+          // the generated assembly); a compiler barrier keeps them apart
+          if constexpr (PREC == P32 && C == 16) asm volatile("" ::: "memory");
+        }
       // compiler-only barrier: LDS operations of one wave complete in order,
       // so the reads below see the writes above without a wait instruction
       asm volatile("" ::: "memory");

@@ -45,6 +45,7 @@ struct BwdArgs {
   size_t gb_sys;
   // per-block partial gradients (accumulate precision)
   void* pdW; void* pdb; void* pdWP; void* pdbP; void* pdWL; void* pdbL;
+  double* dphi0;                      // nullable [B][N^2]: gradient w.r.t. the feature r/s (float64)
 };
 
 struct BSpecArgs {
@@ -75,6 +76,10 @@ void launch_loss(const LossArgs& a, hipStream_t s);
 void launch_bwd(const BwdArgs& a, int prec, int C, int nblk, hipStream_t s);
 void launch_bspec_mix(const BSpecArgs& a, int prec, int C, hipStream_t s);
 void launch_dR(const BSpecArgs& a, int prec, int C, double* gre, double* gim, hipStream_t s);
+// Gradient with respect to the input residual of L = sum_b <g_b, B(r_b)>,
+// from the feature gradient dphi0 (see k_grad_r).
+void launch_grad_r(int N, int B, const SysState* st, const double* r, const double* g, const double* w,
+                   const double* dphi0, double* grad_r, hipStream_t s);
 // stage: REDUCE_CHUNKS * count doubles of scratch
 constexpr int REDUCE_CHUNKS = 64;
 void launch_reduce(const void* part, int prec, int nblk, int count, double* out, double* stage, hipStream_t s);

@@ -296,6 +296,13 @@ __global__ void k_bwd(BwdArgs a) {
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) sA[t][c] = valid ? dv[c] : (acc_t)0;
+    if (a.dphi0 && valid) {
+      // gradient w.r.t. the first feature r/s: W_L[:, 0]^T dv0
+      double d = 0.0;
+#pragma unroll
+      for (int c = 0; c < C; ++c) d += blob[a.off_WL + c * 4] * (double)dv[c];
+      a.dphi0[(size_t)b * n + p] = d;
+    }
     __syncthreads();
     for (int q = t; q < C * 4; q += PB) {
       const int c = q / 4, f = q - c * 4;
@@ -383,6 +390,37 @@ __global__ __launch_bounds__(256) void k_dR(BSpecArgs a, double* grad_re, double
     grad_re[idx] = sr;
     grad_im[idx] = si;
   }
+}
+
+// Gradient of L = sum_p g_p w_p, w = B(r) = s NO(r/s), s = ||r||_2 / N, with
+// respect to r.  With D = dL/d(r/s) at fixed s (dphi0, from the backward
+// pass) and ds/dr = r / (N^2 s):
+//   dL/dr = D / s + r (sum_p g_p w_p / s - sum_p D_p r_p / s^2) / (N^2 s),
+// zero where s = 0 (B(0) = 0).  One block per system, fixed-order sums.
+__global__ __launch_bounds__(256) void k_grad_r(int N, const SysState* st, const double* r, const double* g,
+                                                 const double* w, const double* dphi0, double* grad_r) {
+  __shared__ double lds[4];
+  const size_t n = (size_t)N * N;
+  const size_t o = (size_t)blockIdx.x * n;
+  const double s = st[blockIdx.x].snorm;
+  double gw = 0.0, dr = 0.0;
+  for (size_t p = threadIdx.x; p < n; p += 256) {
+    gw += g[o + p] * w[o + p];
+    dr += dphi0[o + p] * r[o + p];
+  }
+  gw = block_sum(gw, lds);
+  dr = block_sum(dr, lds);
+  if (!(s > 0.0)) {
+    for (size_t p = threadIdx.x; p < n; p += 256) grad_r[o + p] = 0.0;
+    return;
+  }
+  const double coef = (gw / s - dr / (s * s)) / ((double)n * s);
+  for (size_t p = threadIdx.x; p < n; p += 256) grad_r[o + p] = dphi0[o + p] / s + r[o + p] * coef;
+}
+
+void launch_grad_r(int N, int B, const SysState* st, const double* r, const double* g, const double* w,
+                   const double* dphi0, double* grad_r, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_r, dim3(B), dim3(256), 0, s, N, st, r, g, w, dphi0, grad_r);
 }
 
 // Fixed-order reduction of per-block partials, out[i] = sum_blk part[blk][i],

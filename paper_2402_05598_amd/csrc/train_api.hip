@@ -28,10 +28,12 @@ fcgno_status check_train(const fcgno_model* m, int N, int B, int op) {
 }
 
 // Backward of the operator: upstream gradient gw [B][N^2] scaled per system by
-// gscale, with the forward state saved in the plan -> grad (float64 blob).
+// gscale, with the forward state saved in the plan -> grad (float64 blob);
+// with grad_r (gscale = 1, forward output saved in the plan's tw region) also
+// the gradient with respect to r.
 fcgno_status operator_backward(const fcgno_model* m, const Plan& p, char* base, int N, int B, int op,
                                const double* k, const double* r, const double* gw, const double* gscale,
-                               double* grad, hipStream_t s) {
+                               double* grad, hipStream_t s, double* grad_r = nullptr) {
   const int C = m->arch.width, M = m->arch.modes, L = m->arch.layers, MP = p.MP;
   const size_t n = (size_t)N * N;
   const BlobLayout bl(C, M, L);
@@ -43,6 +45,7 @@ fcgno_status operator_backward(const fcgno_model* m, const Plan& p, char* base, 
   a.N = N; a.M = M; a.MP = MP; a.L = L; a.nbs = p.nbs; a.S = p.Sb;
   a.st = (const SysState*)(base + p.state);
   a.gscale = gscale;
+  a.dphi0 = grad_r ? (double*)(base + p.dvec) : nullptr;
   a.gw = gw;
   a.r = r;
   a.k = k;
@@ -112,6 +115,9 @@ fcgno_status operator_backward(const fcgno_model* m, const Plan& p, char* base, 
     }
     cur = 1 - cur;
   }
+  if (grad_r)
+    launch_grad_r(N, B, (const SysState*)(base + p.state), r, gw, (const double*)(base + p.tw),
+                  (const double*)(base + p.dvec), grad_r, s);
   HIPCHK(hipGetLastError());
   return FCGNO_OK;
 }
@@ -164,12 +170,18 @@ extern "C" fcgno_status fcgno_op_forward(const fcgno_model* m, int32_t N, int32_
   const Plan p = make_plan(m, N, B, 1, 1, op, KIND_TRAIN);
   if (ws_bytes < p.total) return fail(FCGNO_E_NOMEM, "workspace too small");
   if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");
-  return operator_forward(m, p, (char*)ws, N, B, op, k, r, w, true, (hipStream_t)stream);
+  fcgno_status fs = operator_forward(m, p, (char*)ws, N, B, op, k, r, w, true, (hipStream_t)stream);
+  if (fs != FCGNO_OK) return fs;
+  // keep w for the input gradient of fcgno_op_backward
+  HIPCHK(hipMemcpyAsync((char*)ws + p.tw, w, (size_t)B * N * N * sizeof(double), hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream));
+  return FCGNO_OK;
 }
 
 extern "C" fcgno_status fcgno_op_backward(const fcgno_model* m, int32_t N, int32_t B, int32_t op,
                                           const double* k, const double* r, const double* grad_w,
-                                          double* grad_params, void* ws, size_t ws_bytes, void* stream) {
+                                          double* grad_params, double* grad_r, void* ws, size_t ws_bytes,
+                                          void* stream) {
   fcgno_status cs = check_train(m, N, B, op);
   if (cs != FCGNO_OK) return cs;
   if (!k || !r || !grad_w || !grad_params || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
@@ -181,7 +193,8 @@ extern "C" fcgno_status fcgno_op_backward(const fcgno_model* m, int32_t N, int32
   std::vector<double> ones(B, 1.0);
   HIPCHK(hipMemcpyAsync(base + p.gscale, ones.data(), B * 8, hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
-  return operator_backward(m, p, base, N, B, op, k, r, grad_w, (const double*)(base + p.gscale), grad_params, s);
+  return operator_backward(m, p, base, N, B, op, k, r, grad_w, (const double*)(base + p.gscale), grad_params, s,
+                           grad_r);
 }
 
 namespace fcgno_host {

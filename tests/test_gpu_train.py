@@ -155,10 +155,11 @@ def test_train_step_matches_oracle_adamw(dev):
     model.close()
 
 
-@pytest.mark.parametrize("N", [32, 136])
-def test_fp32_gradient_close_to_fp64(dev, N):
-    print(f"fp32 vs fp64 gradient N={N}", flush=True)
-    B, C, M, L = 2, 32, 6, 4
+# width 16 guards the pre-activation store of the float32 training forward
+@pytest.mark.parametrize("N,C", [(32, 32), (136, 32), (24, 16), (40, 16)])
+def test_fp32_gradient_close_to_fp64(dev, N, C):
+    print(f"fp32 vs fp64 gradient N={N} C={C}", flush=True)
+    B, M, L = 2, 6, 4
     k, r, _ = _data(N, B, 700)
     g = synth.rng(8).standard_normal((B, N, N))
     blob = synth.init_weights(31, C, M, L)
@@ -270,3 +271,43 @@ def test_residual_samples_match_oracle(dev):
         ee = oracle.exact_solve(k[b], f[b]) - u[b]
         assert np.linalg.norm(r[b] - rr) <= 1e-13 * np.linalg.norm(rr)
         assert np.linalg.norm(e[b] - ee) <= 1e-8 * np.linalg.norm(ee)
+
+
+@pytest.mark.parametrize("N,C,M,L", [(24, 16, 3, 2), (72, 16, 4, 2)])
+def test_op_backward_input_gradient(dev, N, C, M, L):
+    """d/dr of sum <g, B(r)> (B(r) = s NO(r/s), through s too) against the
+    oracle's autograd; Euler's identity for the degree-1 homogeneous operator,
+    sum_p r_p dL/dr_p = sum_p g_p B(r)_p; FP32 against FP64; and the
+    autograd Function delivers the same input gradient."""
+    print(f"input gradient N={N}", flush=True)
+    B = 2
+    k, r, _ = _data(N, B, 60 + N)
+    g = synth.rng(11).standard_normal((B, N, N))
+    blob = synth.init_weights(N + 5, C, M, L)
+    blob[C * 4 + C:] *= 2.0
+    w_o = oracle.unpack_weights(blob, C, M, L)
+    rt = torch.from_numpy(r).clone().requires_grad_(True)
+    val = torch.sum(torch.from_numpy(g) * oracle.no_apply(w_o, torch.from_numpy(k), rt))
+    val.backward()
+    gr_ref = rt.grad.numpy()
+    model = fc.Model(blob, C, M, L)
+    kd, rd, gd = [torch.from_numpy(a).to(dev) for a in (k, r, g)]
+    w64, ws = fc.op_forward(model, kd, rd, "fp64")
+    _, gr = fc.op_backward(model, kd, rd, gd, ws, "fp64", input_grad=True)
+    gr = gr.cpu().numpy()
+    rel = np.linalg.norm(gr - gr_ref) / np.linalg.norm(gr_ref)
+    print(f"  input grad rel err {rel:.2e}", flush=True)
+    assert rel < 1e-10
+    lhs = np.sum(r * gr, axis=(1, 2))
+    rhs = np.sum(g * w64.cpu().numpy(), axis=(1, 2))
+    assert np.max(np.abs(lhs - rhs) / np.abs(rhs)) < 1e-10
+    _, ws32 = fc.op_forward(model, kd, rd, "fp32")
+    _, gr32 = fc.op_backward(model, kd, rd, gd, ws32, "fp32", input_grad=True)
+    assert np.linalg.norm(gr32.cpu().numpy() - gr) / np.linalg.norm(gr) < 1e-4
+    # through the autograd Function
+    wts = torch.from_numpy(blob).to(dev)
+    ra = rd.clone().requires_grad_(True)
+    out = fc.OperatorFunction.apply(wts, model, kd, ra, "fp64")
+    torch.sum(gd * out).backward()
+    assert np.linalg.norm(ra.grad.cpu().numpy() - gr) / np.linalg.norm(gr) < 1e-12
+    model.close()
