@@ -154,11 +154,11 @@ __global__ void k_logk(const SysDev* sys, int N) {
   ((in_t*)sd.logk)[p] = M_::cvt((acc_t)log(sd.k[(i + 1) * (N + 2) + j + 1]));
 }
 
-// y-direction DFT of one row, float64: out[j] = sum_y field(y) T64[j](y) for
-// j < 2M, one wave per row.  FIELD 0: r.  FIELD 1..4: log k, x1, x2, 1.
+// y-direction DFT of one row of a per-solve feature, float64 (set-up only):
+// out[j] = sum_y field(y) T(y, j) for j < 2M, one wave per row.  FIELD 1..4:
+// log k, x1, x2, 1.
 template <int FIELD>
 __device__ __forceinline__ double row_field(const SysDev& sd, int N, int x, int y) {
-  if (FIELD == 0) return sd.r[x * N + y];
   if (FIELD == 1) return log(sd.k[(x + 1) * (N + 2) + y + 1]);
   if (FIELD == 2) return (double)(x + 1) / (double)(N + 1);
   if (FIELD == 3) return (double)(y + 1) / (double)(N + 1);
@@ -169,7 +169,6 @@ template <int FIELD>
 __global__ __launch_bounds__(256) void k_rowdft(const SysDev* sys, int N, int M, int basis, const double* E64,
                                                double* out_base, size_t out_sys_stride) {
   const SysDev sd = sys[blockIdx.y];
-  if (FIELD == 0 && !sd.st->active) return;
   const int x = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (x >= N) return;
   const int lane = threadIdx.x & 63;
@@ -209,11 +208,87 @@ __global__ __launch_bounds__(256) void k_rowdft(const SysDev* sys, int N, int M,
       }
     }
   }
-  double* out = (FIELD == 0 ? sd.Gr : out_base + out_sys_stride * blockIdx.y) + (size_t)x * MP;
+  double* out = out_base + out_sys_stride * blockIdx.y + (size_t)x * MP;
 #pragma unroll
   for (int q = 0; q < 32; ++q) {
     const double s = wave_sum(acc[q]);
     if (lane == 0 && q < 2 * M) out[q] = s;
+  }
+}
+
+// The row transform of r on the matrix cores, float64: Gr[x][k] =
+// sum_y r[x][y] T(y, k) for k < 2M, T as in the tables above.  A block covers
+// 16 rows; each of its eight waves takes an eighth of y (a 16 x 32 x Q product
+// in 16x16x4 steps) and the eight partial tiles are added through LDS in a
+// fixed order, so a system's result does not depend on the batch.  A wave
+// issues all loads of a 64-point chunk of y before its products, since the
+// launch is too small to hide memory latency by occupancy.  T is not read from
+// a table: each lane walks its two columns' twiddle index along y (index of
+// harmonic q at y: q y mod N, sine (q+1)(y+1) mod (2N+2)) and gathers from
+// E64, which stays in L1.
+constexpr int RD_WAVES = 8;   // the combine below adds eight partials; 512 threads = 16 rows x 32 columns
+__global__ __launch_bounds__(64 * RD_WAVES) void k_rowdft_r(const SysDev* sys, int N, int M, int basis,
+                                                            const double* E64) {
+  __shared__ double part[RD_WAVES][16][33];
+  const SysDev sd = sys[blockIdx.y];
+  if (!sd.st->active) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n16 = lane & 15, g = lane >> 4;
+  const int x0 = blockIdx.x * 16;
+  const int MP = round16(2 * M);
+  const int Q = (((N + RD_WAVES - 1) / RD_WAVES) + 3) & ~3;
+  const int ybeg = w * Q, yend = min(N, ybeg + Q);
+  const int xr = x0 + n16;
+  const bool rowok = xr < N;
+  const double* rrow = sd.r + (size_t)(rowok ? xr : 0) * N;
+  const bool sine = basis == B_SINE;
+  const unsigned P = (unsigned)tw_period(basis, N);
+  // this lane's two B columns k = cb*16 + n16: harmonic q = k/2, cosine or sine
+  unsigned idx[2], step[2];
+  int off[2];
+  bool keep[2];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const int k = cb * 16 + n16, q = k >> 1;
+    const unsigned qq = (unsigned)(sine ? q + 1 : q);
+    const unsigned y0 = (unsigned)(sine ? ybeg + g + 1 : ybeg + g);
+    idx[cb] = (qq * y0) % P;
+    step[cb] = (4u * qq) % P;
+    off[cb] = sine ? 0 : (k & 1);
+    keep[cb] = k < 2 * M && !(sine && (k & 1));
+  }
+  double4_t acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  constexpr int CH = 16;   // steps of 4 points per chunk
+  for (int yc = ybeg; yc < yend; yc += 4 * CH) {
+    double av[CH], bv[CH][2];
+#pragma unroll
+    for (int s = 0; s < CH; ++s) {
+      const int y = yc + 4 * s + g;
+      av[s] = (rowok && y < yend) ? rrow[y] : 0.0;
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        bv[s][cb] = keep[cb] ? E64[2 * idx[cb] + off[cb]] : 0.0;
+        idx[cb] += step[cb];
+        if (idx[cb] >= P) idx[cb] -= P;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < CH; ++s)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s][cb], acc[cb], 0, 0, 0);
+  }
+  // accumulator item i of lane (n16, g) holds row 4 i + g, column n16
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) part[w][4 * i + g][cb * 16 + n16] = acc[cb][i];
+  __syncthreads();
+  const int row = threadIdx.x >> 5, col = threadIdx.x & 31;
+  if (col < 2 * M && x0 + row < N) {
+    double v[RD_WAVES];
+#pragma unroll
+    for (int j = 0; j < RD_WAVES; ++j) v[j] = part[j][row][col];
+    sd.Gr[(size_t)(x0 + row) * MP + col] = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
   }
 }
 
@@ -883,8 +958,8 @@ template <int PREC, int C>
 static void apply_pc(const NOLaunch& L) {
   {
     ProfScope ps(PK_ROWDFT, L.stream);
-    hipLaunchKernelGGL(k_rowdft<0>, dim3((L.N + 3) / 4, L.nsys), dim3(256), 0, L.stream, L.sys, L.N, L.M,
-                       L.basis, L.tab.E64, (double*)nullptr, (size_t)0);
+    hipLaunchKernelGGL(k_rowdft_r, dim3((L.N + 15) / 16, L.nsys), dim3(64 * RD_WAVES), 0, L.stream, L.sys, L.N, L.M,
+                       L.basis, L.tab.E64);
   }
   for (int l = 0; l < L.L; ++l) {
     const int XS = (L.N + SX - 1) / SX;
