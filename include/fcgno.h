@@ -23,6 +23,9 @@
  *     memory of at least the queried size, 256-byte aligned; the library does
  *     not allocate per call.
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Sizes: N in 1..32768 and batch (or the engine's max_slots) in 1..65535
+ *     at every entry point; a solve also needs N^2 * batch <= 4e9.  Outside
+ *     these, workspace queries return 0 and calls return FCGNO_E_INVALID.
  *   - Nothing throws across the ABI and nothing aborts.  A negative status
  *     means the call did nothing useful and outputs are undefined; the text of
  *     the last error is available from fcgno_last_error().

@@ -307,7 +307,7 @@ fcgno_status operator_setup(const fcgno_model* m, const Plan& p, char* base, con
 
 fcgno_status check_desc(const fcgno_model* m, const fcgno_solve_desc* d) {
   if (!d) return fail(FCGNO_E_INVALID, "null descriptor");
-  if (d->n < 1 || d->batch < 1) return fail(FCGNO_E_INVALID, "n and batch must be >= 1");
+  if (check_sizes(d->n, d->batch) != FCGNO_OK) return FCGNO_E_INVALID;
   if (d->m_max < 1 || d->m_max > MAXW) return fail(FCGNO_E_INVALID, "m_max must be in 1..32");
   if (d->max_iter < 1) return fail(FCGNO_E_INVALID, "max_iter must be >= 1");
   if (!(d->rtol > 0.0) || !std::isfinite(d->rtol)) return fail(FCGNO_E_INVALID, "rtol must be > 0");
@@ -572,7 +572,7 @@ extern "C" fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc
 }
 
 extern "C" size_t fcgno_krylov_samples_workspace_bytes(int32_t n, int32_t batch, int32_t max_iter) {
-  if (n < 1 || batch < 1 || max_iter < 1) return 0;
+  if (!sizes_ok(n, batch) || max_iter < 1) return 0;
   const size_t sol = make_plan(nullptr, n, batch, 1, max_iter, PID, KIND_SOLVE).total;
   return sol + align256((size_t)batch * n * n * 8) * 2;
 }
@@ -580,7 +580,8 @@ extern "C" size_t fcgno_krylov_samples_workspace_bytes(int32_t n, int32_t batch,
 extern "C" fcgno_status fcgno_krylov_samples(int32_t N, int32_t B, int32_t m_iter, int32_t max_iter,
                                              const double* k, const double* f, const double* u0, double* r_out,
                                              double* e_out, void* ws, size_t ws_bytes, void* stream) {
-  if (N < 1 || B < 1 || m_iter < 1 || max_iter < 1 || !k || !f || !u0 || !r_out || !e_out || !ws)
+  if (check_sizes(N, B) != FCGNO_OK) return FCGNO_E_INVALID;
+  if (m_iter < 1 || max_iter < 1 || !k || !f || !u0 || !r_out || !e_out || !ws)
     return fail(FCGNO_E_INVALID, "invalid argument");
   if (ws_bytes < fcgno_krylov_samples_workspace_bytes(N, B, std::max(max_iter, m_iter)))
     return fail(FCGNO_E_NOMEM, "workspace too small");
@@ -610,7 +611,8 @@ extern "C" fcgno_status fcgno_krylov_samples(int32_t N, int32_t B, int32_t m_ite
 extern "C" fcgno_status fcgno_residual_samples(int32_t N, int32_t B, int32_t max_iter, const double* k,
                                                const double* f, const double* u, double* r_out, double* e_out,
                                                void* ws, size_t ws_bytes, void* stream) {
-  if (N < 1 || B < 1 || max_iter < 1 || !k || !f || !u || !r_out || !e_out || !ws)
+  if (check_sizes(N, B) != FCGNO_OK) return FCGNO_E_INVALID;
+  if (max_iter < 1 || !k || !f || !u || !r_out || !e_out || !ws)
     return fail(FCGNO_E_INVALID, "invalid argument");
   if (ws_bytes < fcgno_krylov_samples_workspace_bytes(N, B, max_iter))
     return fail(FCGNO_E_NOMEM, "workspace too small");
@@ -700,7 +702,7 @@ fcgno_status operator_forward(const fcgno_model* m, const Plan& p, char* base, i
 }  // namespace fcgno_host
 
 extern "C" size_t fcgno_precond_workspace_bytes(const fcgno_model* m, int32_t n, int32_t batch, int32_t op) {
-  if (!m || n < 1 || batch < 1 || op < 0 || op >= PID || !arch_ok_for(m, n)) return 0;
+  if (!m || !sizes_ok(n, batch) || op < 0 || op >= PID || !arch_ok_for(m, n)) return 0;
   return make_plan(m, n, batch, 1, 1, op, KIND_APPLY).total;
 }
 
@@ -708,7 +710,7 @@ extern "C" fcgno_status fcgno_precond_apply(const fcgno_model* m, int32_t N, int
                                             const double* k, const double* r, double* w, void* ws,
                                             size_t ws_bytes, void* stream) {
   if (!m || !k || !r || !w || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
-  if (N < 1 || B < 1) return fail(FCGNO_E_INVALID, "n and batch must be >= 1");
+  if (check_sizes(N, B) != FCGNO_OK) return FCGNO_E_INVALID;
   if (op < 0 || op >= PID) return fail(FCGNO_E_INVALID, "op must be FP64, FP32 or BF16");
   if (!arch_ok_for(m, N)) return fail(FCGNO_E_INVALID, "need 2*modes <= n");
   const Plan p = make_plan(m, N, B, 1, 1, op, KIND_APPLY);

@@ -30,6 +30,17 @@ inline fcgno_status fail(fcgno_status s, const std::string& msg) {
   } while (0)
 
 inline int round16(int v) { return (v + 15) & ~15; }
+
+// Size limits shared by every entry point: a system's grid indices are 32-bit
+// (N^2 < 2^31), twiddle-index products assume N <= 2^15, and the batch is a
+// grid dimension of the launches (at most 65535).
+constexpr int MAX_N = 32768;
+constexpr int MAX_BATCH = 65535;
+inline bool sizes_ok(long long N, long long B) { return N >= 1 && N <= MAX_N && B >= 1 && B <= MAX_BATCH; }
+inline fcgno_status check_sizes(long long N, long long B) {
+  if (!sizes_ok(N, B)) return fail(FCGNO_E_INVALID, "n must be in 1..32768 and batch in 1..65535");
+  return FCGNO_OK;
+}
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 inline int op_esize(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }

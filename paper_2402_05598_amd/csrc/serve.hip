@@ -238,7 +238,7 @@ fcgno_status upload_table(fcgno_engine* e, EngGroup& g, size_t where, const std:
 
 extern "C" size_t fcgno_engine_request_bytes(const fcgno_model* m, const fcgno_engine_desc* d, int32_t n,
                                              int32_t max_iter) {
-  if (!d || n < 1 || max_iter < 1 || d->m_max < 1 || d->m_max > MAXW) return 0;
+  if (!d || !sizes_ok(n, 1) || max_iter < 1 || d->m_max < 1 || d->m_max > MAXW) return 0;
   if (d->op != PID && (!m || !arch_ok_for(m, n))) return 0;
   return align256(request_bytes(m, d->op, d->m_max, n, max_iter));
 }
@@ -249,7 +249,8 @@ extern "C" fcgno_status fcgno_engine_create(const fcgno_model* m, const fcgno_en
   if (d->op < 0 || d->op > PID) return fail(FCGNO_E_INVALID, "the engine takes FP64, FP32, BF16 or IDENTITY");
   if (d->op != PID && !m) return fail(FCGNO_E_INVALID, "operator precision needs a model");
   if (d->m_max < 1 || d->m_max > MAXW) return fail(FCGNO_E_INVALID, "m_max must be in 1..32");
-  if (d->max_slots < 1 || d->budget_bytes < 4096) return fail(FCGNO_E_INVALID, "need max_slots >= 1 and a budget");
+  if (d->max_slots < 1 || d->max_slots > MAX_BATCH || d->budget_bytes < 4096)
+    return fail(FCGNO_E_INVALID, "need max_slots in 1..65535 and a budget");
   fcgno_engine* e = new fcgno_engine();
   e->m = m;
   e->d = *d;
@@ -292,7 +293,8 @@ extern "C" fcgno_status fcgno_engine_create(const fcgno_model* m, const fcgno_en
 extern "C" fcgno_status fcgno_engine_submit(fcgno_engine* e, int32_t N, const double* k, const double* f, double* u,
                                             double rtol, int32_t max_iter, int64_t* id_out) {
   if (!e || !k || !f || !u || !id_out) return fail(FCGNO_E_INVALID, "null argument");
-  if (N < 1 || max_iter < 1 || !(rtol > 0.0) || !std::isfinite(rtol)) return fail(FCGNO_E_INVALID, "bad request");
+  if (check_sizes(N, 1) != FCGNO_OK) return FCGNO_E_INVALID;
+  if (max_iter < 1 || !(rtol > 0.0) || !std::isfinite(rtol)) return fail(FCGNO_E_INVALID, "bad request");
   if (e->d.op != PID && !arch_ok_for(e->m, N)) return fail(FCGNO_E_INVALID, "need 2*modes <= n");
   EngReq q;
   q.id = e->next_id++;

@@ -21,7 +21,7 @@ namespace fcgno_host {
 
 fcgno_status check_train(const fcgno_model* m, int N, int B, int op) {
   if (!m) return fail(FCGNO_E_INVALID, "null model");
-  if (N < 1 || B < 1) return fail(FCGNO_E_INVALID, "n and batch must be >= 1");
+  if (check_sizes(N, B) != FCGNO_OK) return FCGNO_E_INVALID;
   if (op != P64 && op != P32) return fail(FCGNO_E_INVALID, "training runs in FP64 or FP32");
   if (!arch_ok_for(m, N)) return fail(FCGNO_E_INVALID, "need 2*modes <= n");
   return FCGNO_OK;
@@ -217,7 +217,7 @@ LossPlan loss_plan(int N, int B) {
 }  // namespace fcgno_host
 
 extern "C" size_t fcgno_energy_loss_workspace_bytes(int32_t N, int32_t B) {
-  if (N < 1 || B < 1) return 0;
+  if (!sizes_ok(N, B)) return 0;
   return loss_plan(N, B).total;
 }
 
@@ -225,7 +225,8 @@ extern "C" fcgno_status fcgno_loss(int32_t kind, int32_t N, int32_t B, const dou
                                    const double* e, double* loss_dev, double* grad_w, void* ws, size_t ws_bytes,
                                    void* stream) {
   if (kind != FCGNO_LOSS_ENERGY && kind != FCGNO_LOSS_L2) return fail(FCGNO_E_INVALID, "unknown loss");
-  if (N < 1 || B < 1 || !k || !w || !e || !loss_dev || !ws) return fail(FCGNO_E_INVALID, "invalid argument");
+  if (check_sizes(N, B) != FCGNO_OK) return FCGNO_E_INVALID;
+  if (!k || !w || !e || !loss_dev || !ws) return fail(FCGNO_E_INVALID, "invalid argument");
   const LossPlan lp = loss_plan(N, B);
   if (ws_bytes < lp.total) return fail(FCGNO_E_NOMEM, "workspace too small");
   if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");

@@ -109,3 +109,35 @@ def test_status_strings_and_engine_footprint():
     # a neural-operator request needs a model
     dn = b.EngineDesc(b.OP["bf16"], 5, 8, 16, 1 << 30)
     assert lib.fcgno_engine_request_bytes(None, ctypes.byref(dn), 64, 300) == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_size_limits_at_every_entry_point():
+    """Grids above 32768 per side or batches above 65535 are refused before any
+    device work: workspace queries give 0 and calls give FCGNO_E_INVALID with
+    the reason (the kernels index a system with 32-bit products and launch
+    one grid row per system)."""
+    import paper_2402_05598_amd._binding as b
+    lib = b.lib()
+    lib.fcgno_krylov_samples_workspace_bytes.restype = ctypes.c_size_t
+    lib.fcgno_energy_loss_workspace_bytes.restype = ctypes.c_size_t
+    lib.fcgno_krylov_samples.restype = ctypes.c_int
+    ok = dict(n=64, batch=2, op="identity", m_max=5, max_iter=100, rtol=1e-6)
+    assert b.solve_workspace_bytes(None, **ok) > 0
+    assert b.solve_workspace_bytes(None, **{**ok, "n": 32768, "batch": 1}) > 0
+    for d in (dict(n=32769, batch=1), dict(n=8, batch=65536)):
+        assert b.solve_workspace_bytes(None, **{**ok, **d}) == 0, d
+    assert lib.fcgno_krylov_samples_workspace_bytes(64, 2, 10) > 0
+    assert lib.fcgno_krylov_samples_workspace_bytes(32769, 1, 10) == 0
+    assert lib.fcgno_krylov_samples_workspace_bytes(8, 65536, 10) == 0
+    assert lib.fcgno_energy_loss_workspace_bytes(64, 2) > 0
+    assert lib.fcgno_energy_loss_workspace_bytes(32769, 1) == 0
+    assert lib.fcgno_energy_loss_workspace_bytes(8, 65536) == 0
+    # a call with sizes out of range fails on the host, before its pointers are used
+    vp = ctypes.c_void_p(1)
+    st = lib.fcgno_krylov_samples(ctypes.c_int32(32769), ctypes.c_int32(1), ctypes.c_int32(4), ctypes.c_int32(10),
+                                  vp, vp, vp, vp, vp, vp, ctypes.c_size_t(1 << 40), None)
+    assert st == -1 and b"32768" in lib.fcgno_last_error()
+    d = b.EngineDesc(b.OP["identity"], 5, 8, 16, 1 << 30)
+    f = lambda n: lib.fcgno_engine_request_bytes(None, ctypes.byref(d), n, 300)
+    assert f(64) > 0 and f(32769) == 0
