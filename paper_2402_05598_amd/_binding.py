@@ -148,6 +148,25 @@ def _dev_f64(t, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _grid(t, name, lead=1):
+    """(B, N) of a field [B][N][N] (lead=1) or [N][N] (lead=0), refusing any
+    other shape before a pointer reaches the library."""
+    if not isinstance(t, torch.Tensor) or t.dim() != 2 + lead or t.shape[-1] != t.shape[-2]:
+        want = "[B][N][N]" if lead else "[N][N]"
+        raise FcgnoError(f"{name} must have shape {want}, got {tuple(getattr(t, 'shape', ()))}")
+    return (t.shape[0] if lead else 1), t.shape[-1]
+
+
+def _same(t, shape, name):
+    """Refuse a tensor that does not have exactly this shape."""
+    if not isinstance(t, torch.Tensor) or tuple(t.shape) != tuple(shape):
+        raise FcgnoError(f"{name} must have shape {tuple(shape)}, got {tuple(getattr(t, 'shape', ()))}")
+
+
+def _nbytes(ws):
+    return ws.numel() * ws.element_size()
+
+
 def _stream(stream):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -155,7 +174,7 @@ def _stream(stream):
 
 def _workspace(nbytes, device, workspace):
     if workspace is not None:
-        if workspace.numel() * workspace.element_size() < nbytes:
+        if _nbytes(workspace) < nbytes:
             raise FcgnoError("workspace too small")
         return workspace
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
@@ -219,9 +238,11 @@ def solve(model, k, f, u, op="bf16", m_max=5, max_iter=300, rtol=1e-6, r_out=Non
     that many sub-batches on library-owned streams (same bits, overlapped
     kernels).  Returns a dict with numpy arrays iters, status, true_rel_res
     and (if hist) hist [B][max_iter+1]."""
-    B, N = f.shape[0], f.shape[-1]
+    B, N = _grid(f, "f")
     if tuple(k.shape) != (B, N + 2, N + 2) or tuple(u.shape) != (B, N, N):
         raise FcgnoError("shape mismatch: k [B][N+2][N+2], f and u [B][N][N]")
+    if r_out is not None and tuple(r_out.shape) != (B, N, N):
+        raise FcgnoError("shape mismatch: r_out [B][N][N]")
     d = SolveDesc(N, B, m_max, max_iter, rtol, OP[op], check_every, precond_steps, streams)
     h = model.handle if (model is not None and op not in MODEL_FREE) else None
     nbytes = lib().fcgno_solve_workspace_bytes(h, ctypes.byref(d))
@@ -237,7 +258,7 @@ def solve(model, k, f, u, op="bf16", m_max=5, max_iter=300, rtol=1e-6, r_out=Non
         _dev_f64(r_out, "r_out") if r_out is not None else None,
         iters.ctypes.data_as(POINTER(c_int32)), status.ctypes.data_as(POINTER(c_int32)),
         hh.ctypes.data_as(POINTER(c_double)) if hist else None,
-        tres.ctypes.data_as(POINTER(c_double)), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+        tres.ctypes.data_as(POINTER(c_double)), ctypes.c_void_p(ws.data_ptr()), _nbytes(ws), _stream(stream))
     _check(rc, "fcgno_solve")
     out = {"iters": iters, "status": status, "true_rel_res": tres, "rc": rc}
     if hist:
@@ -247,9 +268,11 @@ def solve(model, k, f, u, op="bf16", m_max=5, max_iter=300, rtol=1e-6, r_out=Non
 
 def precond_apply(model, k, r, op="bf16", w=None, workspace=None, stream=None):
     """w = B(r; theta) for a batch (asynchronous on the stream)."""
-    B, N = r.shape[0], r.shape[-1]
+    B, N = _grid(r, "r")
     if tuple(k.shape) != (B, N + 2, N + 2):
         raise FcgnoError("shape mismatch: k [B][N+2][N+2], r [B][N][N]")
+    if w is not None and tuple(w.shape) != (B, N, N):
+        raise FcgnoError("shape mismatch: w [B][N][N]")
     if w is None:
         w = torch.empty_like(r)
     nbytes = lib().fcgno_precond_workspace_bytes(model.handle, N, B, OP[op])
@@ -257,7 +280,7 @@ def precond_apply(model, k, r, op="bf16", w=None, workspace=None, stream=None):
         raise FcgnoError("invalid operator application (need 2*modes <= N and a matrix precision)")
     ws = _workspace(nbytes, r.device, workspace)
     _check(lib().fcgno_precond_apply(model.handle, N, B, OP[op], _dev_f64(k, "k"), _dev_f64(r, "r"),
-                                     _dev_f64(w, "w"), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                     _dev_f64(w, "w"), ctypes.c_void_p(ws.data_ptr()), _nbytes(ws),
                                      _stream(stream)), "fcgno_precond_apply")
     return w
 
@@ -331,11 +354,12 @@ def train_workspace(model, n, batch, op="fp32", device=None):
 
 def op_forward(model, k, r, op="fp64", workspace=None, stream=None):
     """w = B(r), keeping the activations for op_backward in the workspace."""
-    B, N = r.shape[0], r.shape[-1]
+    B, N = _grid(r, "r")
+    _same(k, (B, N + 2, N + 2), "k")
     ws = workspace if workspace is not None else train_workspace(model, N, B, op, r.device)
     w = torch.empty_like(r)
     _check(lib().fcgno_op_forward(model.handle, N, B, OP[op], _dev_f64(k, "k"), _dev_f64(r, "r"),
-                                  _dev_f64(w, "w"), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+                                  _dev_f64(w, "w"), ctypes.c_void_p(ws.data_ptr()), _nbytes(ws), _stream(stream)),
            "fcgno_op_forward")
     return w, ws
 
@@ -343,13 +367,16 @@ def op_forward(model, k, r, op="fp64", workspace=None, stream=None):
 def op_backward(model, k, r, grad_w, ws, op="fp64", stream=None, input_grad=False):
     """Gradient of sum <grad_w, B(r)> with respect to the weight blob (device
     float64); with input_grad, also with respect to r: returns (g, g_r)."""
-    B, N = r.shape[0], r.shape[-1]
+    B, N = _grid(r, "r")
+    _same(k, (B, N + 2, N + 2), "k")
+    grad_w = grad_w.contiguous()
+    _same(grad_w, (B, N, N), "grad_w")
     g = torch.empty(model.n_weights, dtype=torch.float64, device=r.device)
     gr = torch.empty_like(r) if input_grad else None
     _check(lib().fcgno_op_backward(model.handle, N, B, OP[op], _dev_f64(k, "k"), _dev_f64(r, "r"),
-                                   _dev_f64(grad_w.contiguous(), "grad_w"), _dev_f64(g, "grad"),
+                                   _dev_f64(grad_w, "grad_w"), _dev_f64(g, "grad"),
                                    _dev_f64(gr, "grad_r") if input_grad else None,
-                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+                                   ctypes.c_void_p(ws.data_ptr()), _nbytes(ws), _stream(stream)),
            "fcgno_op_backward")
     return (g, gr) if input_grad else g
 
@@ -360,14 +387,18 @@ LOSS = {"energy": 0, "l2": 1}
 def energy_loss(k, w, e, grad=True, stream=None, kind="energy"):
     """Per-system ||w-e||/||e|| in the energy norm (or the Euclidean norm with
     kind="l2") and (optionally) the gradient of their mean."""
-    B, N = w.shape[0], w.shape[-1]
+    B, N = _grid(w, "w")
+    _same(k, (B, N + 2, N + 2), "k")
+    _same(e, (B, N, N), "e")
     nbytes = lib().fcgno_energy_loss_workspace_bytes(N, B)
+    if nbytes == 0:
+        raise FcgnoError("invalid loss shape: " + lib().fcgno_last_error().decode(errors="replace"))
     ws = torch.empty(int(nbytes), dtype=torch.uint8, device=w.device)
     loss = torch.empty(B, dtype=torch.float64, device=w.device)
     g = torch.empty_like(w) if grad else None
     _check(lib().fcgno_loss(LOSS[kind], N, B, _dev_f64(k, "k"), _dev_f64(w, "w"), _dev_f64(e, "e"),
                             _dev_f64(loss, "loss"), _dev_f64(g, "grad") if grad else None,
-                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)), "fcgno_loss")
+                            ctypes.c_void_p(ws.data_ptr()), _nbytes(ws), _stream(stream)), "fcgno_loss")
     return loss, g
 
 
@@ -375,13 +406,15 @@ def train_step(model, opt, k, r, e, op="fp32", workspace=None, stream=None, retu
     """One AdamW step on the energy-norm loss (or loss="l2"); returns the
     batch-mean loss (which synchronises the stream), or None with
     ``return_loss=False``."""
-    B, N = r.shape[0], r.shape[-1]
+    B, N = _grid(r, "r")
+    _same(k, (B, N + 2, N + 2), "k")
+    _same(e, (B, N, N), "e")
     ws = workspace if workspace is not None else train_workspace(model, N, B, op, r.device)
     out = c_double(0.0)
     _check(lib().fcgno_train_step_loss(model.handle, opt.handle, N, B, OP[op], LOSS[loss], _dev_f64(k, "k"),
                                        _dev_f64(r, "r"), _dev_f64(e, "e"),
                                        ctypes.byref(out) if return_loss else None,
-                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+                                       ctypes.c_void_p(ws.data_ptr()), _nbytes(ws), _stream(stream)),
            "fcgno_train_step_loss")
     return float(out.value) if return_loss else None
 
@@ -389,30 +422,38 @@ def train_step(model, opt, k, r, e, op="fp32", workspace=None, stream=None, retu
 def residual_samples(k, f, u, max_iter=None, stream=None):
     """(f - A u, A^-1 f - u) for a batch of random right-hand sides and points;
     returns two device tensors [B][N][N]."""
-    B, N = f.shape[0], f.shape[-1]
+    B, N = _grid(f, "f")
+    _same(k, (B, N + 2, N + 2), "k")
+    _same(u, (B, N, N), "u")
     max_iter = max_iter or max(20 * N, 2000)
     nbytes = lib().fcgno_krylov_samples_workspace_bytes(N, B, max_iter)
+    if nbytes == 0:
+        raise FcgnoError("invalid sample shape: " + lib().fcgno_last_error().decode(errors="replace"))
     ws = torch.empty(int(nbytes), dtype=torch.uint8, device=f.device)
     r = torch.empty((B, N, N), dtype=torch.float64, device=f.device)
     e = torch.empty_like(r)
     _check(lib().fcgno_residual_samples(N, B, max_iter, _dev_f64(k, "k"), _dev_f64(f, "f"), _dev_f64(u, "u"),
                                         _dev_f64(r, "r"), _dev_f64(e, "e"), ctypes.c_void_p(ws.data_ptr()),
-                                        ws.numel(), _stream(stream)), "fcgno_residual_samples")
+                                        _nbytes(ws), _stream(stream)), "fcgno_residual_samples")
     return r, e
 
 
 def krylov_samples(k, f, u0, m_iter=100, max_iter=None, stream=None):
     """(r_i, e_i = u* - u_i), i = 1..m_iter, of conjugate gradients from u0;
     returns two device tensors [B][m_iter][N][N]."""
-    B, N = f.shape[0], f.shape[-1]
+    B, N = _grid(f, "f")
+    _same(k, (B, N + 2, N + 2), "k")
+    _same(u0, (B, N, N), "u0")
     max_iter = max_iter or max(20 * N, 2000)
     nbytes = lib().fcgno_krylov_samples_workspace_bytes(N, B, max(max_iter, m_iter))
+    if nbytes == 0:
+        raise FcgnoError("invalid sample shape: " + lib().fcgno_last_error().decode(errors="replace"))
     ws = torch.empty(int(nbytes), dtype=torch.uint8, device=f.device)
     r = torch.empty((B, m_iter, N, N), dtype=torch.float64, device=f.device)
     e = torch.empty_like(r)
     _check(lib().fcgno_krylov_samples(N, B, m_iter, max_iter, _dev_f64(k, "k"), _dev_f64(f, "f"),
                                       _dev_f64(u0, "u0"), _dev_f64(r, "r"), _dev_f64(e, "e"),
-                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)),
+                                      ctypes.c_void_p(ws.data_ptr()), _nbytes(ws), _stream(stream)),
            "fcgno_krylov_samples")
     return r, e
 
@@ -441,7 +482,7 @@ class Engine:
     def submit(self, k, f, u, rtol=1e-6, max_iter=None):
         """Queue one system: k [N+2][N+2], f and u [N][N] float64 device tensors
         (u: in u0, out the iterate).  Returns the request id."""
-        N = f.shape[-1]
+        _, N = _grid(f, "f", lead=0)
         if tuple(k.shape) != (N + 2, N + 2) or tuple(u.shape) != (N, N):
             raise FcgnoError("shape mismatch: k [N+2][N+2], f and u [N][N]")
         max_iter = max_iter or max(2 * N, 300)
