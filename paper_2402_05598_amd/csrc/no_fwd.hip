@@ -377,11 +377,17 @@ __global__ __launch_bounds__(256) void k_spec_fwd(SpecArgs a) {
   const acc_t* E = (const acc_t*)a.Eacc;
   const int t = threadIdx.x;
   acc_t* Vp = (acc_t*)sd.Vp + ((size_t)(ky * a.XS + xs) * C) * twoM * 2;
-  for (int q = t; q < twoM * SX; q += 256) {
-    const int kx = q / SX, xl = q - kx * SX;
-    const int idx = (int)tw_index(a.basis, N, M, kx, x0 + xl);
-    Er_[kx][xl] = E[2 * idx];
-    Ei_[kx][xl] = -E[2 * idx + 1];
+  // a fixed trip count (2M <= 32) so that every thread's table loads are in
+  // flight together rather than one round trip per pass
+#pragma unroll
+  for (int i = 0; i < 32 * SX / 256; ++i) {
+    const int q = t + 256 * i;
+    if (q < twoM * SX) {
+      const int kx = q / SX, xl = q - kx * SX;
+      const int idx = (int)tw_index(a.basis, N, M, kx, x0 + xl);
+      Er_[kx][xl] = E[2 * idx];
+      Ei_[kx][xl] = -E[2 * idx + 1];
+    }
   }
   if (a.layer0) {
     if (t < SX) {
@@ -406,12 +412,17 @@ __global__ __launch_bounds__(256) void k_spec_fwd(SpecArgs a) {
   acc_t gc[LPT], gs[LPT];
 #pragma unroll
   for (int u = 0; u < LPT; ++u) {
-    const int q = t + 256 * u;
-    const int xl = q / CH, c = q - xl * CH;
     gc[u] = 0;
     gs[u] = 0;
-    if (xl < nx) {
-      for (int sg = 0; sg < a.S; ++sg) {
+  }
+  // segments outermost: the LPT points' loads of one segment are independent
+  // and issue together (the per-point sums keep their segment order)
+  for (int sg = 0; sg < a.S; ++sg) {
+#pragma unroll
+    for (int u = 0; u < LPT; ++u) {
+      const int q = t + 256 * u;
+      const int xl = q / CH, c = q - xl * CH;
+      if (xl < nx) {
         const acc_t* row = Gp + (size_t)((x0 + xl) * a.S + sg) * MP * C;
         gc[u] += row[(2 * ky) * C + c];
         gs[u] += row[(2 * ky + 1) * C + c];
@@ -445,65 +456,62 @@ template <int PREC, int C>
 __global__ __launch_bounds__(256) void k_spec_mix(SpecArgs a) {
   using M_ = Mf<PREC>;
   using acc_t = typename M_::acc_t;
-  __shared__ acc_t Vr[C][33], Vi[C][33];
+  // one block per (ky, chunk of KXB kept x-modes, system); thread t owns
+  // channel t % C of mode kx0 + t / C in both phases
+  constexpr int KXB = 256 / C;
+  __shared__ acc_t Vr[C][KXB + 1], Vi[C][KXB + 1];
   const int ky = blockIdx.x;
-  const SysDev sd = a.sys[blockIdx.y];
+  const SysDev sd = a.sys[blockIdx.z];
   if (!sd.st->active) return;
   const int M = a.M, twoM = 2 * M;
   const int t = threadIdx.x;
+  const int ch = t % C, kl = t / C, kx = blockIdx.y * KXB + kl;
+  const bool live = kx < twoM;
   const acc_t* Vp = (const acc_t*)sd.Vp + (size_t)ky * a.XS * C * twoM * 2;
-  if (a.layer0) {
-    const double snorm = sd.st->snorm;
-    const double inv_s = snorm > 0.0 ? 1.0 / snorm : 0.0;
-    for (int q = t; q < C * twoM; q += 256) {
-      const int c = q / twoM, kx = q - c * twoM;
-      acc_t rr = 0, ri = 0;
-      for (int xs = 0; xs < a.XS; ++xs) {
-        rr += Vp[(size_t)xs * C * twoM * 2 + 2 * kx];
-        ri += Vp[(size_t)xs * C * twoM * 2 + 2 * kx + 1];
-      }
-      const double wl = (double)((const acc_t*)a.WL0)[c] * inv_s;
-      const acc_t* vc = (const acc_t*)sd.Vc + 2 * ((size_t)(c * twoM + kx) * M + ky);
-      Vr[c][kx] = (acc_t)(wl * (double)rr) + vc[0];
-      Vi[c][kx] = (acc_t)(wl * (double)ri) + vc[1];
+  // phase 1: this thread's V[c = ch][kx], the sum of the XS chunk partials
+  if (live) {
+    const size_t e = a.layer0 ? (size_t)2 * kx : (size_t)2 * (ch * twoM + kx);
+    acc_t vr = 0, vi = 0;
+    for (int xs = 0; xs < a.XS; ++xs) {
+      vr += Vp[(size_t)xs * C * twoM * 2 + e];
+      vi += Vp[(size_t)xs * C * twoM * 2 + e + 1];
     }
-  } else {
-    for (int q = t; q < C * twoM; q += 256) {
-      const int c = q / twoM, kx = q - c * twoM;
-      acc_t vr = 0, vi = 0;
-      for (int xs = 0; xs < a.XS; ++xs) {
-        vr += Vp[(size_t)xs * C * twoM * 2 + 2 * q];
-        vi += Vp[(size_t)xs * C * twoM * 2 + 2 * q + 1];
-      }
-      Vr[c][kx] = vr;
-      Vi[c][kx] = vi;
+    if (a.layer0) {
+      const double snorm = sd.st->snorm;
+      const double inv_s = snorm > 0.0 ? 1.0 / snorm : 0.0;
+      const double wl = (double)((const acc_t*)a.WL0)[ch] * inv_s;
+      const acc_t* vc = (const acc_t*)sd.Vc + 2 * ((size_t)(ch * twoM + kx) * M + ky);
+      vr = (acc_t)(wl * (double)vr) + vc[0];
+      vi = (acc_t)(wl * (double)vi) + vc[1];
+    }
+    Vr[ch][kl] = vr;
+    Vi[ch][kl] = vi;
+    if (a.Vsave) {
+      acc_t* vs = (acc_t*)a.Vsave + a.vs_sys * blockIdx.z + (size_t)ky * C * twoM * 2;
+      vs[2 * (ch * twoM + kx)] = vr;
+      vs[2 * (ch * twoM + kx) + 1] = vi;
     }
   }
   __syncthreads();
-  if (a.Vsave) {
-    acc_t* vs = (acc_t*)a.Vsave + a.vs_sys * blockIdx.y + (size_t)ky * C * twoM * 2;
-    for (int q = t; q < C * twoM; q += 256) {
-      const int c = q / twoM, kx = q - c * twoM;
-      vs[2 * q] = Vr[c][kx];
-      vs[2 * q + 1] = Vi[c][kx];
-    }
+  if (!live) return;
+  // phase 2: output channel o = ch of mode kx, all C weight pairs in flight
+  const int o = ch, MP = round16(twoM);
+  const acc_t* Rk = (const acc_t*)a.R + ((size_t)ky * twoM + kx) * C * C * 2;
+  acc_t rr[C], ri[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    rr[c] = Rk[2 * (c * C + o)];
+    ri[c] = Rk[2 * (c * C + o) + 1];
   }
-  const int MP = round16(twoM);
-  const acc_t* R = (const acc_t*)a.R + (size_t)ky * twoM * C * C * 2;
+  acc_t sr = 0, si = 0;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    sr += Vr[c][kl] * rr[c] - Vi[c][kl] * ri[c];
+    si += Vr[c][kl] * ri[c] + Vi[c][kl] * rr[c];
+  }
   acc_t* Wh = (acc_t*)sd.Wh + (size_t)ky * C * MP * 2;
-  for (int q = t; q < C * twoM; q += 256) {
-    const int o = q % C, kx = q / C;
-    const acc_t* Rk = R + (size_t)kx * C * C * 2;
-    acc_t sr = 0, si = 0;
-#pragma unroll 8
-    for (int c = 0; c < C; ++c) {
-      const acc_t rr = Rk[2 * (c * C + o)], ri = Rk[2 * (c * C + o) + 1];
-      sr += Vr[c][kx] * rr - Vi[c][kx] * ri;
-      si += Vr[c][kx] * ri + Vi[c][kx] * rr;
-    }
-    Wh[2 * (o * MP + kx)] = sr;
-    Wh[2 * (o * MP + kx) + 1] = si;
-  }
+  Wh[2 * (o * MP + kx)] = sr;
+  Wh[2 * (o * MP + kx) + 1] = si;
 }
 
 // x-direction synthesis for SR rows: H[x][o][ky] = sum_a W^[ky][o][a]
@@ -969,7 +977,8 @@ static void apply_pc(const NOLaunch& L) {
       ProfScope ps(PK_SPECTRAL, L.stream);
       constexpr int SR = SynthRows<PREC>::SR;
       hipLaunchKernelGGL((k_spec_fwd<PREC, C>), dim3(L.M, XS, L.nsys), dim3(256), 0, L.stream, sa);
-      hipLaunchKernelGGL((k_spec_mix<PREC, C>), dim3(L.M, L.nsys), dim3(256), 0, L.stream, sa);
+      hipLaunchKernelGGL((k_spec_mix<PREC, C>), dim3(L.M, (2 * L.M + 256 / C - 1) / (256 / C), L.nsys), dim3(256), 0,
+                         L.stream, sa);
       if (L.MP == 16)
         hipLaunchKernelGGL((k_spec_inv<PREC, C, 16>), dim3((L.N + SR - 1) / SR, L.nsys), dim3(synth_threads(C, L.M)), 0,
                        L.stream, sa);
