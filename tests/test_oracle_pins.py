@@ -466,6 +466,28 @@ def test_loss_gradient_finite_differences():
     assert torch.autograd.gradcheck(loss_of, params, eps=1e-6, atol=1e-8, rtol=1e-6)
 
 
+def test_operator_input_gradient_finite_differences():
+    """The oracle's gradient of B(r) = s NO(r/s) with respect to r, through
+    s = ||r||/N as well, against central differences (gradcheck), and Euler's
+    identity sum_p r_p d<g, B(r)>/dr_p = <g, B(r)> of a degree-1 positively
+    homogeneous map: the reference for the library's input gradient."""
+    N, C, M = 8, 2, 2
+    g = synth.rng(23)
+    k = torch.from_numpy(np.exp(0.3 * g.standard_normal((2, N + 2, N + 2))))
+    r = torch.from_numpy(g.standard_normal((2, N, N))).requires_grad_(True)
+    wb = synth.init_weights(5, C, M, L=2)
+    wb[C * 4 + C:] *= 2.0
+    w = oracle.unpack_weights(wb, C, M, L=2)
+    assert torch.autograd.gradcheck(lambda x: oracle.no_apply(w, k, x), (r,), eps=1e-6, atol=1e-8, rtol=1e-6)
+    gw = torch.from_numpy(g.standard_normal((2, N, N)))
+    val = torch.sum(gw * oracle.no_apply(w, k, r))
+    (grad,) = torch.autograd.grad(val, r)
+    with torch.no_grad():
+        lhs = torch.sum(r * grad, dim=(1, 2))
+        rhs = torch.sum(gw * oracle.no_apply(w, k, r), dim=(1, 2))
+    assert torch.allclose(lhs, rhs, rtol=1e-12, atol=0)
+
+
 def test_krylov_samples_consistent():
     """e_i = u* - u_i satisfies A e_i = r_i for every kept CG iterate."""
     N = 16
