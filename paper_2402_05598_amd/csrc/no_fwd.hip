@@ -382,11 +382,14 @@ __global__ __launch_bounds__(256) void k_spec_fwd(SpecArgs a) {
 #pragma unroll
   for (int i = 0; i < 32 * SX / 256; ++i) {
     const int q = t + 256 * i;
-    if (q < twoM * SX) {
-      const int kx = q / SX, xl = q - kx * SX;
+    const int kx = q / SX, xl = q - kx * SX;
+    if (kx < twoM) {
       const int idx = (int)tw_index(a.basis, N, M, kx, x0 + xl);
       Er_[kx][xl] = E[2 * idx];
       Ei_[kx][xl] = -E[2 * idx + 1];
+    } else {   // rows past 2M feed only output rows that are not stored
+      Er_[kx][xl] = 0;
+      Ei_[kx][xl] = 0;
     }
   }
   if (a.layer0) {
@@ -437,16 +440,36 @@ __global__ __launch_bounds__(256) void k_spec_fwd(SpecArgs a) {
     Gi_[xl][c] = -gs[u];
   }
   __syncthreads();
-  for (int q = t; q < C * twoM; q += 256) {
-    const int c = q % C, kx = q / C;
-    acc_t sr = 0, si = 0;
-    for (int xl = 0; xl < nx; ++xl) {
-      const acc_t gr = Gr_[xl][c], gi = Gi_[xl][c], er = Er_[kx][xl], ei = Ei_[kx][xl];
-      sr += gr * er - gi * ei;
-      si += gr * ei + gi * er;
+  // V^[kx][c] on the matrix cores in the accumulate precision, as real
+  // products over the SX rows of the chunk (rows past nx hold zeros):
+  // Re = Er Gr - Ei Gi, Im = Er Gi + Ei Gr.  Wave w takes the (16 x-modes,
+  // 16 channels) output tiles w, w + 4, ...
+  using MM = Mf<sizeof(acc_t) == 8 ? P64 : P32>;
+  using vec_t = typename MM::accv_t;
+  const int lane = t & 63, w = t >> 6, n16 = lane & 15, g = lane >> 4;
+  const int nkt = (twoM + 15) >> 4;
+  for (int pr = w; pr < nkt * (C / 16); pr += 4) {
+    const int kt = pr % nkt, ct = pr / nkt;
+    const int ka = kt * 16 + n16, cb = ct * 16 + n16;
+    vec_t vr = {0, 0, 0, 0}, vi = {0, 0, 0, 0};
+#pragma unroll 4
+    for (int xb = 0; xb < SX; xb += 4) {
+      const int xl = xb + g;
+      const acc_t er = Er_[ka][xl], ei = Ei_[ka][xl];
+      const acc_t gr = Gr_[xl][cb], gi = Gi_[xl][cb];
+      vr = MM::mma(er, gr, vr);
+      vr = MM::mma(-ei, gi, vr);
+      vi = MM::mma(er, gi, vi);
+      vi = MM::mma(ei, gr, vi);
     }
-    Vp[2 * (c * twoM + kx)] = sr;
-    Vp[2 * (c * twoM + kx) + 1] = si;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int kx = kt * 16 + MM::row(g, i);
+      if (kx < twoM) {
+        Vp[2 * (cb * twoM + kx)] = vr[i];
+        Vp[2 * (cb * twoM + kx) + 1] = vi[i];
+      }
+    }
   }
 }
 
