@@ -682,6 +682,10 @@ def main():
         d = {"solves_per_sec": round(B * Rr["steps"] / Rr["seconds"], 3),
              "converged_per_sec": round(float(conv.sum()) / Rr["seconds"], 3),
              "ms_per_solve_batch": round(Rr["seconds"] / Rr["steps"] * 1e3, 2),
+             # FCG iterations of all systems per second: the kernels' throughput,
+             # far less sensitive than converged solves/s to how well the
+             # operator trained at set-up transfers to this grid
+             "system_iters_per_sec": round(float(Rr["iters"].sum()) / Rr["seconds"], 1),
              "iters_mean": round(float(Rr["iters"].mean()), 2), "iters_max": int(Rr["iters"].max()),
              "status_counts": {"ok": int(conv.sum()), "not_converged": int((Rr["status"] == 1).sum()),
                                "breakdown": int((Rr["status"] == 2).sum())},
