@@ -300,10 +300,14 @@ fcgno_status fcgno_engine_create(const fcgno_model* m, const fcgno_engine_desc* 
 /* Queue a request; FCGNO_E_NOMEM if it can never fit the budget. */
 fcgno_status fcgno_engine_submit(fcgno_engine* e, int32_t n, const double* k, const double* f, double* u,
                                  double rtol, int32_t max_iter, int64_t* id_out);
-/* Admit what fits, advance every group, report and release stopped requests. */
+/* Admit what fits, advance every group, report and release stopped requests.
+ * A negative status (a failed HIP call) leaves the queue and the slots in an
+ * unspecified state: the engine can only be destroyed, after which the
+ * buffers of unreported requests belong to the caller again. */
 fcgno_status fcgno_engine_step(fcgno_engine* e, int32_t* n_active, int32_t* n_queued);
 /* Move up to max_results finished requests into out; returns the count. */
 int32_t fcgno_engine_poll(fcgno_engine* e, fcgno_engine_result* out, int32_t max_results);
+/* Waits for the engine's work, then frees its streams and pool. */
 void fcgno_engine_destroy(fcgno_engine* e);
 
 /* ------------------------------------------------------------------------ */
