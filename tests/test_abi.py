@@ -141,3 +141,43 @@ def test_size_limits_at_every_entry_point():
     d = b.EngineDesc(b.OP["identity"], 5, 8, 16, 1 << 30)
     f = lambda n: lib.fcgno_engine_request_bytes(None, ctypes.byref(d), n, 300)
     assert f(64) > 0 and f(32769) == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_model_and_training_arguments_refused_on_the_host():
+    """Unsupported architectures, wrong weight counts, non-finite weights,
+    unknown losses and training precisions are refused before any device
+    call, each with its reason."""
+    import numpy as np
+    import paper_2402_05598_amd._binding as b
+    lib = b.lib()
+
+    def create(layers=4, width=32, modes=12, cin=4, basis=0, count=None, bad=None):
+        a = b.Arch(layers, width, modes, cin, basis)
+        n = int(lib.fcgno_weight_count(ctypes.byref(a))) if count is None else count
+        w = np.zeros(max(n, 1))
+        if bad is not None:
+            w[bad] = np.nan
+        h = ctypes.c_void_p()
+        st = lib.fcgno_model_create(ctypes.byref(a), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n,
+                                    ctypes.byref(h))
+        return st, lib.fcgno_last_error()
+
+    # the blob size follows the layout in the header
+    a = b.Arch(4, 32, 12, 4, 0)
+    C, M, L = 32, 12, 4
+    assert lib.fcgno_weight_count(ctypes.byref(a)) == C * 4 + C + L * (2 * C * C * 2 * M * M + C * C + C) + C + 1
+    for kw, why in ((dict(width=24), b"width"), (dict(modes=17), b"modes"), (dict(modes=0), b"modes"),
+                    (dict(cin=3), b"in_channels"), (dict(basis=2), b"basis"), (dict(layers=0), b"layers"),
+                    (dict(count=10), b"weight count"), (dict(bad=5), b"non-finite")):
+        st, msg = create(**kw)
+        assert st == -1 and why in msg, (kw, msg)
+    # losses and training precisions
+    lib.fcgno_loss.restype = ctypes.c_int
+    vp = ctypes.c_void_p(1)
+    st = lib.fcgno_loss(ctypes.c_int32(7), ctypes.c_int32(8), ctypes.c_int32(1), vp, vp, vp, vp, None, vp,
+                        ctypes.c_size_t(1 << 30), None)
+    assert st == -1 and b"unknown loss" in lib.fcgno_last_error()
+    lib.fcgno_train_workspace_bytes.restype = ctypes.c_size_t
+    assert lib.fcgno_train_workspace_bytes(None, 32, 2, 1) == 0
+    assert b"null model" in lib.fcgno_last_error()
