@@ -132,6 +132,28 @@ def test_fcg_jacobi_is_pcg():
     assert np.max(np.abs(np.array(res.hist) - ref) / np.array(ref)) < 1e-10
 
 
+@pytest.mark.parametrize("steps", [1, 2, 4])
+def test_jacobi_is_truncated_neumann_series(steps):
+    """Sec. 3.3.1: k Jacobi steps x <- x + D^-1 (z - A x) from x = 0 give
+    x_k = sum_{j<k} (I - D^-1 A)^j D^-1 z.  Dense matrices on a 6x6 grid from
+    the assembled matrix (not the stencil the oracle sweeps with)."""
+    N = 6
+    k, _, _ = synth.diffusion_system(45, N)
+    A = oracle.assemble(k).toarray()
+    Dinv = np.diag(1.0 / np.diag(A))
+    E = np.eye(N * N) - Dinv @ A
+    Bmat = sum(np.linalg.matrix_power(E, j) for j in range(steps)) @ Dinv
+    B = oracle.jacobi_precond(k, steps)
+    cols = np.stack([B(torch.from_numpy(e.reshape(N, N))).numpy().reshape(-1) for e in np.eye(N * N)], axis=1)
+    assert np.max(np.abs(cols - Bmat)) <= 1e-12 * np.max(np.abs(Bmat))
+    if steps == 1:   # one step is D^-1: the diagonal by hand at one point
+        h2 = 1.0 / (N + 1) ** 2
+        i, j = 2, 3
+        c = k[i + 1, j + 1]
+        d = 0.5 * (4 * c + k[i + 2, j + 1] + k[i, j + 1] + k[i + 1, j + 2] + k[i + 1, j]) / h2
+        assert abs(cols[i * N + j, i * N + j] - 1.0 / d) <= 1e-14 / d
+
+
 def _red_black_by_hand(N):
     reds = [i * N + j for i in range(N) for j in range(N) if (i + j) % 2 == 0]
     blacks = [i * N + j for i in range(N) for j in range(N) if (i + j) % 2 == 1]
@@ -486,6 +508,55 @@ def test_operator_input_gradient_finite_differences():
         lhs = torch.sum(r * grad, dim=(1, 2))
         rhs = torch.sum(gw * oracle.no_apply(w, k, r), dim=(1, 2))
     assert torch.allclose(lhs, rhs, rtol=1e-12, atol=0)
+
+
+def test_krylov_samples_are_cg_iterates_one_to_m():
+    """The kept pairs are iterates i = 1..m of conjugate gradients from u0
+    (Sec. 3.1, Fig. 2a): r_i equal to textbook Hestenes-Stiefel CG's residual
+    after i steps (written in this file) and e_i = u* - u_i for the same u_i."""
+    N, m = 12, 9
+    k, f, u0, _ = synth.system(18, N, (10.0, 100.0))
+    A = lambda v: oracle.stencil_apply(k, v).numpy()
+    ustar = np.linalg.solve(oracle.assemble(k).toarray(), f.reshape(-1)).reshape(N, N)
+    u = u0.copy(); r = f - A(u); p = r.copy(); rr = np.sum(r * r)
+    want_r, want_e = [], []
+    for _ in range(m):
+        Ap = A(p); a = rr / np.sum(p * Ap)
+        u = u + a * p; r = r - a * Ap
+        rr_new = np.sum(r * r); p = r + (rr_new / rr) * p; rr = rr_new
+        want_r.append(r.copy()); want_e.append(ustar - u)
+    rs, es = oracle.krylov_samples(k, f, u0, m, u_star=torch.from_numpy(ustar))
+    assert rs.shape == (m, N, N) and es.shape == (m, N, N)
+    for i in range(m):
+        sc = np.max(np.abs(want_r[i]))
+        assert np.max(np.abs(rs[i].numpy() - want_r[i])) <= 1e-9 * sc, i
+        assert np.max(np.abs(es[i].numpy() - want_e[i])) <= 1e-9 * np.max(np.abs(want_e[i])), i
+    # i = 0 (the initial residual) is not among them
+    assert np.max(np.abs(rs[0].numpy() - (f - A(u0)))) > 1e-3 * np.max(np.abs(f - A(u0)))
+
+
+def test_pack_weights_layout_and_round_trip():
+    """pack_weights writes the blob order of the header: W_L[C][4], b_L[C],
+    per layer Re R[C][C][2M][M], Im R, W[C][C], b[C], then W_P[C], b_P.  A blob
+    holding its own indices unpacks to those positions and packs back."""
+    C, M, L = 4, 2, 3
+    n = synth.weight_count(C, M, L)
+    blob = np.arange(n, dtype=np.float64)
+    w = oracle.unpack_weights(blob, C, M, L)
+    nR = C * C * 2 * M * M
+    assert w.W_L[1, 2].item() == 1 * 4 + 2 and w.b_L[3].item() == 4 * C + 3
+    o = 5 * C
+    for l in range(L):
+        c, oc, a, q = 1, 3, 2, 1
+        assert w.R[l][c, oc, a, q].real.item() == o + ((c * C + oc) * 2 * M + a) * M + q
+        assert w.R[l][c, oc, a, q].imag.item() == o + nR + ((c * C + oc) * 2 * M + a) * M + q
+        assert w.W[l][2, 1].item() == o + 2 * nR + 2 * C + 1
+        assert w.b[l][2].item() == o + 2 * nR + C * C + 2
+        o += 2 * nR + C * C + C
+    assert w.W_P[1].item() == o + 1 and w.b_P[0].item() == o + C == n - 1
+    assert np.array_equal(oracle.pack_weights(w), blob)
+    wb = synth.init_weights(5, C, M, L)
+    assert np.array_equal(oracle.pack_weights(oracle.unpack_weights(wb, C, M, L)), wb)
 
 
 def test_krylov_samples_consistent():
