@@ -5,12 +5,18 @@ contrast drawn log-uniformly from [10, 1e3], f ~ GRF, u0 ~ N(0, I)), solved to
 1e-6 relative residual by flexible conjugate gradients (window m = 5) with the
 neural-operator preconditioner (4 layers, width 32, 12 modes) in BF16 on the
 matrix cores with FP32 accumulation; Krylov vectors, stencil, dot products and
-the final true-residual check in FP64.  The operator is trained at set-up
-(untimed) on 64 x 64 systems with the energy-norm loss on conjugate-gradient
-Krylov samples, all on the GPU through the library.
+the final true-residual check in FP64.  The operator is the committed blob
+weights/bench_operator_c32_m12_l4.npy, trained on 64 x 64 systems with the
+energy-norm loss on conjugate-gradient Krylov samples, all on the GPU through
+the library (weights/make_bench_operator.py writes it), so that the measured
+figures compare kernels, not training runs.
 
 One step = one batched solve of the 16 systems.  The same solves with the FP32
-and FP64 operator are timed afterwards for comparison.  Prints one JSON line.
+and FP64 operator are timed afterwards for comparison, then the other
+workloads: the 32 x 32 single solve (FP64 operator, seeded initial weights),
+64 solves at 128 x 128 and 256 x 256 (FP32 operator), training throughput
+(64 x 64, batch 256) and a serving run (Poisson arrivals, grids 64..1024).
+Prints one JSON line.
 """
 import argparse
 import hashlib
@@ -27,6 +33,7 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "layer_bf16_512x512x16_traffic.json")
+BENCH_WEIGHTS = os.path.join(ROOT, "weights", "bench_operator_c32_m12_l4.npy")
 KERNEL_SOURCES = ("paper_2402_05598_amd/csrc/no_fwd.hip", "paper_2402_05598_amd/csrc/common.h")
 
 
@@ -37,17 +44,20 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--n", type=int, default=512)
     p.add_argument("--batch", type=int, default=16)
-    p.add_argument("--train-steps", type=int, default=48000)
-    p.add_argument("--weights", default=None, help="load trained weights (.npy) instead of training")
+    p.add_argument("--train-steps", type=int, default=48000, help="with --train-operator")
+    p.add_argument("--weights", default=BENCH_WEIGHTS, help="trained weights (.npy) of the benchmark's operator")
+    p.add_argument("--train-operator", action="store_true",
+                   help="train the operator at set-up (1024 systems, lr 6e-4) instead of loading --weights")
     p.add_argument("--save-weights", default=None)
     p.add_argument("--ops", default="bf16,fp32,fp64", help="first one is the reported value")
     p.add_argument("--max-iter", type=int, default=0, help="default max(2N, 300)")
     p.add_argument("--rtol", type=float, default=1e-6)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--serve-requests", type=int, default=0,
-                   help="requests per serving run through the continuous-batching engine (0: no serving leg; "
-                        "it runs the same layer kernel, so it is kept out of the default run whose kernel "
-                        "statistics the roofline quotes)")
+    p.add_argument("--serve-requests", type=int, default=200,
+                   help="requests per serving run through the continuous-batching engine (0: no serving leg); "
+                        "it runs after the timed and roofline legs")
+    p.add_argument("--train-bench-steps", type=int, default=100,
+                   help="timed steps of the training-throughput leg (64x64, batch 256; 0: skip)")
     p.add_argument("--cpu-seconds", type=float, default=20.0)
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 1 GiB device copy first (HBM counter calibration under rocprofv3)")
@@ -336,6 +346,89 @@ def batched(fc, torch, dev, model, C, M, L, logf, steps=3):
     return out
 
 
+def config0(fc, torch, dev, logf, solves=10):
+    """The single-solve parity configuration: 32 x 32, k = exp(GRF) (no
+    contrast rescaling), f ~ GRF, u0 ~ N(0, I), operator with 4 layers, width
+    16 and 8 modes at its seeded initial weights in FP64, m = 5, tol 1e-6, at
+    most 300 iterations.  Latency-bound: reported per iteration and per solve."""
+    import synth
+    N, C, M, L = 32, 16, 8, 4
+    k, f, u0, _ = synth.system(0, N)
+    model = fc.Model(synth.init_weights(0, C, M, L), C, M, L)
+    kd, fd, ud = [torch.from_numpy(a)[None].to(dev).contiguous() for a in (k, f, u0)]
+    ws = torch.empty(fc.solve_workspace_bytes(model, N, 1, "fp64", 5, 300, 1e-6), dtype=torch.uint8, device=dev)
+    for _ in range(2):
+        fc.solve(model, kd, fd, ud.clone(), op="fp64", m_max=5, max_iter=300, rtol=1e-6, hist=False, workspace=ws)
+    torch.cuda.synchronize()
+    lat, its = [], []
+    for _ in range(solves):
+        u = ud.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        o = fc.solve(model, kd, fd, u, op="fp64", m_max=5, max_iter=300, rtol=1e-6, hist=False, workspace=ws)
+        lat.append(time.perf_counter() - t0)
+        its.append(int(o["iters"][0]))
+    model.close()
+    lat = np.array(lat)
+    out = {"grid": N, "width": C, "modes": M, "layers": L, "op": "fp64", "weights": "seeded initial",
+           "iters": its[-1], "status": int(o["status"][0]),
+           "true_rel_res": float(o["true_rel_res"][0]), "true_rel_res_f": float(o["true_rel_res_f"][0]),
+           "us_per_iteration": round(float(np.median(lat)) / max(its[-1], 1) * 1e6, 2),
+           "solves_per_sec": round(1.0 / float(np.median(lat)), 3),
+           "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+           "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3)}
+    log(f"config0: {out}", logf)
+    return out
+
+
+def training_throughput(fc, torch, dev, C, M, L, steps, logf, N=64, B=256, m_iter=100):
+    """The training configuration: 256 seeded 64 x 64 systems (k = exp(GRF)
+    rescaled to contrast 10..1e3), Krylov samples of 100 conjugate-gradient
+    iterations each (Sec. 3.1), train steps at batch 256 (one sample per
+    system, the iteration drawn at random) with the FP32 operator: forward,
+    energy-norm loss, hand-written backward and AdamW.  The operator starts
+    from the seeded initial weights (projection scaled by 1e-3)."""
+    import synth
+    blob = synth.init_weights(3, C, M, L)
+    blob[blob.size - C - 1:] *= 1e-3
+    model = fc.Model(blob, C, M, L)
+    k, f, u0, _ = synth.batch(3, B, N, (10.0, 1000.0))
+    kd, fd, ud = [torch.from_numpy(a).to(dev) for a in (k, f, u0)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, e = fc.krylov_samples(kd, fd, ud, m_iter=m_iter)
+    torch.cuda.synchronize()
+    t_samples = time.perf_counter() - t0
+    opt = fc.Optim(model, lr=3e-4, weight_decay=1e-2)
+    ws = fc.train_workspace(model, N, B, "fp32", dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(99)
+    ar = torch.arange(B, device=dev)
+    pick = torch.randint(0, m_iter, (steps + 10, B), generator=g, device=dev)
+    batches = [(r[ar, pick[s]].contiguous(), e[ar, pick[s]].contiguous()) for s in range(steps + 10)]
+    losses = []
+    for s in range(10):
+        fc.train_step(model, opt, kd, batches[s][0], batches[s][1], op="fp32", workspace=ws, return_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        rb, eb = batches[10 + s]
+        want = s == 0 or s == steps - 1
+        v = fc.train_step(model, opt, kd, rb, eb, op="fp32", workspace=ws, return_loss=want)
+        if want:
+            losses.append(v)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    opt.close()
+    model.close()
+    out = {"grid": N, "batch": B, "op": "fp32", "samples": f"CG iterations 1..{m_iter} of {B} systems",
+           "sample_seconds": round(t_samples, 3), "steps": steps, "seconds": round(dt, 3),
+           "steps_per_sec": round(steps / dt, 2), "ms_per_step": round(dt / steps * 1e3, 3),
+           "loss_first_timed": round(losses[0], 4), "loss_last_timed": round(losses[-1], 4)}
+    log(f"training throughput: {out}", logf)
+    return out
+
+
 def time_solves(fc, torch, model, kd, fd, u0d, op, steps, warmup, args, prof_kernels=None, streams=0):
     B = fd.shape[0]
     N = fd.shape[-1]
@@ -388,7 +481,7 @@ def serving(fc, torch, dev, model, n_req, logf):
         eng = fc.Engine(model, op="bf16", m_max=5, check_every=8, max_slots=64, budget_bytes=24 << 30)
         us = [r[2].clone() for r in reqs]
         torch.cuda.synchronize()
-        ids, t_sub, t_done, res = {}, {}, {}, {}
+        ids, t_arr, t_sub, t_done, res = {}, {}, {}, {}, {}
         order = np.argsort(arrivals, kind="stable")
         nxt = 0
         t0 = time.perf_counter()
@@ -398,6 +491,9 @@ def serving(fc, torch, dev, model, n_req, logf):
                 i = int(order[nxt])
                 k, f, _ = reqs[i]
                 ids[eng.submit(k, f, us[i], rtol=1e-6, max_iter=max(2 * grids[i], 300))] = i
+                # latency counts from the arrival, including the wait for the
+                # engine step that was running when the request arrived
+                t_arr[i] = float(arrivals[i])
                 t_sub[i] = time.perf_counter() - t0
                 nxt += 1
             active, queued = eng.step()
@@ -409,23 +505,26 @@ def serving(fc, torch, dev, model, n_req, logf):
                 time.sleep(max(0.0, arrivals[order[nxt]] - (time.perf_counter() - t0)))
         total = time.perf_counter() - t0
         eng.close()
-        lat = np.array([t_done[i] - t_sub[i] for i in range(n_req)]) * 1e3
+        lat = np.array([t_done[i] - t_arr[i] for i in range(n_req)]) * 1e3
+        wait = np.array([t_sub[i] - t_arr[i] for i in range(n_req)]) * 1e3
         conv = np.array([res[i]["status"] == 0 for i in range(n_req)])
-        return total, lat, conv, res
+        return total, lat, conv, res, wait
 
-    t_closed, lat_c, conv_c, res_c = run(np.zeros(n_req))
+    t_closed, lat_c, conv_c, res_c, _ = run(np.zeros(n_req))
     mu = n_req / t_closed
     open_loop = {}
     for load in (0.5, 0.9):
         lam = load * mu
         arr = np.cumsum(np.random.default_rng(4343).exponential(1.0 / lam, n_req))
         arr -= arr[0]
-        t_open, lat_o, conv_o, _ = run(arr)
+        t_open, lat_o, conv_o, _, wait_o = run(arr)
         open_loop[f"{load:g}_mu"] = {"arrival_rate_per_sec": round(lam, 3), "seconds": round(t_open, 3),
                                      "solves_per_sec": round(n_req / t_open, 3),
                                      "converged_per_sec": round(float(conv_o.sum()) / t_open, 3),
                                      "p50_ms": round(float(np.percentile(lat_o, 50)), 1),
-                                     "p99_ms": round(float(np.percentile(lat_o, 99)), 1)}
+                                     "p99_ms": round(float(np.percentile(lat_o, 99)), 1),
+                                     "submit_wait_p50_ms": round(float(np.percentile(wait_o, 50)), 1),
+                                     "submit_wait_p99_ms": round(float(np.percentile(wait_o, 99)), 1)}
         log(f"serving: open-loop at {lam:.2f}/s: {t_open:.2f}s p50 {np.percentile(lat_o, 50):.0f} ms "
             f"p99 {np.percentile(lat_o, 99):.0f} ms", logf)
     by_n = {}
@@ -436,6 +535,7 @@ def serving(fc, torch, dev, model, n_req, logf):
             by_n[str(N)] = {"requests": len(it), "converged": int(sum(ok)), "iters_median": float(np.median(it))}
     log(f"serving: closed {t_closed:.2f}s mu={mu:.2f}/s", logf)
     return {"requests": n_req, "grids": sizes, "op": "bf16", "tol": 1e-6,
+            "latency": "from the request's arrival (closed loop: t = 0) to its result being polled",
             "closed_loop": {"seconds": round(t_closed, 3), "solves_per_sec": round(mu, 3),
                             "converged_per_sec": round(float(conv_c.sum()) / t_closed, 3),
                             "p50_ms": round(float(np.percentile(lat_c, 50)), 1),
@@ -460,6 +560,17 @@ def copy_bandwidth(torch, dev):
     bw = 5 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del a, b
     return bw
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(k, f, u0, blob, C, M, L, iters_needed, conv_frac, seconds, logf, kb=None, fb=None,
@@ -510,6 +621,7 @@ def cpu_baseline(k, f, u0, blob, C, M, L, iters_needed, conv_frac, seconds, logf
                     "rel_err_A": float(oracle.energy_norm(kt_b, torch.from_numpy(d))) / en_star}
         log(f"accuracy vs oracle: {accuracy}", logf)
     return {"value": conv_frac / (per_iter * iters_needed), "unit": "solves/sec", "cores": torch.get_num_threads(),
+            "host_cpus": os.cpu_count(), "host_cpu_model": cpu_model(),
             "kind": "oracle", "accuracy_vs_oracle": accuracy,
             "sample": f"first {n_it} FCG iterations (FP64 operator, m=5) of system 0 of the batch, "
                       f"{per_iter:.3f} s/iteration, scaled by the {iters_needed} iterations the batch's "
@@ -546,9 +658,11 @@ def main():
         log("copy calibration: 1 GiB read + 1 GiB written", logf)
         del a, b
 
-    if args.weights:
-        model = fc.Model(np.load(args.weights), C, M, L)
-        train_info = {"loaded": os.path.basename(args.weights)}
+    if not args.train_operator:
+        wb = np.load(args.weights).astype(np.float64)
+        model = fc.Model(wb, C, M, L)
+        train_info = {"loaded": os.path.relpath(args.weights, ROOT),
+                      "sha256_16": hashlib.sha256(wb.tobytes()).hexdigest()[:16]}
     else:
         # the benchmark's operator: 1024 training systems, lr 6e-4 (measured
         # best on the 512^2 batch among 256/1024 systems, lr 3e-4 .. 1e-3)
@@ -574,8 +688,9 @@ def main():
         iters = np.concatenate([o["iters"] for o in outs])
         status = np.concatenate([o["status"] for o in outs])
         tres = np.concatenate([o["true_rel_res"] for o in outs])
+        tresf = np.concatenate([o["true_rel_res_f"] for o in outs])
         results[op] = {"seconds": total, "steps": steps, "lat": lat, "iters": iters, "status": status,
-                       "tres": tres, "u": ulast, "prof": pr}
+                       "tres": tres, "tresf": tresf, "u": ulast, "prof": pr}
         log(f"op={op}: {steps} solves in {total:.3f}s, iters mean {iters.mean():.1f} max {iters.max()}, "
             f"status {np.bincount(status, minlength=4).tolist()}, true rel res max {tres.max():.2e}", logf)
 
@@ -590,6 +705,7 @@ def main():
         results[f"{main_op}_streams{args.streams}"] = {"seconds": total, "steps": len(outs), "lat": lat, "iters": iters,
                                                        "status": status,
                                                        "tres": np.concatenate([o["true_rel_res"] for o in outs]),
+                                                       "tresf": np.concatenate([o["true_rel_res_f"] for o in outs]),
                                                        "u": ulast}
         assert np.array_equal(iters[-B:], R["iters"][-B:]) and torch.equal(ulast, R["u"]), \
             "sub-batched solve differs from the single-stream solve"
@@ -689,7 +805,8 @@ def main():
              "iters_mean": round(float(Rr["iters"].mean()), 2), "iters_max": int(Rr["iters"].max()),
              "status_counts": {"ok": int(conv.sum()), "not_converged": int((Rr["status"] == 1).sum()),
                                "breakdown": int((Rr["status"] == 2).sum())},
-             "true_rel_res_max_converged": float(Rr["tres"][conv].max()) if conv.any() else None}
+             "true_rel_res_max_converged": float(Rr["tres"][conv].max()) if conv.any() else None,
+             "true_rel_res_f_max_converged": float(Rr["tresf"][conv].max()) if conv.any() else None}
         if ref is not None and op != "fp64":
             # same systems, last timed step of each; compare where both converged
             lo, lr_ = Rr["status"][-B:] == 0, ref["status"][-B:] == 0
@@ -700,6 +817,10 @@ def main():
         comparison[op] = d
 
     batch_cfg = batched(fc, torch, dev, model, C, M, L, logf)
+    cfg0 = config0(fc, torch, dev, logf)
+    train_tp = None
+    if args.train_bench_steps > 0:
+        train_tp = training_throughput(fc, torch, dev, C, M, L, args.train_bench_steps, logf)
 
     abl = None
     if args.ablation:
@@ -736,7 +857,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": main_op, "data": "synthetic",
         "config": {"workload": f"FCG-NO solve, {N}x{N} grid, batch {B}, k=exp(GRF) contrast 10..1e3, "
-                               f"NO L={L} C={C} M={M} trained at set-up, op {main_op} (FP32 accumulate), "
+                               f"NO L={L} C={C} M={M} trained on 64x64 systems (committed weights), "
+                               f"op {main_op} (FP32 accumulate), "
                                f"FP64 Krylov, m=5, tol {args.rtol:g}",
                    "grid": N, "batch": B, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 2),
@@ -746,7 +868,9 @@ def main():
         "kernels": per_kernel,
         "operator_utilisation": operator_util,
         "batched_fp32": batch_cfg,
-        "training": train_info,
+        "single_solve_32x32_fp64": cfg0,
+        "training_throughput": train_tp,
+        "operator": train_info,
         "serving": serve,
         "ablation": abl,
         "classical": classic,

@@ -159,14 +159,20 @@ size_t fcgno_solve_workspace_bytes(const fcgno_model* m, const fcgno_solve_desc*
  *   rel_hist host [batch][max_iter+1] float64 or NULL; out: ||r_i||/||r_0||,
  *           i = 0..iters, the rest of each row untouched
  *   true_rel_res host [batch] float64 or NULL; out: ||f - A u||_2 / ||r_0||_2
- *           recomputed from the returned u
+ *           recomputed from the returned u (the quantity the stopping test of
+ *           Table 1 bounds, here for the true rather than the recurrence residual)
+ *   true_rel_res_f host [batch] float64 or NULL; out: ||f - A u||_2 / ||f||_2
+ *           from the same u (0 if f = 0 and A u = 0; +inf if f = 0 otherwise);
+ *           with a random u_0 (Algorithm 1's initialisation) ||r_0|| can
+ *           exceed ||f|| by orders of magnitude, so this is the stricter figure
  * The call enqueues on stream, polls convergence from the host and returns
  * when every system has stopped; the outputs are then final.  Returns
  * FCGNO_OK if every system converged, FCGNO_NOT_CONVERGED otherwise. */
 fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc* d,
                          const double* k, const double* f, double* u, double* r_out,
                          int32_t* iters, int32_t* sys_status, double* rel_hist,
-                         double* true_rel_res, void* ws, size_t ws_bytes, void* stream);
+                         double* true_rel_res, double* true_rel_res_f, void* ws, size_t ws_bytes,
+                         void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* fcgno_precond_apply: w = B(r; theta) (the preconditioner of Sec. 2.4.2).   */
@@ -291,6 +297,7 @@ typedef struct {
   int32_t status;        /* FCGNO_SYS_* */
   int32_t iters;
   double true_rel_res;   /* ||f - A u|| / ||r0|| */
+  double true_rel_res_f; /* ||f - A u|| / ||f|| (as for fcgno_solve) */
 } fcgno_engine_result;
 
 /* Device bytes one request of grid n takes from the pool (0 if invalid). */

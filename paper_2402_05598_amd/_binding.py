@@ -40,7 +40,8 @@ class EngineDesc(ctypes.Structure):
 
 
 class EngineResult(ctypes.Structure):
-    _fields_ = [("id", ctypes.c_int64), ("status", c_int32), ("iters", c_int32), ("true_rel_res", c_double)]
+    _fields_ = [("id", ctypes.c_int64), ("status", c_int32), ("iters", c_int32), ("true_rel_res", c_double),
+                ("true_rel_res_f", c_double)]
 
 
 class FcgnoError(RuntimeError):
@@ -73,7 +74,7 @@ def lib():
     L.fcgno_solve_workspace_bytes.argtypes = [vp, POINTER(SolveDesc)]
     L.fcgno_solve_workspace_bytes.restype = c_size_t
     L.fcgno_solve.argtypes = [vp, POINTER(SolveDesc), vp, vp, vp, vp, POINTER(c_int32), POINTER(c_int32),
-                              POINTER(c_double), POINTER(c_double), vp, c_size_t, vp]
+                              POINTER(c_double), POINTER(c_double), POINTER(c_double), vp, c_size_t, vp]
     L.fcgno_solve.restype = c_int32
     L.fcgno_precond_workspace_bytes.argtypes = [vp, c_int32, c_int32, c_int32]
     L.fcgno_precond_workspace_bytes.restype = c_size_t
@@ -199,6 +200,11 @@ class Model:
                "fcgno_model_create")
         self.handle = h
         self.C, self.M, self.L = C, M, L
+        # weights version: bumped whenever the device weights change (set_weights,
+        # train_step), so that OperatorFunction never pairs saved activations with
+        # other weights; _loaded caches the blob OperatorFunction last loaded
+        self._version = 0
+        self._loaded = None
 
     def get_weights(self):
         out = np.empty(self.n_weights, dtype=np.float64)
@@ -210,6 +216,8 @@ class Model:
         w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
         _check(lib().fcgno_model_set_weights(self.handle, w.ctypes.data_as(POINTER(c_double)), w.size),
                "fcgno_model_set_weights")
+        self._version += 1
+        self._loaded = None
 
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:
@@ -237,7 +245,7 @@ def solve(model, k, f, u, op="bf16", m_max=5, max_iter=300, rtol=1e-6, r_out=Non
     "sgs_rb") applied precond_steps times.  streams > 1 splits the batch into
     that many sub-batches on library-owned streams (same bits, overlapped
     kernels).  Returns a dict with numpy arrays iters, status, true_rel_res
-    and (if hist) hist [B][max_iter+1]."""
+    true_rel_res_f (||f - A u|| / ||f||) and (if hist) hist [B][max_iter+1]."""
     B, N = _grid(f, "f")
     if tuple(k.shape) != (B, N + 2, N + 2) or tuple(u.shape) != (B, N, N):
         raise FcgnoError("shape mismatch: k [B][N+2][N+2], f and u [B][N][N]")
@@ -252,15 +260,17 @@ def solve(model, k, f, u, op="bf16", m_max=5, max_iter=300, rtol=1e-6, r_out=Non
     iters = np.zeros(B, dtype=np.int32)
     status = np.zeros(B, dtype=np.int32)
     tres = np.zeros(B, dtype=np.float64)
+    tresf = np.zeros(B, dtype=np.float64)
     hh = np.full((B, max_iter + 1), np.nan) if hist else None
     rc = lib().fcgno_solve(
         h, ctypes.byref(d), _dev_f64(k, "k"), _dev_f64(f, "f"), _dev_f64(u, "u"),
         _dev_f64(r_out, "r_out") if r_out is not None else None,
         iters.ctypes.data_as(POINTER(c_int32)), status.ctypes.data_as(POINTER(c_int32)),
         hh.ctypes.data_as(POINTER(c_double)) if hist else None,
-        tres.ctypes.data_as(POINTER(c_double)), ctypes.c_void_p(ws.data_ptr()), _nbytes(ws), _stream(stream))
+        tres.ctypes.data_as(POINTER(c_double)), tresf.ctypes.data_as(POINTER(c_double)),
+        ctypes.c_void_p(ws.data_ptr()), _nbytes(ws), _stream(stream))
     _check(rc, "fcgno_solve")
-    out = {"iters": iters, "status": status, "true_rel_res": tres, "rc": rc}
+    out = {"iters": iters, "status": status, "true_rel_res": tres, "true_rel_res_f": tresf, "rc": rc}
     if hist:
         out["hist"] = hh
     return out
@@ -411,6 +421,8 @@ def train_step(model, opt, k, r, e, op="fp32", workspace=None, stream=None, retu
     _same(e, (B, N, N), "e")
     ws = workspace if workspace is not None else train_workspace(model, N, B, op, r.device)
     out = c_double(0.0)
+    model._version += 1    # AdamW updates the device weights in place
+    model._loaded = None
     _check(lib().fcgno_train_step_loss(model.handle, opt.handle, N, B, OP[op], LOSS[loss], _dev_f64(k, "k"),
                                        _dev_f64(r, "r"), _dev_f64(e, "e"),
                                        ctypes.byref(out) if return_loss else None,
@@ -506,7 +518,8 @@ class Engine:
         for i in range(n):
             r = buf[i]
             self._held.pop(r.id, None)
-            out.append({"id": r.id, "status": r.status, "iters": r.iters, "true_rel_res": r.true_rel_res})
+            out.append({"id": r.id, "status": r.status, "iters": r.iters, "true_rel_res": r.true_rel_res,
+                        "true_rel_res_f": r.true_rel_res_f})
         return out
 
     def close(self):
@@ -526,17 +539,21 @@ class OperatorFunction(torch.autograd.Function):
     """w = B(r; theta) with the hand-written HIP backward for theta.
 
     ``weights`` is the float64 blob; it is loaded into ``model`` when it differs
-    from the model's current weights.  Gradients flow to the weights and to r
-    (not to k)."""
+    from the blob this function last loaded there (or the model's weights have
+    changed since).  If the model's weights change between forward and
+    backward, backward reloads the forward's blob first, so the gradient always
+    pairs the saved activations with the weights that produced them.
+    Gradients flow to the weights and to r (not to k)."""
 
     @staticmethod
     def forward(ctx, weights, model, k, r, op="fp64"):
         wh = weights.detach().to("cpu", torch.float64).contiguous().numpy()
-        if getattr(model, "_loaded", None) is None or not np.array_equal(model._loaded, wh):
+        if model._loaded is None or not np.array_equal(model._loaded, wh):
             model.set_weights(wh)
             model._loaded = wh.copy()
         w, ws = op_forward(model, k, r, op)
         ctx.model, ctx.op, ctx.ws = model, op, ws
+        ctx.version, ctx.wh = model._version, model._loaded
         ctx.save_for_backward(k, r)
         ctx.wdev = weights.device
         return w
@@ -544,6 +561,9 @@ class OperatorFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_w):
         k, r = ctx.saved_tensors
+        if ctx.model._version != ctx.version:
+            ctx.model.set_weights(ctx.wh)
+            ctx.model._loaded = ctx.wh
         if ctx.needs_input_grad[3]:
             g, gr = op_backward(ctx.model, k, r, grad_w, ctx.ws, ctx.op, input_grad=True)
         else:

@@ -247,7 +247,7 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
 bool arch_ok_for(const fcgno_model* m, int N) { return m && 2 * m->arch.modes <= N; }
 
 // Fill the per-system operator pointers of a plan.
-void fill_no(const fcgno_model* m, const Plan& p, char* base, int N, int B, int op, std::vector<SysDev>& h) {
+void fill_no(const fcgno_model* m, const Plan& p, char* base, int N, int B, int op, SysDev* h) {
   const int C = m->arch.width, M = m->arch.modes, MP = p.MP;
   const size_t n = (size_t)N * N;
   const int esz = op_esize(op), asz = acc_esize(op);
@@ -390,7 +390,8 @@ struct EventSet {
 
 fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const double* k, const double* f,
                         double* u, double* r_out, int32_t* iters, int32_t* sys_status, double* rel_hist,
-                        double* true_rel_res, void* ws, size_t ws_bytes, void* stream, const Record* rec) {
+                        double* true_rel_res, double* true_rel_res_f, void* ws, size_t ws_bytes, void* stream,
+                        const Record* rec) {
   fcgno_status cs = check_desc(m, d);
   if (cs != FCGNO_OK) return cs;
   if (!k || !f || !u || !iters || !sys_status || !ws) return fail(FCGNO_E_INVALID, "null pointer argument");
@@ -426,7 +427,7 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
     sd.n_active = (decltype(sd.n_active))(counter + grp);
     if (op == PJAC) sd.tmp = (decltype(sd.tmp))((double*)(base + p.tmp) + (size_t)b * n);
   }
-  if (is_no(op)) fill_no(m, p, base, N, B, op, h);
+  if (is_no(op)) fill_no(m, p, base, N, B, op, h.data());
   const SysDev* sysdev = (const SysDev*)(base + p.sysdev);
   HIPCHK(hipMemcpyAsync(base + p.sysdev, h.data(), B * sizeof(SysDev), hipMemcpyHostToDevice, s));
   KrylovLaunch KL{sysdev, B, N, d->m_max, s};
@@ -553,6 +554,7 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
     sys_status[b] = hs[b].status;
     if (hs[b].status != S_OK) all_ok = false;
     if (true_rel_res) true_rel_res[b] = hs[b].tres;
+    if (true_rel_res_f) true_rel_res_f[b] = hs[b].tresf;
     if (rel_hist) {
       const int upto = hs[b].status == S_NONFINITE ? 0 : hs[b].iters;
       for (int i = 0; i <= upto; ++i)
@@ -565,10 +567,10 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
 
 extern "C" fcgno_status fcgno_solve(const fcgno_model* m, const fcgno_solve_desc* d, const double* k,
                                     const double* f, double* u, double* r_out, int32_t* iters,
-                                    int32_t* sys_status, double* rel_hist, double* true_rel_res, void* ws,
-                                    size_t ws_bytes, void* stream) {
-  return solve_impl(m, d, k, f, u, r_out, iters, sys_status, rel_hist, true_rel_res, ws, ws_bytes, stream,
-                    nullptr);
+                                    int32_t* sys_status, double* rel_hist, double* true_rel_res,
+                                    double* true_rel_res_f, void* ws, size_t ws_bytes, void* stream) {
+  return solve_impl(m, d, k, f, u, r_out, iters, sys_status, rel_hist, true_rel_res, true_rel_res_f, ws, ws_bytes,
+                    stream, nullptr);
 }
 
 extern "C" size_t fcgno_krylov_samples_workspace_bytes(int32_t n, int32_t batch, int32_t max_iter) {
@@ -595,14 +597,14 @@ extern "C" fcgno_status fcgno_krylov_samples(int32_t N, int32_t B, int32_t m_ite
   // u* = A^-1 f by conjugate gradients to a tight tolerance
   HIPCHK(hipMemcpyAsync(ustar, u0, (size_t)B * n * 8, hipMemcpyDeviceToDevice, s));
   fcgno_solve_desc d1{N, B, 1, max_iter, 1e-13, PID, 0};
-  fcgno_status r1 = solve_impl(nullptr, &d1, k, f, ustar, nullptr, it.data(), st.data(), nullptr, nullptr, ws, sol,
+  fcgno_status r1 = solve_impl(nullptr, &d1, k, f, ustar, nullptr, it.data(), st.data(), nullptr, nullptr, nullptr, ws, sol,
                                stream, nullptr);
   if (r1 < 0) return r1;
   // the recorded CG run (FCG with B = I, window 1) from u0
   HIPCHK(hipMemcpyAsync(ucur, u0, (size_t)B * n * 8, hipMemcpyDeviceToDevice, s));
   fcgno_solve_desc d2{N, B, 1, m_iter, 1e-300, PID, m_iter};
   Record rec{m_iter, r_out, e_out, ustar};
-  fcgno_status r2 = solve_impl(nullptr, &d2, k, f, ucur, nullptr, it.data(), st.data(), nullptr, nullptr, ws, sol,
+  fcgno_status r2 = solve_impl(nullptr, &d2, k, f, ucur, nullptr, it.data(), st.data(), nullptr, nullptr, nullptr, ws, sol,
                                stream, &rec);
   if (r2 < 0) return r2;
   return r1;
@@ -625,8 +627,8 @@ extern "C" fcgno_status fcgno_residual_samples(int32_t N, int32_t B, int32_t max
   // A^-1 f by conjugate gradients to a tight tolerance, starting from u
   HIPCHK(hipMemcpyAsync(ustar, u, (size_t)B * n * 8, hipMemcpyDeviceToDevice, s));
   fcgno_solve_desc d1{N, B, 1, max_iter, 1e-13, PID, 0};
-  fcgno_status r1 = solve_impl(nullptr, &d1, k, f, ustar, nullptr, it.data(), st.data(), nullptr, nullptr, ws,
-                               p.total, stream, nullptr);
+  fcgno_status r1 = solve_impl(nullptr, &d1, k, f, ustar, nullptr, it.data(), st.data(), nullptr, nullptr, nullptr,
+                               ws, p.total, stream, nullptr);
   if (r1 < 0) return r1;
   // r = f - A u into r_out, then e = A^-1 f - u (state and partials reused from the plan)
   std::vector<SysDev> h(B);
@@ -659,9 +661,15 @@ extern "C" fcgno_status fcgno_residual_samples(int32_t N, int32_t B, int32_t max
 namespace fcgno_host {
 
 fcgno_status operator_forward(const fcgno_model* m, const Plan& p, char* base, int N, int B, int op,
-                              const double* k, const double* r, double* w, bool train, hipStream_t s) {
+                              const double* k, const double* r, double* w, bool train, hipStream_t s,
+                              SysDev* table) {
   const size_t n = (size_t)N * N;
-  std::vector<SysDev> h(B);
+  std::vector<SysDev> own;
+  if (!table) {
+    own.resize(B);
+    table = own.data();
+  }
+  SysDev* h = table;
   SysState* st = (SysState*)(base + p.state);
   for (int b = 0; b < B; ++b) {
     SysDev& sd = h[b];
@@ -675,7 +683,7 @@ fcgno_status operator_forward(const fcgno_model* m, const Plan& p, char* base, i
   }
   fill_no(m, p, base, N, B, op, h);
   const SysDev* sysdev = (const SysDev*)(base + p.sysdev);
-  HIPCHK(hipMemcpyAsync(base + p.sysdev, h.data(), B * sizeof(SysDev), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(base + p.sysdev, h, B * sizeof(SysDev), hipMemcpyHostToDevice, s));
   KrylovLaunch KL{sysdev, B, N, 1, s};
   launch_init_state(KL, 1, 1.0);
   NOLaunch NL = make_no(m, p, base, sysdev, N, B, op, s);

@@ -49,6 +49,8 @@ struct SysState {
   double alpha;
   double snorm;   // ||r_i||_2 / N, the operator's input scale
   double tres;    // ||f - A u||_2 / ||r_0||_2 (final check)
+  double tresf;   // ||f - A u||_2 / ||f||_2 (final check)
+  double ff;      // ||f||_2^2
   double rtol;
   double ps_ring[MAXW + 1];   // (p_k, A p_k) by ring slot k mod (m_max+1)
   double coef[MAXW];          // (w_i, s_k)/(p_k, s_k) of the current window
@@ -213,7 +215,8 @@ void launch_update(const KrylovLaunch& L);
 void launch_jacobi(const KrylovLaunch& L, int steps);
 void launch_rbsgs(const KrylovLaunch& L, int steps);
 void launch_record(const KrylovLaunch& L, int it, int m, double* rec_r, double* rec_e, const double* ustar);
-// flags[3b..3b+2] = {active, status, iters}, tres[b] = true relative residual
+// flags[3b..3b+2] = {active, status, iters}; tres[2b], tres[2b+1] = true
+// residual relative to ||r_0|| and to ||f||
 void launch_export(const SysDev* sys, int nsys, int* flags, double* tres, hipStream_t s);
 
 struct NOLaunch {

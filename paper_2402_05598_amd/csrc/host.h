@@ -101,13 +101,16 @@ size_t part_blocks(int N);
 void bwd_geometry(int N, int prec, int& Sb, int& nbs);
 Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int op, int kind);
 bool arch_ok_for(const fcgno_model* m, int N);
-void fill_no(const fcgno_model* m, const Plan& p, char* base, int N, int B, int op, std::vector<SysDev>& h);
+void fill_no(const fcgno_model* m, const Plan& p, char* base, int N, int B, int op, SysDev* h);
 NOLaunch make_no(const fcgno_model* m, const Plan& p, char* base, const SysDev* sysdev, int N, int B, int op,
                  hipStream_t s);
 fcgno_status operator_setup(const fcgno_model* m, const Plan& p, char* base, const NOLaunch& NL, int N, int B,
                             int op, hipStream_t s);
+// table: host storage for the B per-system pointer records (NULL: a vector of
+// its own); it must stay valid until the call returns.
 fcgno_status operator_forward(const fcgno_model* m, const Plan& p, char* base, int N, int B, int op,
-                              const double* k, const double* r, double* w, bool train, hipStream_t s);
+                              const double* k, const double* r, double* w, bool train, hipStream_t s,
+                              SysDev* table = nullptr);
 // Model weights (api.hip).
 fcgno_status alloc_derived(fcgno_model* m);
 void derive_all(fcgno_model* m, hipStream_t s);

@@ -56,21 +56,24 @@ __global__ __launch_bounds__(64) void k_init_state(const SysDev* sys, int nsys, 
   st->alpha = 0.0;
   st->snorm = 0.0;
   st->tres = 0.0;
+  st->tresf = 0.0;
+  st->ff = 0.0;
   st->rtol = rtol;
   for (int q = 0; q <= MAXW; ++q) st->ps_ring[q] = 0.0;
   for (int q = 0; q < MAXW; ++q) st->coef[q] = 0.0;
   if (b == 0) *sys[0].n_active = nsys;
 }
 
-// mode 0: r = f - A u, partial ||r_0||^2 and input checks (k > 0 and finite,
-//         f and u finite).  mode 1: partial ||f - A u||^2 only, every system.
+// mode 0: r = f - A u, partial ||r_0||^2, ||f||^2 and input checks (k > 0
+//         and finite, f and u finite).  mode 1: partial ||f - A u||^2 only,
+//         every system.
 __global__ __launch_bounds__(256) void k_residual(const SysDev* sys, int N, int mode) {
   __shared__ double lds[4];
   const SysDev sd = sys[blockIdx.y];
   if (mode == 0 && !sd.st->active) return;
   const int n = N * N;
   const int K = N + 2;
-  double acc = 0.0, bad = 0.0;
+  double acc = 0.0, bad = 0.0, ff = 0.0;
 #pragma unroll
   for (int e = 0; e < PPT; ++e) {
     const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
@@ -93,15 +96,20 @@ __global__ __launch_bounds__(256) void k_residual(const SysDev* sys, int N, int 
         if (j == N - 1) { double t = sd.k[(i + 1) * K + N + 1]; ok = ok && t > 0.0 && isfinite(t); }
         if (!ok) bad += 1.0;
         sd.r[p] = rv;
+        ff += fv * fv;
       }
       acc += rv * rv;
     }
   }
   acc = block_sum(acc, lds);
-  if (mode == 0) bad = block_sum(bad, lds);
+  if (mode == 0) {
+    bad = block_sum(bad, lds);
+    ff = block_sum(ff, lds);
+  }
   if (threadIdx.x == 0) {
     sd.part[(size_t)blockIdx.x * NQ + 0] = acc;
     sd.part[(size_t)blockIdx.x * NQ + 1] = bad;
+    sd.part[(size_t)blockIdx.x * NQ + 2] = ff;
   }
 }
 
@@ -327,9 +335,10 @@ __global__ __launch_bounds__(256) void k_fin(const SysDev* sys, int N, int mode)
       else if (i + 1 >= st->max_iter) deactivate(st, sd.n_active, S_NOTCONV, i + 1);
     }
   } else if (mode == 3) {
-    const double rr = fsum(0), nbad = fsum(1);
+    const double rr = fsum(0), nbad = fsum(1), ff = fsum(2);
     if (threadIdx.x == 0) {
       st->rr0 = rr;
+      st->ff = ff;
       st->rr = rr;
       st->snorm = sqrt(rr) / (double)N;
       if (nbad > 0.0 || !isfinite(rr)) {
@@ -342,7 +351,11 @@ __global__ __launch_bounds__(256) void k_fin(const SysDev* sys, int N, int mode)
     }
   } else if (mode == 4) {
     const double rr = fsum(0);
-    if (threadIdx.x == 0) st->tres = st->rr0 > 0.0 ? sqrt(rr / st->rr0) : 0.0;
+    if (threadIdx.x == 0) {
+      st->tres = st->rr0 > 0.0 ? sqrt(rr / st->rr0) : 0.0;
+      // f = 0: zero when u solves A u = 0 exactly, else not defined (+inf)
+      st->tresf = st->ff > 0.0 ? sqrt(rr / st->ff) : (rr > 0.0 ? __longlong_as_double(0x7ff0000000000000ll) : 0.0);
+    }
   } else {
     const double rr = fsum(0);
     if (threadIdx.x == 0) {
@@ -431,7 +444,8 @@ __global__ __launch_bounds__(64) void k_export(const SysDev* sys, int nsys, int*
   flags[3 * b] = st->active;
   flags[3 * b + 1] = st->status;
   flags[3 * b + 2] = st->iters;
-  tres[b] = st->tres;
+  tres[2 * b] = st->tres;
+  tres[2 * b + 1] = st->tresf;
 }
 
 // ---- launchers ------------------------------------------------------------

@@ -56,7 +56,7 @@ struct fcgno_engine {
   std::vector<fcgno_engine_result> done;
   int64_t next_id = 1;
   int* hflags = nullptr;     // pinned host copies of the exported state, max_slots entries
-  double* htres = nullptr;
+  double* htres = nullptr;   // two per slot: relative to ||r_0|| and to ||f||
   // Groups of different N run on separate streams (default priority), so a
   // large group's bandwidth-bound launches and a small group's latency-bound
   // ones overlap on the device; every step first waits for the caller's stream.
@@ -115,7 +115,7 @@ size_t group_bytes(const fcgno_model* m, int op, int N, int slots, EngGroup* g) 
   t.table = cv.take((size_t)slots * sizeof(SysDev));
   t.ftable = cv.take((size_t)slots * sizeof(SysDev));
   t.flags = cv.take((size_t)slots * 3 * sizeof(int));
-  t.tres = cv.take((size_t)slots * sizeof(double));
+  t.tres = cv.take((size_t)slots * 2 * sizeof(double));
   if (g) {
     g->E64 = t.E64; g->Eacc = t.Eacc; g->T = t.T; g->TT = t.TT;
     g->table = t.table; g->ftable = t.ftable; g->flags = t.flags; g->tres = t.tres;
@@ -156,26 +156,24 @@ NOLaunch group_no(const fcgno_engine* e, const EngGroup& g, const SysDev* table,
   return L;
 }
 
-fcgno_status group_open(fcgno_engine* e, int N, EngGroup** out) {
-  auto it = e->groups.find(N);
-  if (it != e->groups.end()) {
-    *out = &it->second;
-    return FCGNO_OK;
-  }
-  EngGroup g;
-  g.N = N;
+// Lay out a new group of grid N and reserve its pool block; nothing is queued
+// on the device yet, so a failed admission can hand the block back at once.
+bool group_reserve(fcgno_engine* e, int N, EngGroup* g) {
+  g->N = N;
+  g->bytes = group_bytes(e->d.op == PID ? nullptr : e->m, e->d.op, N, e->d.max_slots, g);
+  return pool_alloc(e, g->bytes, &g->off);
+}
+
+// Register a reserved group: pick its lane and queue its twiddle tables there.
+EngGroup* group_commit(fcgno_engine* e, EngGroup g) {
   g.s = e->lanes[e->next_lane];
-  g.bytes = group_bytes(e->d.op == PID ? nullptr : e->m, e->d.op, N, e->d.max_slots, &g);
-  if (!pool_alloc(e, g.bytes, &g.off)) return FCGNO_E_NOMEM;
+  e->next_lane = (e->next_lane + 1) % (int)e->lanes.size();
   if (e->d.op != PID) {
     const NOLaunch NL = group_no(e, g, nullptr, 0);
     char* base = e->pool + g.off;
     launch_tables(NL, (double*)(base + g.E64), base + g.Eacc, base + g.T, base + g.TT);
   }
-  e->next_lane = (e->next_lane + 1) % (int)e->lanes.size();
-  auto res = e->groups.emplace(N, g);
-  *out = &res.first->second;
-  return FCGNO_OK;
+  return &e->groups.emplace(g.N, g).first->second;
 }
 
 void group_close(fcgno_engine* e, int N) {
@@ -207,7 +205,7 @@ fcgno_status admit(fcgno_engine* e, EngReq& q, EngGroup& g) {
   sd.n_active = (decltype(sd.n_active))(base + p.counter);
   if (op != PID) {
     std::vector<SysDev> h(1, sd);
-    fill_no(m, p, base, N, 1, op, h);
+    fill_no(m, p, base, N, 1, op, h.data());
     sd = h[0];
   }
   const SysDev* own = (const SysDev*)(base + p.sysdev);
@@ -274,7 +272,7 @@ extern "C" fcgno_status fcgno_engine_create(const fcgno_model* m, const fcgno_en
     e->pool = nullptr;
     st = fail(FCGNO_E_NOMEM, "cannot allocate the engine pool");
   } else if (hipHostMalloc((void**)&e->hflags, (size_t)d->max_slots * 3 * sizeof(int), 0) != hipSuccess ||
-             hipHostMalloc((void**)&e->htres, (size_t)d->max_slots * sizeof(double), 0) != hipSuccess) {
+             hipHostMalloc((void**)&e->htres, (size_t)d->max_slots * 2 * sizeof(double), 0) != hipSuccess) {
     st = fail(FCGNO_E_HIP, "hipHostMalloc failed");
   }
   if (st != FCGNO_OK) {
@@ -320,17 +318,23 @@ extern "C" fcgno_status fcgno_engine_step(fcgno_engine* e, int32_t* n_active, in
   HIPCHK(hipEventRecord(e->ready, e->s));
   for (hipStream_t ls : e->lanes) HIPCHK(hipStreamWaitEvent(ls, e->ready, 0));
   // 1. admission: scan the queue in arrival order, admit what fits now
+  // A request needs its own pool block and, for a grid size with no group
+  // yet, the group's block too.  Both are reserved before any work is queued:
+  // a block handed back after queuing work on one lane could be reused at
+  // once by a request on another lane while that work is still pending.
   for (auto it = e->queue.begin(); it != e->queue.end();) {
     if ((int)e->active.size() >= e->d.max_slots) break;
-    EngGroup* g = nullptr;
-    const bool had_group = e->groups.count(it->N) != 0;
-    if (group_open(e, it->N, &g) != FCGNO_OK) { ++it; continue; }
+    auto git = e->groups.find(it->N);
+    const bool new_group = git == e->groups.end();
+    EngGroup ng;
+    if (new_group && !group_reserve(e, it->N, &ng)) { ++it; continue; }
     size_t off = 0;
     if (!pool_alloc(e, it->bytes, &off)) {
-      if (!had_group && g->members.empty()) group_close(e, it->N);
+      if (new_group) pool_free(e, ng.off, ng.bytes);
       ++it;
       continue;
     }
+    EngGroup* g = new_group ? group_commit(e, ng) : &git->second;
     EngReq q = *it;
     q.off = off;
     it = e->queue.erase(it);
@@ -393,7 +397,8 @@ extern "C" fcgno_status fcgno_engine_step(fcgno_engine* e, int32_t* n_active, in
     launch_export(ft, F, (int*)(base + g.flags), (double*)(base + g.tres), g.s);
     HIPCHK(hipMemcpyAsync(e->hflags + 3 * ho, base + g.flags, (size_t)F * 3 * sizeof(int), hipMemcpyDeviceToHost,
                           g.s));
-    HIPCHK(hipMemcpyAsync(e->htres + ho, base + g.tres, (size_t)F * sizeof(double), hipMemcpyDeviceToHost, g.s));
+    HIPCHK(hipMemcpyAsync(e->htres + 2 * ho, base + g.tres, (size_t)F * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                          g.s));
     ho += F;
     any = true;
   }
@@ -408,7 +413,8 @@ extern "C" fcgno_status fcgno_engine_step(fcgno_engine* e, int32_t* n_active, in
         r.id = id;
         r.status = e->hflags[3 * (g.hoff + b) + 1];
         r.iters = e->hflags[3 * (g.hoff + b) + 2];
-        r.true_rel_res = e->htres[g.hoff + b];
+        r.true_rel_res = e->htres[2 * (g.hoff + b)];
+        r.true_rel_res_f = e->htres[2 * (g.hoff + b) + 1];
         e->done.push_back(r);
         EngReq& q = e->active.at(id);
         pool_free(e, q.off, q.bytes);

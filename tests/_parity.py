@@ -45,3 +45,27 @@ def iteration_tolerance(ref_iters, shadow_iters):
     the oracle's own shadows, at least 2."""
     allits = list(shadow_iters) + [ref_iters]
     return max(2.0, 1.5 * (max(allits) - min(allits)))
+
+
+# Operator parity bounds per precision, from the measured errors against the
+# oracle (FP64 ~1e-16, FP32 ~3e-8, BF16 1.5e-4..8e-4 in the relative 2-norm):
+# about ten times those.  Each system is checked in the relative 2-norm and
+# point by point, the largest absolute difference against the largest value,
+# so that one bad tile or a wrong ragged-edge row cannot hide in the norm.
+NORM_TOL = {"fp64": 1e-13, "fp32": 3e-7, "bf16": 3e-3}
+MAX_TOL = {"fp64": 1e-13, "fp32": 1e-6, "bf16": 5e-3}
+
+
+def assert_operator_close(got, ref, op, label=""):
+    """got, ref: numpy [N][N] (one system).  Prints and asserts both measures."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    assert got.shape == ref.shape, (got.shape, ref.shape)
+    assert np.all(np.isfinite(got)), f"{label} {op}: non-finite output"
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    mx = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    # worst row, to name a bad tile or edge
+    row = int(np.argmax(np.max(np.abs(got - ref), axis=1)))
+    print(f"  {label} {op}: rel2 {rel:.2e} max {mx:.2e} (worst row {row})", flush=True)
+    assert rel < NORM_TOL[op], (label, op, "rel2", rel)
+    assert mx < MAX_TOL[op], (label, op, "max", mx, row)

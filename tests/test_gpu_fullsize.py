@@ -1,17 +1,22 @@
 """Parity at the benchmark's full sizes, on sampled systems the oracle computes
 whole: the operator (width 32, 12 modes, 4 layers) on 512x512 x 16 systems in
-every precision and on 128x128 and 256x256 x 64 systems in FP32, and the first
-FCG iterations of the 512x512 x 16 batch in the launch configuration the
-benchmark times (m = 5, check every 4 iterations): FP64 residual histories to
-1e-10, the BF16 and FP32 operator's to their operator tolerance, the returned
-true residual recomputed on the CPU, and one system solved alone equal to the
-same system inside the batch."""
+every precision, on 128x128 and 256x256 x 64 systems in FP32, and above 512
+points per row (520 and 1024: the layer kernel then splits each row into
+segments of 512 points and the spectral forward transform adds their partial
+sums) in every precision, each system checked in the 2-norm and point by
+point; the first FCG iterations of the 512x512 x 16 batch in the launch
+configuration the benchmark times (m = 5, check every 4 iterations) and of a
+1024x1024 system: FP64 residual histories to 1e-10, the BF16 and FP32
+operator's to their operator tolerance, the returned true residual recomputed
+on the CPU, and one system solved alone equal to the same system inside the
+batch."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import synth
+from _parity import assert_operator_close
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +40,9 @@ def weights():
 
 @pytest.mark.parametrize("N,B,ops,sample", [(512, 16, ("fp64", "fp32", "bf16"), (0, 15)),
                                             (128, 64, ("fp32",), (0, 37, 63)),
-                                            (256, 64, ("fp32",), (5, 63))])
+                                            (256, 64, ("fp32",), (5, 63)),
+                                            (520, 2, ("fp64", "fp32", "bf16"), (0, 1)),
+                                            (1024, 2, ("fp64", "fp32", "bf16"), (0, 1))])
 def test_operator_full_size_sampled(dev, weights, N, B, ops, sample):
     print(f"full-size operator N={N} B={B}", flush=True)
     wb, w = weights
@@ -45,11 +52,8 @@ def test_operator_full_size_sampled(dev, weights, N, B, ops, sample):
     refs = {b: oracle.no_apply(w, torch.from_numpy(k[b]), torch.from_numpy(f[b])).numpy() for b in sample}
     for op in ops:
         got = fc.precond_apply(model, kd, fd, op=op).cpu().numpy()
-        tol = {"fp64": 1e-12, "fp32": 2e-5, "bf16": 3e-2}[op]
         for b in sample:
-            rel = np.linalg.norm(got[b] - refs[b]) / np.linalg.norm(refs[b])
-            print(f"  {op} b={b} rel={rel:.2e}", flush=True)
-            assert rel < tol, (op, b, rel)
+            assert_operator_close(got[b], refs[b], op, f"N={N} b={b}")
         assert np.all(np.isfinite(got))
     model.close()
 
@@ -91,4 +95,29 @@ def test_fcg_full_size_first_iterations(dev, weights):
                            max_iter=its, rtol=1e-300, check_every=4)
             assert torch.equal(u1[0], u[b])
             assert np.array_equal(one["hist"][0], out["hist"][b])
+    model.close()
+
+
+def test_fcg_1024_first_iterations(dev, weights):
+    """One 1024x1024 system (two row segments per layer-kernel row): six FCG
+    iterations with the FP64 operator against the oracle's Algorithm 1, the
+    residual history to 1e-10 and the iterate's increment point by point."""
+    N, its = 1024, 6
+    wb, w = weights
+    k, f, u0, _ = synth.batch(2, 1, N, (10.0, 1000.0))
+    kt = torch.from_numpy(k[0])
+    ref = oracle.fcg(k[0], f[0], u0[0], lambda r: oracle.no_apply(w, kt, r), m_max=5, max_iter=its, tol=1e-300)
+    model = fc.Model(wb, C, M, L)
+    kd, fd = torch.from_numpy(k).to(dev), torch.from_numpy(f).to(dev)
+    u = torch.from_numpy(u0).to(dev)
+    out = fc.solve(model, kd, fd, u, op="fp64", m_max=5, max_iter=its, rtol=1e-300, check_every=4)
+    h = out["hist"][0, :its + 1]
+    hr = np.asarray(ref.hist)
+    rel = np.max(np.abs(h - hr) / hr)
+    du_g = u[0].cpu().numpy() - u0[0]
+    du_o = ref.u.numpy() - u0[0]
+    mx = np.max(np.abs(du_g - du_o)) / np.max(np.abs(du_o))
+    print(f"  1024 fcg fp64: rel hist diff {rel:.2e}, max increment diff {mx:.2e}", flush=True)
+    assert rel < 1e-10
+    assert mx < 1e-9
     model.close()

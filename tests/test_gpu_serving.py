@@ -1,10 +1,14 @@
 """Serving engine (continuous batching) through the C ABI: every request's
 result is the same alone and in a mix of grid sizes and arrival times, equals
-the batched solve of the same system, and admission respects the pool."""
+the batched solve of the same system and the oracle's Algorithm 1 on the same
+request (first iterations point by point, up to 1024x1024; converged BF16
+requests by the oracle's own residual), and admission respects the pool,
+including a large request that is refused for now between small ones."""
 import numpy as np
 import pytest
 import torch
 
+import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -36,11 +40,15 @@ def _system(seed, N, dev):
 def _run(engine, jobs, arrivals):
     """jobs: list of (k, f, u); arrivals[i] = engine step before which job i is
     submitted.  Returns {job index: result} and the largest active count."""
+    return _run_rtol(engine, jobs, arrivals, 1e-6, 400)
+
+
+def _run_rtol(engine, jobs, arrivals, rtol, max_iter):
     ids, res, step, peak = {}, {}, 0, 0
     while len(res) < len(jobs):
         for i, a in enumerate(arrivals):
             if a == step and i not in ids.values():
-                ids[engine.submit(*jobs[i], rtol=1e-6, max_iter=400)] = i
+                ids[engine.submit(*jobs[i], rtol=rtol, max_iter=max_iter)] = i
         active, _ = engine.step()
         peak = max(peak, active)
         for r in engine.poll():
@@ -105,3 +113,94 @@ def test_admission_by_footprint(dev, model):
     with pytest.raises(fc.FcgnoError):
         eng.submit(big[0], big[1], big[2].clone())
     eng.close()
+
+
+def test_refused_admission_leaves_others_intact(dev, model):
+    """A pool that holds a 160x160 request alone but not beside a 64x64 one:
+    the large request, queued first while a 64x64 one runs, is refused for now
+    and hands its group's block back before any work is queued there; the 64x64
+    requests behind it are admitted into that space and give the same bits as
+    alone; the large request runs once the small ones have left."""
+    probe = fc.Engine(model, op="fp64", m_max=5, check_every=4, max_slots=4, budget_bytes=1 << 30)
+    r64, r160 = probe.request_bytes(64, 400), probe.request_bytes(160, 400)
+    probe.close()
+    assert r160 > 4 * r64
+    # the large request fits alone (with its group's tables, far below r64 / 4),
+    # not beside a 64x64 one, while three 64x64 ones fit together
+    budget = r160 + (3 * r64) // 4
+    small = [_system(900 + i, 64, dev) for i in range(3)]
+    big = _system(950, 160, dev)
+    alone = []
+    for s_ in small:
+        eng = fc.Engine(model, op="fp64", m_max=5, check_every=4, max_slots=4, budget_bytes=budget)
+        u = s_[2].clone()
+        res, _ = _run(eng, [(s_[0], s_[1], u)], [0])
+        alone.append((u, res[0]))
+        eng.close()
+    eng = fc.Engine(model, op="fp64", m_max=5, check_every=4, max_slots=4, budget_bytes=budget)
+    us = [s_[2].clone() for s_ in small]
+    ub = big[2].clone()
+    # step 0: the first small request occupies the pool; step 1: the big one
+    # (refused while the first is active) is queued ahead of the other two
+    jobs = [(small[0][0], small[0][1], us[0]), (big[0], big[1], ub),
+            (small[1][0], small[1][1], us[1]), (small[2][0], small[2][1], us[2])]
+    res, peak = _run(eng, jobs, [0, 1, 1, 1])
+    eng.close()
+    for j, i in ((0, 0), (2, 1), (3, 2)):
+        assert torch.equal(us[i], alone[i][0]), f"small request {i} differs from its alone run"
+        assert res[j]["iters"] == alone[i][1]["iters"]
+    eng1 = fc.Engine(model, op="fp64", m_max=5, check_every=4, max_slots=4, budget_bytes=budget)
+    ub1 = big[2].clone()
+    rb, _ = _run(eng1, [(big[0], big[1], ub1)], [0])
+    eng1.close()
+    assert torch.equal(ub, ub1) and res[1]["iters"] == rb[0]["iters"]
+
+
+@pytest.mark.parametrize("N", [64, 130, 1024])
+def test_engine_first_iterations_match_oracle(dev, model, N):
+    """FP64 engine requests stopped after six iterations (rtol below reach):
+    the returned iterate's increment u - u0 against the oracle's Algorithm 1
+    with the same operator, point by point, and the reported true residual
+    against the oracle's.  1024x1024 runs the layer kernel's two-segment rows."""
+    print(f"engine vs oracle N={N}", flush=True)
+    its = 6
+    k, f, u0 = _system(1000 + N, N, dev)
+    kn, fn, un = (a.cpu().numpy() for a in (k, f, u0))
+    w = oracle.unpack_weights(synth.init_weights(17, C, M), C, M)
+    kt = torch.from_numpy(kn)
+    ref = oracle.fcg(kn, fn, un, lambda r: oracle.no_apply(w, kt, r), m_max=5, max_iter=its, tol=1e-300)
+    eng = fc.Engine(model, op="fp64", m_max=5, check_every=4, max_slots=4, budget_bytes=3 << 30)
+    u = u0.clone()
+    res, _ = _run_rtol(eng, [(k, f, u)], [0], 1e-300, its)
+    eng.close()
+    assert res[0]["iters"] == its and res[0]["status"] == fc.SYS_NOT_CONVERGED
+    du_g = u.cpu().numpy() - un
+    du_o = ref.u.numpy() - un
+    mx = np.max(np.abs(du_g - du_o)) / np.max(np.abs(du_o))
+    tr = abs(res[0]["true_rel_res"] - ref.true_rel_res) / ref.true_rel_res
+    print(f"  increment max diff {mx:.2e}, true residual diff {tr:.2e}", flush=True)
+    assert mx < 1e-9
+    assert tr < 1e-9
+
+
+def test_engine_bf16_converged_requests_by_oracle_residual(dev, model):
+    """Converged BF16 requests of several grid sizes: the oracle's stencil
+    gives ||f - A u|| / ||f - A u0|| <= 1e-6 (up to rounding) on the returned
+    iterate, equal to the reported true residual."""
+    sizes = [32, 64, 96, 128]
+    systems = [_system(1100 + i, N, dev) for i, N in enumerate(sizes)]
+    eng = fc.Engine(model, op="bf16", m_max=5, check_every=4, max_slots=8, budget_bytes=1 << 29)
+    us = [s_[2].clone() for s_ in systems]
+    res, _ = _run(eng, [(s_[0], s_[1], us[i]) for i, s_ in enumerate(systems)], [0, 0, 1, 2])
+    eng.close()
+    n_ok = 0
+    for i, (k, f, u0) in enumerate(systems):
+        kn, fn, un = (a.cpu().numpy() for a in (k, f, u0))
+        r0 = np.linalg.norm(fn - oracle.stencil_apply(kn, un).numpy())
+        true = np.linalg.norm(fn - oracle.stencil_apply(kn, us[i].cpu().numpy()).numpy()) / r0
+        print(f"  N={sizes[i]} status {res[i]['status']} iters {res[i]['iters']} true {true:.3e}", flush=True)
+        assert abs(res[i]["true_rel_res"] - true) <= 1e-8 * true
+        if res[i]["status"] == fc.SYS_OK:
+            n_ok += 1
+            assert true <= 1.5e-6
+    assert n_ok >= 2

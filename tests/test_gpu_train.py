@@ -192,6 +192,41 @@ def test_autograd_function(dev):
     model.close()
 
 
+def test_autograd_function_interleaved_weights(dev):
+    """Two forwards with different weights on one model, then the first one's
+    backward: its gradient is the oracle's for the first weights (the model is
+    reloaded when its weights changed after the forward); a train step in
+    between invalidates the cached blob too."""
+    N, B, C, M, L = 16, 2, 16, 3, 2
+    k, r, _ = _data(N, B, 810)
+    blob_a = synth.init_weights(42, C, M, L)
+    blob_b = synth.init_weights(43, C, M, L)
+    model = fc.Model(blob_a, C, M, L)
+    kd, rd = [torch.from_numpy(a).to(dev) for a in (k, r)]
+    wa = torch.from_numpy(blob_a).to(dev).requires_grad_(True)
+    wb = torch.from_numpy(blob_b).to(dev).requires_grad_(True)
+    ya = fc.OperatorFunction.apply(wa, model, kd, rd, "fp64")
+    yb = fc.OperatorFunction.apply(wb, model, kd, rd, "fp64")
+    (ya * ya).sum().backward()
+    kt, rt = torch.from_numpy(k), torch.from_numpy(r)
+    _, ga = _oracle_grad(blob_a, C, M, L, lambda ww: torch.sum(oracle.no_apply(ww, kt, rt) ** 2))
+    rel = np.linalg.norm(wa.grad.cpu().numpy() - ga) / np.linalg.norm(ga)
+    print(f"  interleaved backward rel {rel:.2e}", flush=True)
+    assert rel < 1e-11
+    (yb * yb).sum().backward()
+    _, gb = _oracle_grad(blob_b, C, M, L, lambda ww: torch.sum(oracle.no_apply(ww, kt, rt) ** 2))
+    assert np.linalg.norm(wb.grad.cpu().numpy() - gb) / np.linalg.norm(gb) < 1e-11
+    # a train step changes the device weights: the same blob must be reloaded
+    opt = fc.Optim(model, lr=1e-2)
+    e = torch.randn_like(rd)
+    fc.train_step(model, opt, kd, rd, e, op="fp64")
+    opt.close()
+    y2 = fc.OperatorFunction.apply(wa.detach(), model, kd, rd, "fp64")
+    ref = oracle.no_apply(oracle.unpack_weights(blob_a, C, M, L), kt, rt).numpy()
+    assert np.max(np.abs(y2.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+    model.close()
+
+
 def test_krylov_samples_match_oracle(dev):
     """GPU conjugate-gradient samples (r_i, u* - u_i) against the oracle's CG
     with u* from a sparse direct solve.  CG amplifies rounding differences
