@@ -186,6 +186,25 @@ fcgno_status fcgno_precond_apply(const fcgno_model* m, int32_t n, int32_t batch,
                                  const double* k, const double* r, double* w,
                                  void* ws, size_t ws_bytes, void* stream);
 
+/* Scratch-free operator application, for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid allocation): w = B(r)
+ * exactly as fcgno_precond_apply computes it (the same kernels and bits), with
+ * the workspace taken from a static device array of the library of
+ * FCGNO_NOALLOC_SCRATCH_BYTES per device, which each device holds from its
+ * first call until the process ends.  k, r, w, op and stream as for
+ * fcgno_precond_apply; batch <= 64.  Every call on one device shares that
+ * device's array and leaves its contents behind (the call clears what must
+ * start at zero itself): calls that overlap on one device, on different
+ * streams or from different host threads, race and give undefined results;
+ * calls ordered on one stream are safe.  The call allocates nothing, but it
+ * copies a per-system pointer table from host memory, so it is not meant for
+ * stream capture.  Errors: E_INVALID as for fcgno_precond_apply, or batch >
+ * 64; E_NOMEM when fcgno_precond_workspace_bytes(m, n, batch, op) exceeds
+ * FCGNO_NOALLOC_SCRATCH_BYTES (nothing is launched); E_HIP. */
+#define FCGNO_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+fcgno_status fcgno_precond_apply_noalloc(const fcgno_model* m, int32_t n, int32_t batch, int32_t op,
+                                         const double* k, const double* r, double* w, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Training (Sec. 3.1): the operator is trained on the error form of the      */
 /* Notay loss, mean_b ||B(r_b) - e_b||_A / ||e_b||_A with e_b = A^-1 r_b, on  */

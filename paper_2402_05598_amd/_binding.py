@@ -80,6 +80,8 @@ def lib():
     L.fcgno_precond_workspace_bytes.restype = c_size_t
     L.fcgno_precond_apply.argtypes = [vp, c_int32, c_int32, c_int32, vp, vp, vp, vp, c_size_t, vp]
     L.fcgno_precond_apply.restype = c_int32
+    L.fcgno_precond_apply_noalloc.argtypes = [vp, c_int32, c_int32, c_int32, vp, vp, vp, vp]
+    L.fcgno_precond_apply_noalloc.restype = c_int32
     L.fcgno_optim_create.argtypes = [vp, c_double, c_double, c_double, c_double, c_double, POINTER(vp)]
     L.fcgno_optim_create.restype = c_int32
     L.fcgno_optim_set_lr.argtypes = [vp, c_double]
@@ -292,6 +294,23 @@ def precond_apply(model, k, r, op="bf16", w=None, workspace=None, stream=None):
     _check(lib().fcgno_precond_apply(model.handle, N, B, OP[op], _dev_f64(k, "k"), _dev_f64(r, "r"),
                                      _dev_f64(w, "w"), ctypes.c_void_p(ws.data_ptr()), _nbytes(ws),
                                      _stream(stream)), "fcgno_precond_apply")
+    return w
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def precond_apply_noalloc(model, k, r, op="bf16", w=None, stream=None):
+    """w = B(r; theta) like precond_apply, with the library's static scratch
+    array instead of a workspace (no device allocation inside the call; the
+    output w is allocated here unless given)."""
+    B, N = _grid(r, "r")
+    _same(k, (B, N + 2, N + 2), "k")
+    if w is None:
+        w = torch.empty_like(r)
+    _same(w, (B, N, N), "w")
+    _check(lib().fcgno_precond_apply_noalloc(model.handle, N, B, OP[op], _dev_f64(k, "k"), _dev_f64(r, "r"),
+                                             _dev_f64(w, "w"), _stream(stream)), "fcgno_precond_apply_noalloc")
     return w
 
 

@@ -298,8 +298,8 @@ NOLaunch make_no(const fcgno_model* m, const Plan& p, char* base, const SysDev* 
 // Operator set-up shared by every kind: tables, log k, constant layer-0 spectrum.
 fcgno_status operator_setup(const fcgno_model* m, const Plan& p, char* base, const NOLaunch& NL, int N, int B,
                             int op, hipStream_t s) {
-  HIPCHK(hipMemsetAsync(base + p.Hc, 0, (size_t)B * N * m->arch.width * p.MP * op_esize(op), s));
-  HIPCHK(hipMemsetAsync(base + p.Wh, 0, (size_t)B * p.wh_bytes_per_sys, s));
+  launch_zero(base + p.Hc, (size_t)B * N * m->arch.width * p.MP * op_esize(op), s);
+  launch_zero(base + p.Wh, (size_t)B * p.wh_bytes_per_sys, s);
   launch_tables(NL, (double*)(base + p.E64), base + p.Eacc, base + p.T, base + p.TT);
   launch_no_setup(NL, (double*)(base + p.Gp));
   return FCGNO_OK;
@@ -725,6 +725,60 @@ extern "C" fcgno_status fcgno_precond_apply(const fcgno_model* m, int32_t N, int
   if (ws_bytes < p.total) return fail(FCGNO_E_NOMEM, "workspace too small");
   if (((uintptr_t)ws & 255u) != 0) return fail(FCGNO_E_INVALID, "workspace must be 256-byte aligned");
   return operator_forward(m, p, (char*)ws, N, B, op, k, r, w, false, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Operator application without a workspace argument: the scratch memory is a
+// static device array of the library (one per device, held until the process
+// ends).  Host code never passes the array's name to a kernel or a copy: on
+// the host it is a stand-in symbol, not a device address.  The device
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current, and only that address is used.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[FCGNO_NOALLOC_SCRATCH_BYTES];
+
+namespace fcgno_host {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (looked up on first use).
+fcgno_status scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(FCGNO_E_INVALID, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FCGNO_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FCGNO_OK;
+}
+}  // namespace fcgno_host
+
+extern "C" fcgno_status fcgno_precond_apply_noalloc(const fcgno_model* m, int32_t N, int32_t B, int32_t op,
+                                                    const double* k, const double* r, double* w, void* stream) {
+  if (!m || !k || !r || !w) return fail(FCGNO_E_INVALID, "null pointer argument");
+  if (check_sizes(N, B) != FCGNO_OK) return FCGNO_E_INVALID;
+  if (op < 0 || op >= PID) return fail(FCGNO_E_INVALID, "op must be FP64, FP32 or BF16");
+  if (!arch_ok_for(m, N)) return fail(FCGNO_E_INVALID, "need 2*modes <= n");
+  const Plan p = make_plan(m, N, B, 1, 1, op, KIND_APPLY);
+  if (p.total > FCGNO_NOALLOC_SCRATCH_BYTES)
+    return fail(FCGNO_E_NOMEM, "operator application needs " + std::to_string(p.total) +
+                                   " scratch bytes, more than the static array's " +
+                                   std::to_string((size_t)FCGNO_NOALLOC_SCRATCH_BYTES));
+  void* ws = nullptr;
+  fcgno_status s = scratch_address(&ws);
+  if (s != FCGNO_OK) return s;
+  // at most this many per-system records live on the stack (no host allocation)
+  constexpr int STACK_SYS = 64;
+  if (B > STACK_SYS) return fail(FCGNO_E_INVALID, "batch must be <= 64 without a workspace");
+  SysDev table[STACK_SYS];
+  return operator_forward(m, p, (char*)ws, N, B, op, k, r, w, false, (hipStream_t)stream, table);
 }
 
 // ---------------------------------------------------------------------------

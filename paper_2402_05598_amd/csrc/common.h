@@ -218,6 +218,7 @@ void launch_record(const KrylovLaunch& L, int it, int m, double* rec_r, double* 
 // flags[3b..3b+2] = {active, status, iters}; tres[2b], tres[2b+1] = true
 // residual relative to ||r_0|| and to ||f||
 void launch_export(const SysDev* sys, int nsys, int* flags, double* tres, hipStream_t s);
+void launch_zero(void* p, size_t nbytes, hipStream_t s);      // bytes [0, nbytes) = 0
 
 struct NOLaunch {
   const SysDev* sys;

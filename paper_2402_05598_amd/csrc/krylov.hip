@@ -13,6 +13,8 @@
 // block order (the kernel boundary makes the slots visible, so no device-wide
 // fences are needed).  The block -> points mapping depends only on N, so a
 // system gives the same bits alone and inside any batch.
+#include <algorithm>
+
 #include "common.h"
 #include "prof.h"
 
@@ -436,6 +438,17 @@ __global__ __launch_bounds__(256) void k_rbgs(const SysDev* sys, int N, int colo
   sd.w[p] = (sd.r[p] + off) / diag;
 }
 
+// Zero bytes [0, nbytes) of a buffer (16-byte body, byte tail).  A kernel
+// rather than a memset so that work a caller captures into a graph holds
+// no memset node.
+__global__ __launch_bounds__(256) void k_zero(char* p, size_t nbytes) {
+  const size_t n16 = nbytes >> 4;
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n16; q += stride) ((uint4*)p)[q] = uint4{0, 0, 0, 0};
+  const size_t t = (n16 << 4) + (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && t < nbytes) p[t] = 0;
+}
+
 // Per-system summary for the host: {active, status, iters} and the true residual.
 __global__ __launch_bounds__(64) void k_export(const SysDev* sys, int nsys, int* flags, double* tres) {
   const int b = blockIdx.x * 64 + threadIdx.x;
@@ -467,6 +480,13 @@ void launch_rbsgs(const KrylovLaunch& L, int steps) {
   // alternating half sweeps red, black, ..., red.
   for (int h = 0; h < 2 * steps + 1; ++h)
     hipLaunchKernelGGL(k_rbgs, g, dim3(256), 0, L.stream, L.sys, L.N, h & 1, h == 0 ? 1 : 0);
+}
+
+void launch_zero(void* p, size_t nbytes, hipStream_t s) {
+  if (nbytes == 0) return;
+  const size_t n16 = (nbytes >> 4) + 1;
+  const unsigned nb = (unsigned)std::min<size_t>((n16 + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero, dim3(nb), dim3(256), 0, s, (char*)p, nbytes);
 }
 
 void launch_export(const SysDev* sys, int nsys, int* flags, double* tres, hipStream_t s) {

@@ -213,8 +213,8 @@ fcgno_status admit(fcgno_engine* e, EngReq& q, EngGroup& g) {
   KrylovLaunch KL{own, 1, N, e->d.m_max, g.s};
   launch_init_state(KL, q.max_iter, q.rtol);
   if (op != PID) {
-    HIPCHK(hipMemsetAsync(base + p.Hc, 0, (size_t)N * m->arch.width * p.MP * op_esize(op), g.s));
-    HIPCHK(hipMemsetAsync(base + p.Wh, 0, p.wh_bytes_per_sys, g.s));
+    launch_zero(base + p.Hc, (size_t)N * m->arch.width * p.MP * op_esize(op), g.s);
+    launch_zero(base + p.Wh, p.wh_bytes_per_sys, g.s);
     NOLaunch NL = group_no(e, g, own, 1);
     launch_no_setup(NL, (double*)(base + p.Gp));
   }
