@@ -77,6 +77,9 @@ def parse():
                    help="also time the main operator with the batch split over this many streams "
                         "(reported under comparison; kept out of the default run, whose kernel "
                         "statistics the roofline quotes)")
+    p.add_argument("--main-only", action="store_true",
+                   help="only the timed solves and their kernel figures (for profiler runs): no batched, "
+                        "single-solve, training, serving or CPU legs")
     p.add_argument("--log", default=None, help="progress log file (default: stderr)")
     return p.parse_args()
 
@@ -429,6 +432,55 @@ def training_throughput(fc, torch, dev, C, M, L, steps, logf, N=64, B=256, m_ite
     return out
 
 
+def krylov_bytes_per_point(i, m_max=5):
+    """Algorithmic HBM bytes per grid point of the three Krylov kernels at
+    iteration i (Algorithm 1, window m_i): (w, s_k) reads w and the m_i
+    s-vectors; the direction kernel reads w, the m_i p-vectors, r and k and
+    writes p_i and s_i; the update reads u, p_i, r, s_i and writes u and r."""
+    mi = min(i, max(1, i % (m_max + 1)))
+    return {"wdots": 8 * (mi + 1) if mi > 0 else 0, "dir": 8 * (mi + 5), "update": 48}
+
+
+def all_active_kernels(fc, torch, model, kd, fd, u0d, op, C, M, L, S, logf, iters=24):
+    """Per-kernel averages over a solve of the whole batch stopped after
+    ``iters`` iterations, before any system can reach the tolerance, so every
+    launch carries every system (events around each kernel family)."""
+    B, N = fd.shape[0], fd.shape[-1]
+    kinds = ["layer", "layer_feat", "layer_proj", "spectral", "rowdft", "wdots", "dir", "update"]
+    fc.profile_reset()
+    fc.profile_enable(True, kinds)
+    o = fc.solve(model, kd, fd, u0d.clone(), op=op, m_max=5, max_iter=iters, rtol=1e-300, hist=False)
+    torch.cuda.synchronize()
+    fc.profile_enable(False)
+    if not all(int(x) == iters for x in o["iters"]):
+        log(f"all-active solve: iteration counts {o['iters']}", logf)
+    out = {"iterations": iters, "systems": B}
+    tot = {"wdots": 0, "dir": 0, "update": 0}
+    for i in range(iters):
+        for kname, v in krylov_bytes_per_point(i).items():
+            tot[kname] += v * N * N * B
+    esize = {"bf16": 2, "fp32": 4, "fp64": 8}[op]
+    lb = layer_bytes_per_launch(N, B, C, M, esize, 8 if op == "fp64" else 4, S)
+    it_us = 0.0
+    for name in kinds:
+        n_, ms_ = fc.profile_read(name)
+        avg = ms_ / max(n_, 1) * 1e3
+        it_us += ms_ * 1e3 / iters
+        d = {"launches": n_, "avg_us": round(avg, 2)}
+        if name in tot:
+            gbs = tot[name] / max(ms_ * 1e-3, 1e-30) / 1e9
+            d.update({"GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                      "bytes_per_launch": round(tot[name] / max(n_, 1))})
+        if name == "layer":
+            gbs = lb / (avg * 1e-6) / 1e9
+            d.update({"GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": lb})
+        out[name] = d
+    out["sum_of_kernel_us_per_iteration"] = round(it_us, 1)
+    log(f"all-active ({iters} iterations x {B} systems): " +
+        ", ".join(f"{k} {v['avg_us']} us" for k, v in out.items() if isinstance(v, dict)), logf)
+    return out
+
+
 def time_solves(fc, torch, model, kd, fd, u0d, op, steps, warmup, args, prof_kernels=None, streams=0):
     B = fd.shape[0]
     N = fd.shape[-1]
@@ -758,22 +810,20 @@ def main():
         n_, ms_ = fc.profile_read(name)
         per_kernel[name] = {"launches": n_, "avg_us": round(ms_ / max(n_, 1) * 1e3, 2)}
     per_kernel["note"] = "one untimed solve of the batch with events around every kernel family"
-    # Krylov kernels against HBM: algorithmic bytes per point of iteration i
-    # with window m_i (Algorithm 1) -- (w, s_k): 8(m_i + 1); direction and
-    # stencil: 8(m_i + 4); updates: 48 -- summed over every system's iterations
+    # Krylov kernels against HBM: algorithmic bytes per point of each
+    # iteration (krylov_bytes_per_point) summed over every system's iterations
     kry_bytes = {"wdots": 0, "dir": 0, "update": 0}
     for itb in ob["iters"]:
         for i in range(int(itb)):
-            mi = min(i, max(1, i % 6))
-            kry_bytes["wdots"] += 8 * (mi + 1)
-            kry_bytes["dir"] += 8 * (mi + 4)
-            kry_bytes["update"] += 48
+            for kname, v in krylov_bytes_per_point(i).items():
+                kry_bytes[kname] += v
     krylov = {}
     for name, bpp in kry_bytes.items():
         n_, avg = per_kernel[name]["launches"], per_kernel[name]["avg_us"]
         gbs = bpp * N * N / max(n_ * avg * 1e-6, 1e-30) / 1e9
         krylov[name] = {"GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
     per_kernel["krylov_hbm"] = krylov
+    per_kernel["all_active"] = all_active_kernels(fc, torch, model, kd, fd, u0d, main_op, C, M, L, S, logf)
     # the operator against the matrix cores: algorithmic flops of an inner
     # layer per point, y-synthesis 2(2M)C + bypass 2C^2 + next y-analysis 2(2M)C
     flops_pt = 8 * M * C + 2 * C * C
@@ -816,8 +866,11 @@ def main():
             d["iters_diff_vs_fp64_op"] = (Rr["iters"][-B:] - ref["iters"][-B:]).tolist()
         comparison[op] = d
 
-    batch_cfg = batched(fc, torch, dev, model, C, M, L, logf)
-    cfg0 = config0(fc, torch, dev, logf)
+    if args.main_only:
+        args.train_bench_steps = args.serve_requests = 0
+        args.no_cpu_baseline = True
+    batch_cfg = None if args.main_only else batched(fc, torch, dev, model, C, M, L, logf)
+    cfg0 = None if args.main_only else config0(fc, torch, dev, logf)
     train_tp = None
     if args.train_bench_steps > 0:
         train_tp = training_throughput(fc, torch, dev, C, M, L, args.train_bench_steps, logf)

@@ -152,7 +152,7 @@ extern "C" void fcgno_model_destroy(fcgno_model* m) {
 namespace fcgno_host {
 
 size_t part_blocks(int N) {
-  const size_t flat = ((size_t)N * N + FLAT_PTS - 1) / FLAT_PTS;
+  const size_t flat = ((size_t)N * N + UPD_PTS - 1) / UPD_PTS;   // UPD_PTS <= FLAT_PTS
   const size_t tile = (size_t)((N + TILE_I - 1) / TILE_I) * ((N + TILE_J - 1) / TILE_J);
   return std::max(flat, tile);
 }

@@ -10,6 +10,7 @@ namespace fcgno {
 constexpr int MAXW = 32;        // largest truncation window m_max
 constexpr int NQ = MAXW + 4;    // partial-sum slots per block
 constexpr int FLAT_PTS = 2048;  // points per workgroup in the flat Krylov kernels
+constexpr int UPD_PTS = 512;    // points per workgroup of the update kernel (two per thread)
 constexpr int TILE_I = 16;      // stencil tile rows (x1)
 constexpr int TILE_J = 64;      // stencil tile columns (x2, contiguous)
 constexpr int TPW = 32;         // 16-point column tiles per wave in the layer kernel

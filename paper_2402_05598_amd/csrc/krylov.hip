@@ -23,6 +23,7 @@ namespace fcgno {
 constexpr int PPT = FLAT_PTS / 256;   // points per thread in the flat kernels
 
 __device__ __forceinline__ int flat_blocks(int n) { return (n + FLAT_PTS - 1) / FLAT_PTS; }
+__device__ __forceinline__ int upd_blocks(int n) { return (n + UPD_PTS - 1) / UPD_PTS; }
 __device__ __forceinline__ int tile_blocks(int N) {
   return ((N + TILE_I - 1) / TILE_I) * ((N + TILE_J - 1) / TILE_J);
 }
@@ -135,7 +136,6 @@ __global__ __launch_bounds__(256) void k_rnorm(const SysDev* sys, int N) {
 
 // Window dot products (w_i, s_k), in passes of up to 8 window vectors.
 __global__ __launch_bounds__(256) void k_wdots(const SysDev* sys, int N) {
-  __shared__ double lds[4];
   const SysDev sd = sys[blockIdx.y];
   const GLOBAL SysState* st = sd.st;
   if (!st->active) return;
@@ -151,6 +151,7 @@ __global__ __launch_bounds__(256) void k_wdots(const SysDev* sys, int N) {
     const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
     wv[e] = p < n ? w[p] : 0.0;
   }
+  __shared__ double red[8][4];
   for (int q0 = 0; q0 < m; q0 += 8) {
     const int nq = min(8, m - q0);
     double acc[8];
@@ -166,13 +167,22 @@ __global__ __launch_bounds__(256) void k_wdots(const SysDev* sys, int N) {
         }
       }
     }
+    // all window sums through LDS at once: wave sums, then lane q of the
+    // first wave adds the four waves' values in a fixed order
+    const int wv_ = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       if (q < nq) {
-        const double v = block_sum(acc[q], lds);
-        if (threadIdx.x == 0) sd.part[(size_t)blockIdx.x * NQ + q0 + q] = v;
+        const double v = wave_sum(acc[q]);
+        if ((threadIdx.x & 63) == 0) red[q][wv_] = v;
       }
     }
+    __syncthreads();
+    if (threadIdx.x < nq) {
+      const int q = threadIdx.x;
+      sd.part[(size_t)blockIdx.x * NQ + q0 + q] = (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
+    }
+    __syncthreads();
   }
 }
 
@@ -181,7 +191,6 @@ __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
   constexpr int HW = TILE_J + 2, HN = (TILE_I + 2) * (TILE_J + 2);
   constexpr int HR = (HN + 255) / 256;
   constexpr int IR = TILE_I * TILE_J / 256;
-  __shared__ double lds[4];
   __shared__ double pl[HN];
   __shared__ double cf[MAXW];
   const SysDev sd = sys[blockIdx.y];
@@ -238,16 +247,26 @@ __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
       ps += pc * s;
     }
   }
-  pr = block_sum(pr, lds);
-  ps = block_sum(ps, lds);
-  if (threadIdx.x == 0) {
-    sd.part[(size_t)blockIdx.x * NQ + 0] = pr;
-    sd.part[(size_t)blockIdx.x * NQ + 1] = ps;
+  // both sums through LDS at once (wave sums, then a fixed-order add)
+  __shared__ double red[2][4];
+  pr = wave_sum(pr);
+  ps = wave_sum(ps);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = pr;
+    red[1][threadIdx.x >> 6] = ps;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int q = threadIdx.x;
+    sd.part[(size_t)blockIdx.x * NQ + q] = (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
   }
 }
 
-// u += alpha p_i, r -= alpha s_i, partial ||r_{i+1}||^2.
+// u += alpha p_i, r -= alpha s_i, partial ||r_{i+1}||^2.  Two points per
+// thread: measured the fastest streaming shape for four reads and two writes
+// per point (more blocks in flight beat more loads per thread here).
 __global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
+  constexpr int UPT = UPD_PTS / 256;
   __shared__ double lds[4];
   const SysDev sd = sys[blockIdx.y];
   const GLOBAL SysState* st = sd.st;
@@ -259,10 +278,10 @@ __global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
   const double* __restrict__ Si = sd.S + (size_t)(i % ring) * n;
   double* __restrict__ u = sd.u;
   double* __restrict__ r = sd.r;
-  double uv[PPT], pv[PPT], rv[PPT], sv[PPT];
+  double uv[UPT], pv[UPT], rv[UPT], sv[UPT];
 #pragma unroll
-  for (int e = 0; e < PPT; ++e) {
-    const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
+  for (int e = 0; e < UPT; ++e) {
+    const int p = blockIdx.x * UPD_PTS + e * 256 + threadIdx.x;
     if (p < n) {
       uv[e] = u[p];
       pv[e] = Pi[p];
@@ -272,8 +291,8 @@ __global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
   }
   double acc = 0.0;
 #pragma unroll
-  for (int e = 0; e < PPT; ++e) {
-    const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
+  for (int e = 0; e < UPT; ++e) {
+    const int p = blockIdx.x * UPD_PTS + e * 256 + threadIdx.x;
     if (p < n) {
       const double rn = rv[e] - alpha * sv[e];
       u[p] = uv[e] + alpha * pv[e];
@@ -298,7 +317,7 @@ __global__ __launch_bounds__(256) void k_fin(const SysDev* sys, int N, int mode)
   const SysDev sd = sys[blockIdx.x];
   GLOBAL SysState* st = sd.st;
   if (mode != 4 && mode != 5 && !st->active) return;
-  const int nb = (mode == 1) ? tile_blocks(N) : flat_blocks(N * N);
+  const int nb = (mode == 1) ? tile_blocks(N) : (mode == 2 ? upd_blocks(N * N) : flat_blocks(N * N));
   auto fsum = [&](int q) {
     double v = 0.0;
     for (int b = threadIdx.x; b < nb; b += 256) v += sd.part[(size_t)b * NQ + q];
@@ -535,7 +554,8 @@ void launch_dir(const KrylovLaunch& L) {
 void launch_update(const KrylovLaunch& L) {
   {
     ProfScope ps(PK_UPDATE, L.stream);
-    hipLaunchKernelGGL(k_update, dim3(flat_nb(L.N), L.nsys), dim3(256), 0, L.stream, L.sys, L.N);
+    hipLaunchKernelGGL(k_update, dim3((L.N * L.N + UPD_PTS - 1) / UPD_PTS, L.nsys), dim3(256), 0, L.stream, L.sys,
+                       L.N);
   }
   fin(L, 2);
 }

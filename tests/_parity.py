@@ -47,17 +47,21 @@ def iteration_tolerance(ref_iters, shadow_iters):
     return max(2.0, 1.5 * (max(allits) - min(allits)))
 
 
-# Operator parity bounds per precision, from the measured errors against the
-# oracle (FP64 ~1e-16, FP32 ~3e-8, BF16 1.5e-4..8e-4 in the relative 2-norm):
-# about ten times those.  Each system is checked in the relative 2-norm and
-# point by point, the largest absolute difference against the largest value,
-# so that one bad tile or a wrong ragged-edge row cannot hide in the norm.
-NORM_TOL = {"fp64": 1e-13, "fp32": 3e-7, "bf16": 3e-3}
-MAX_TOL = {"fp64": 1e-13, "fp32": 1e-6, "bf16": 5e-3}
+# Operator parity bounds per precision.  FP64: about ten times the measured
+# ~1e-16 error against the oracle.  FP32: 16 unit roundoffs of float32
+# (u = 6e-8), 1e-6 in the norm and 3e-6 point by point; the measured errors
+# are 3e-8 (Fourier basis) to 3e-7 (sine basis, whose twiddles carry more
+# float32 rounding).  BF16: about ten times the measured 1.5e-4..8e-4.  Each
+# system is checked in the relative 2-norm and point by point, the largest
+# absolute difference against the largest value, so that one bad tile or a
+# wrong ragged-edge row cannot hide in the norm.
+NORM_TOL = {"fp64": 1e-13, "fp32": 1e-6, "bf16": 3e-3}
+MAX_TOL = {"fp64": 1e-13, "fp32": 3e-6, "bf16": 5e-3}
 
 
-def assert_operator_close(got, ref, op, label=""):
-    """got, ref: numpy [N][N] (one system).  Prints and asserts both measures."""
+def assert_operator_close(got, ref, op, label="", scale=1.0):
+    """got, ref: numpy [N][N] (one system).  Prints and asserts both measures;
+    ``scale`` widens both bounds for a case whose weights amplify rounding."""
     got = np.asarray(got)
     ref = np.asarray(ref)
     assert got.shape == ref.shape, (got.shape, ref.shape)
@@ -67,5 +71,5 @@ def assert_operator_close(got, ref, op, label=""):
     # worst row, to name a bad tile or edge
     row = int(np.argmax(np.max(np.abs(got - ref), axis=1)))
     print(f"  {label} {op}: rel2 {rel:.2e} max {mx:.2e} (worst row {row})", flush=True)
-    assert rel < NORM_TOL[op], (label, op, "rel2", rel)
-    assert mx < MAX_TOL[op], (label, op, "max", mx, row)
+    assert rel < scale * NORM_TOL[op], (label, op, "rel2", rel)
+    assert mx < scale * MAX_TOL[op], (label, op, "max", mx, row)
