@@ -216,6 +216,14 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
     p.Eacc = cv.take((size_t)tw_period(m->arch.basis, N) * 2 * asz);
     p.T = cv.take((size_t)NP * MP * esz);
     p.TT = cv.take((size_t)MP * NP * esz);
+    if (op == PBF) {
+      // matrix-core x transforms: split-bfloat16 twiddle operands and the
+      // synthesis operand of each system (see the bfloat16 spectral kernels)
+      p.FA = cv.take((size_t)2 * 32 * 2 * NP * 2);
+      p.SA = cv.take((size_t)2 * NP * 64 * 2);
+      p.wt_bytes_per_sys = (size_t)2 * C * M * 64 * 2;
+      p.WT = cv.take((size_t)B * p.wt_bytes_per_sys);
+    }
     if (kind == KIND_TRAIN) {
       const size_t vs = (size_t)M * C * 2 * M * 2;
       p.z = cv.take((size_t)L * B * n * C * esz);
@@ -261,6 +269,7 @@ void fill_no(const fcgno_model* m, const Plan& p, char* base, int N, int B, int 
     h[b].Vc = (decltype(h[b].Vc))(base + p.Vc + (size_t)b * C * 2 * M * M * 2 * asz);
     h[b].Wh = (decltype(h[b].Wh))(base + p.Wh + (size_t)b * p.wh_bytes_per_sys);
     h[b].Vp = (decltype(h[b].Vp))(base + p.Vp + (size_t)b * p.vp_bytes_per_sys);
+    h[b].WT = p.wt_bytes_per_sys ? (decltype(h[b].WT))(base + p.WT + (size_t)b * p.wt_bytes_per_sys) : nullptr;
   }
 }
 
@@ -281,6 +290,8 @@ NOLaunch make_no(const fcgno_model* m, const Plan& p, char* base, const SysDev* 
   L.tab.Eacc = base + p.Eacc;
   L.tab.T = base + p.T;
   L.tab.TT = base + p.TT;
+  L.tab.FA = op == PBF ? base + p.FA : nullptr;
+  L.tab.SA = op == PBF ? base + p.SA : nullptr;
   L.Wfrag = m->Wfrag[op].data();
   L.bias = m->bias[op].data();
   L.Rmix = m->Rmix[op].data();
@@ -300,7 +311,8 @@ fcgno_status operator_setup(const fcgno_model* m, const Plan& p, char* base, con
                             int op, hipStream_t s) {
   launch_zero(base + p.Hc, (size_t)B * N * m->arch.width * p.MP * op_esize(op), s);
   launch_zero(base + p.Wh, (size_t)B * p.wh_bytes_per_sys, s);
-  launch_tables(NL, (double*)(base + p.E64), base + p.Eacc, base + p.T, base + p.TT);
+  launch_tables(NL, (double*)(base + p.E64), base + p.Eacc, base + p.T, base + p.TT,
+                op == PBF ? base + p.FA : nullptr, op == PBF ? base + p.SA : nullptr);
   launch_no_setup(NL, (double*)(base + p.Gp));
   return FCGNO_OK;
 }

@@ -81,6 +81,8 @@ struct SysDev {
   GLOBAL void* Wh;          // [M][C][MP] complex, accumulate precision: mixed spectrum of the current layer (zero past 2M)
   GLOBAL void* Vp;          // [M][XS][C][2M] complex, accumulate precision: per-chunk forward spectra
   GLOBAL double* tmp;       // [N^2] second iterate of the Jacobi sweeps
+  GLOBAL void* WT;          // bfloat16 operator: mixed spectrum as the synthesis operand,
+                            // [2 (hi, lo)][C*M][64] bfloat16 (see k_xfm_bf)
 };
 
 // Per-N tables shared by the systems of one launch.
@@ -108,6 +110,10 @@ struct Tables {
   const void* T;      // [N][MP] op precision: Fourier T[y][2q] = cos(2 pi q y/N), T[y][2q+1] = sin(...);
                       // sine T[y][2q] = sin(pi (q+1)(y+1)/(N+1)), T[y][2q+1] = 0
   const void* TT;     // [MP][N] transpose of T
+  // bfloat16 operator only: the x-direction transforms as matrix-core
+  // operands, each value split into a bfloat16 pair hi + lo
+  const void* FA;     // [2][32][2 NP] forward: FA[h][a][2x] = cos, FA[h][a][2x+1] = -sin
+  const void* SA;     // [2][NP][64]   synthesis: SA[h][x][2a] = cos, SA[h][x][2a+1] = -sin
 };
 
 __device__ __forceinline__ int window_size(int i, int m_max) {
@@ -261,7 +267,9 @@ struct SpecArgs {
   int basis;         // B_FOURIER or B_SINE (set from NOLaunch::basis)
 };
 
-void launch_tables(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT);
+// FA, SA: bfloat16 operator only (nullptr otherwise)
+void launch_tables(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT, void* FA = nullptr,
+                   void* SA = nullptr);
 // single stages of the spectral part (used by the backward pass)
 void launch_spec_fwd(const NOLaunch& L, const SpecArgs& a);
 void launch_spec_inv(const NOLaunch& L, const SpecArgs& a);

@@ -603,6 +603,336 @@ __global__ __launch_bounds__(512) void k_spec_inv(SpecArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// bfloat16 operator: the x-direction transforms on the matrix cores
+// (16x16x32 bfloat16 products with float32 accumulation).  Every operand
+// value v travels as a bfloat16 pair hi = bf16(v), lo = bf16(v - hi), and a
+// product is accumulated as hi*hi + hi*lo + lo*hi (the dropped lo*lo term is
+// below 2^-16 of it), so the spectra keep close to float32 accuracy while the
+// contraction runs at the bfloat16 rate.
+//
+// Interleaving real and imaginary parts along the contraction index k makes
+// the complex sums real products:
+//   forward, k = (x, t):   V~r[a][c] = sum_k Ar[a][k] G[k][c], V~i likewise
+//       with Ai, where G[(x,0)][c] = Gc[x][c], G[(x,1)][c] = Gs[x][c],
+//       Ar[a][(x,0)] = cos, Ar[a][(x,1)] = -sin and Ai = (-sin, -cos) per
+//       pair (V^ = sum_x (cos - i sin)(Gc - i Gs) with the angle of mode a at
+//       row x);
+//   synthesis, k = (a, t): Hr[x][j] = sum_k Sr[x][k] W[k][j], Hi likewise
+//       with Si, where W[(a,0)][j] = Re W^[a][j], W[(a,1)][j] = Im W^[a][j],
+//       Sr[x][(a,0)] = cos, Sr[x][(a,1)] = -sin and Si = (sin, cos) per pair
+//       (H = sum_a W^ (cos + i sin)).
+// Ai and Si pairs are Ar and Sr pairs swapped with one sign flipped, so
+// only Ar (table FA) and Sr (table SA) are stored; both hold the same values
+// in two layouts.  For the sine basis the "cos" slot holds the sine mode and
+// the "sin" slot zero, as in the other tables.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef short short8_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ float4_t mfma_bf32(bf16x8_t a, bf16x8_t b, float4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// hi*hi + hi*lo + lo*hi
+__device__ __forceinline__ float4_t mfma_bf3(bf16x8_t ah, bf16x8_t al, bf16x8_t bh, bf16x8_t bl, float4_t c) {
+  c = mfma_bf32(ah, bh, c);
+  c = mfma_bf32(ah, bl, c);
+  return mfma_bf32(al, bh, c);
+}
+// pairs (e0, e1) -> (e1, -e0): forward Ai from Ar
+__device__ __forceinline__ bf16x8_t pairs_fwd(bf16x8_t v) {
+  const short8_t s = __builtin_bit_cast(short8_t, v);
+  short8_t o;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    o[2 * p] = s[2 * p + 1];
+    o[2 * p + 1] = (short)(s[2 * p] ^ (short)0x8000);
+  }
+  return __builtin_bit_cast(bf16x8_t, o);
+}
+// pairs (e0, e1) -> (-e1, e0): synthesis Si from Sr
+__device__ __forceinline__ bf16x8_t pairs_inv(bf16x8_t v) {
+  const short8_t s = __builtin_bit_cast(short8_t, v);
+  short8_t o;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    o[2 * p] = (short)(s[2 * p + 1] ^ (short)0x8000);
+    o[2 * p + 1] = s[2 * p];
+  }
+  return __builtin_bit_cast(bf16x8_t, o);
+}
+__device__ __forceinline__ void split_bf(float v, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)v;
+  lo = (__bf16)(v - (float)hi);
+}
+
+// FA[h][a][2x + t] and SA[h][x][2a + t] (h: 0 hi, 1 lo; a < 32, x < NP):
+// t = 0 cos, t = 1 -sin of mode a at row x for a < 2M and x < N, else 0.
+__global__ __launch_bounds__(256) void k_tables_bfx(int N, int M, int basis, const double* E64, __bf16* FA,
+                                                   __bf16* SA) {
+  const int NP = round16(N);
+  const int q = blockIdx.x * 256 + threadIdx.x;   // (x, a, t), a fastest after t
+  if (q >= NP * 64) return;
+  const int x = q >> 6, a = (q >> 1) & 31, t = q & 1;
+  double v = 0.0;
+  if (a < 2 * M && x < N) {
+    const unsigned idx = tw_index(basis, N, M, a, x);
+    v = t == 0 ? E64[2 * idx] : -E64[2 * idx + 1];
+  }
+  const __bf16 hi = (__bf16)(float)v;
+  const __bf16 lo = (__bf16)(float)(v - (double)(float)hi);
+  FA[(size_t)a * 2 * NP + 2 * x + t] = hi;
+  FA[(size_t)32 * 2 * NP + (size_t)a * 2 * NP + 2 * x + t] = lo;
+  SA[(size_t)x * 64 + 2 * a + t] = hi;
+  SA[(size_t)NP * 64 + (size_t)x * 64 + 2 * a + t] = lo;
+}
+
+// Forward transform along x and mode mixing of one layer, one block per
+// (ky, system), bfloat16 operator:
+//   V^[c][a] = sum_x (Gc - i Gs)[x][c] e^{-2 pi i kx_a x / N}   (matrix cores)
+//   W^[o][a] = sum_c V^[c][a] R[c][o][a][ky]                      (vector ALU)
+// written as the synthesis operand WT[h][o*M + ky][2a + t] (zero for a >= 2M).
+// Eight waves split the 16-row steps of x; each issues the loads of up to
+// four steps before their products, and the eight partial tiles are added
+// in a fixed order through LDS.  Layer 0 transforms the single channel of
+// r's row partials instead and adds the per-solve constant part.
+constexpr int XFM_THREADS = 512;
+template <int C>
+__global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16* FA) {
+  constexpr int NW = XFM_THREADS / 64, NCT = C / 16, SPW = 4;
+  __shared__ float red[NW][8][256];   // [wave][(kt, re/im, ct)][element]
+  __shared__ float Vr_[C][33], Vi_[C][33];
+  const int ky = blockIdx.x;
+  const SysDev sd = a.sys[blockIdx.y];
+  if (!sd.st->active) return;
+  const int N = a.N, M = a.M, twoM = 2 * M, MP = round16(twoM), NP = round16(N);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, n16 = lane & 15, g = lane >> 4;
+  const int nkt = (twoM + 15) >> 4;
+  if (a.layer0) {
+    // S[a] = sum_x (Gr - i Gi)[x] e^{-i theta}, float32, 16 row parts per mode
+    __shared__ float pr_[16][33], pi_[16][33];
+    const float* E = (const float*)a.Eacc;
+    const int ka = t & 31, part = t >> 5;
+    float sr = 0.f, si = 0.f;
+    if (ka < twoM) {
+      for (int x = part; x < N; x += XFM_THREADS / 32) {
+        const float gr = (float)sd.Gr[(size_t)x * MP + 2 * ky], gi = -(float)sd.Gr[(size_t)x * MP + 2 * ky + 1];
+        const unsigned idx = tw_index(a.basis, N, M, ka, x);
+        const float er = E[2 * idx], ei = -E[2 * idx + 1];
+        sr += gr * er - gi * ei;
+        si += gr * ei + gi * er;
+      }
+    }
+    pr_[part][ka] = sr;
+    pi_[part][ka] = si;
+    __syncthreads();
+    const double snorm = sd.st->snorm;
+    const double inv_s = snorm > 0.0 ? 1.0 / snorm : 0.0;
+    for (int q = t; q < C * twoM; q += XFM_THREADS) {
+      const int c = q / twoM, kx = q - c * twoM;
+      float vr = 0.f, vi = 0.f;
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        vr += pr_[p][kx];
+        vi += pi_[p][kx];
+      }
+      const double wl = (double)((const float*)a.WL0)[c] * inv_s;
+      const float* vc = (const float*)sd.Vc + 2 * ((size_t)(c * twoM + kx) * M + ky);
+      Vr_[c][kx] = (float)(wl * (double)vr) + vc[0];
+      Vi_[c][kx] = (float)(wl * (double)vi) + vc[1];
+    }
+  } else {
+    const float* Gp = (const float*)sd.Gp;
+    const __bf16* FAl = FA + (size_t)32 * 2 * NP;
+    float4_t acc[2][2][NCT];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+      for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[kt][ri][ct] = float4_t{0.f, 0.f, 0.f, 0.f};
+    const int nsteps = NP >> 4;
+    for (int s0 = w; s0 < nsteps; s0 += NW * SPW) {
+      // loads of up to SPW steps (s0, s0 + NW, ...) before any product
+      float gv[SPW][NCT][8];
+      bf16x8_t ah[SPW][2], al[SPW][2];
+#pragma unroll
+      for (int u = 0; u < SPW; ++u) {
+        const int st = s0 + u * NW;
+        const bool live = st < nsteps;
+        const int x0 = st * 16 + 4 * g;
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          const int c = ct * 16 + n16;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float gc = 0.f, gs = 0.f;
+            const int x = x0 + r;
+            if (live && x < N) {
+              for (int sg = 0; sg < a.S; ++sg) {
+                const float* row = Gp + (size_t)((x * a.S + sg) * MP + 2 * ky) * C;
+                gc += row[c];
+                gs += row[C + c];
+              }
+            }
+            gv[u][ct][2 * r] = gc;
+            gv[u][ct][2 * r + 1] = gs;
+          }
+        }
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+          const size_t o = (size_t)(kt * 16 + n16) * 2 * NP + 2 * (size_t)x0;
+          if (live && kt < nkt) {
+            ah[u][kt] = *(const bf16x8_t*)(FA + o);
+            al[u][kt] = *(const bf16x8_t*)(FAl + o);
+          } else {
+            ah[u][kt] = bf16x8_t{};
+            al[u][kt] = bf16x8_t{};
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SPW; ++u) {
+        if (s0 + u * NW >= nsteps) break;
+        bf16x8_t bh[NCT], bl[NCT];
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            __bf16 h, l;
+            split_bf(gv[u][ct][e], h, l);
+            bh[ct][e] = h;
+            bl[ct][e] = l;
+          }
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+          if (kt >= nkt) break;
+          const bf16x8_t aih = pairs_fwd(ah[u][kt]), ail = pairs_fwd(al[u][kt]);
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) {
+            acc[kt][0][ct] = mfma_bf3(ah[u][kt], al[u][kt], bh[ct], bl[ct], acc[kt][0][ct]);
+            acc[kt][1][ct] = mfma_bf3(aih, ail, bh[ct], bl[ct], acc[kt][1][ct]);
+          }
+        }
+      }
+    }
+    // partial tiles -> LDS; element index i * 64 + lane (row 4 g + i, column n16)
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+      for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) red[w][(kt * 2 + ri) * NCT + ct][i * 64 + lane] = acc[kt][ri][ct][i];
+    __syncthreads();
+    // fixed-order sum over the waves, then V^[c][a]
+    for (int q = t; q < nkt * 2 * NCT * 256; q += XFM_THREADS) {
+      const int tile = q >> 8, el = q & 255;
+      float v = 0.f;
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) v += red[ww][tile][el];
+      const int ct = tile % NCT, ri = (tile / NCT) & 1, kt = tile / (2 * NCT);
+      const int i = el >> 6, ln = el & 63;
+      const int kx = kt * 16 + 4 * (ln >> 4) + i, c = ct * 16 + (ln & 15);
+      if (kx < twoM) {
+        if (ri == 0) Vr_[c][kx] = v;
+        else Vi_[c][kx] = v;
+      }
+    }
+  }
+  __syncthreads();
+  // mixing: output (a, o) per thread, all C weight pairs of it loaded together
+  const float* Rk0 = (const float*)a.R + (size_t)ky * twoM * C * C * 2;
+  __bf16* WTh = (__bf16*)sd.WT;
+  __bf16* WTl = WTh + (size_t)C * M * 64;
+  for (int q = t; q < 32 * C; q += XFM_THREADS) {
+    const int kx = q / C, o = q - kx * C;
+    float sr = 0.f, si = 0.f;
+    if (kx < twoM) {
+      const float* Rk = Rk0 + (size_t)kx * C * C * 2;
+      float rr[C], rim[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        rr[c] = Rk[2 * (c * C + o)];
+        rim[c] = Rk[2 * (c * C + o) + 1];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        sr += Vr_[c][kx] * rr[c] - Vi_[c][kx] * rim[c];
+        si += Vr_[c][kx] * rim[c] + Vi_[c][kx] * rr[c];
+      }
+    }
+    __bf16 h, l;
+    const size_t e = (size_t)(o * M + ky) * 64 + 2 * kx;
+    split_bf(sr, h, l);
+    WTh[e] = h;
+    WTl[e] = l;
+    split_bf(si, h, l);
+    WTh[e + 1] = h;
+    WTl[e + 1] = l;
+  }
+}
+
+// x-direction synthesis, bfloat16 operator, one block per 16 rows:
+// H[x][j] = sum_a W^[a][j] e^{+2 pi i kx_a x / N}, j = o*M + ky, on the matrix
+// cores, written as the complete rows Hc[x][o][.] = (s Re H, -s Im H) with the
+// inverse normalisation s of the basis (Fourier N^-2 g_ky, g_0 = 1 else 2;
+// sine (2/(N+1))^2), zero past 2M.  Waves take the 16-column tiles of j in
+// turn; the rows pass through LDS for contiguous stores.
+template <int C, int MP>
+__global__ __launch_bounds__(256) void k_xinv_bf(SpecArgs a, const __bf16* SA) {
+  __shared__ __attribute__((aligned(16))) uint16_t tile[16 * C * MP];
+  const SysDev sd = a.sys[blockIdx.y];
+  if (!sd.st->active) return;
+  const int N = a.N, M = a.M, NP = round16(N);
+  const int x0 = blockIdx.x * 16;
+  const int nx = min(16, N - x0);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, n16 = lane & 15, g = lane >> 4;
+  for (int q = t; q < 16 * C * MP / 8; q += 256) ((uint4*)tile)[q] = uint4{0u, 0u, 0u, 0u};
+  // A operands of this lane's row x0 + n16, both contraction steps (k = 32 ks + 8 g ..)
+  const __bf16* SAl = SA + (size_t)NP * 64;
+  bf16x8_t sh[2], sl[2], ih[2], il[2];
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) {
+    const size_t o = (size_t)(x0 + n16) * 64 + 32 * ks + 8 * g;
+    sh[ks] = *(const bf16x8_t*)(SA + o);
+    sl[ks] = *(const bf16x8_t*)(SAl + o);
+    ih[ks] = pairs_inv(sh[ks]);
+    il[ks] = pairs_inv(sl[ks]);
+  }
+  __syncthreads();
+  const __bf16* WTh = (const __bf16*)sd.WT;
+  const __bf16* WTl = WTh + (size_t)C * M * 64;
+  const float scale0 = a.basis == B_SINE ? (float)(4.0 / ((double)(N + 1) * (double)(N + 1)))
+                                         : (float)(1.0 / ((double)N * (double)N));
+  const int ntile = C * M / 16;
+  for (int jt = w; jt < ntile; jt += 4) {
+    const int j = jt * 16 + n16;
+    float4_t hr = {0.f, 0.f, 0.f, 0.f}, hi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const size_t o = (size_t)j * 64 + 32 * ks + 8 * g;
+      const bf16x8_t bh = *(const bf16x8_t*)(WTh + o), bl = *(const bf16x8_t*)(WTl + o);
+      hr = mfma_bf3(sh[ks], sl[ks], bh, bl, hr);
+      hi = mfma_bf3(ih[ks], il[ks], bh, bl, hi);
+    }
+    // lane holds rows 4 g + i of column j
+    const int o = j / M, ky = j - o * M;
+    const float sc = a.basis == B_SINE ? scale0 : (ky == 0 ? scale0 : 2.f * scale0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int xl = 4 * g + i;
+      tile[(xl * C + o) * MP + 2 * ky] = f2bf(sc * hr[i]);
+      tile[(xl * C + o) * MP + 2 * ky + 1] = f2bf(-sc * hi[i]);
+    }
+  }
+  __syncthreads();
+  const int nchunk = nx * C * MP / 8;   // 16-byte chunks of the block's rows
+  uint4* dst = (uint4*)((uint16_t*)sd.Hc + (size_t)x0 * C * MP);
+  for (int q = t; q < nchunk; q += 256) dst[q] = ((const uint4*)tile)[q];
+}
+
+// ---------------------------------------------------------------------------
 // Layer kernel: synthesis along y + bypass + bias + GELU, then either the
 // next layer's y-direction analysis or the projection.
 // ---------------------------------------------------------------------------
@@ -923,10 +1253,16 @@ static void tables_p(const NOLaunch& L, double* E64, void* Eacc, void* T, void* 
                      T, TT);
 }
 
-void launch_tables(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT) {
+void launch_tables(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT, void* FA, void* SA) {
   if (L.prec == P64) tables_p<P64>(L, E64, Eacc, T, TT);
   else if (L.prec == P32) tables_p<P32>(L, E64, Eacc, T, TT);
-  else tables_p<PBF>(L, E64, Eacc, T, TT);
+  else {
+    tables_p<PBF>(L, E64, Eacc, T, TT);
+    // after E64 on the same stream
+    const int n = round16(L.N) * 64;
+    hipLaunchKernelGGL(k_tables_bfx, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.N, L.M, L.basis, E64,
+                       (__bf16*)FA, (__bf16*)SA);
+  }
 }
 
 template <int PREC>
@@ -996,7 +1332,18 @@ static void apply_pc(const NOLaunch& L) {
     const int XS = (L.N + SX - 1) / SX;
     SpecArgs sa{L.sys, L.N, L.S, L.M, l == 0 ? 1 : 0, XS, L.nsys, L.tab.Eacc, L.tab.E64, L.Rmix[l], L.WL0,
                 L.vsave ? (char*)L.vsave + L.vs_layer * l * L.acc_bytes : nullptr, L.vs_sys, 0, L.basis};
-    {
+    if constexpr (PREC == PBF) {
+      // matrix-core x transforms (inference only: training runs FP32/FP64)
+      ProfScope ps(PK_SPECTRAL, L.stream);
+      hipLaunchKernelGGL((k_xfm_bf<C>), dim3(L.M, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
+                         (const __bf16*)L.tab.FA);
+      if (L.MP == 16)
+        hipLaunchKernelGGL((k_xinv_bf<C, 16>), dim3(round16(L.N) / 16, L.nsys), dim3(256), 0, L.stream, sa,
+                           (const __bf16*)L.tab.SA);
+      else
+        hipLaunchKernelGGL((k_xinv_bf<C, 32>), dim3(round16(L.N) / 16, L.nsys), dim3(256), 0, L.stream, sa,
+                           (const __bf16*)L.tab.SA);
+    } else {
       ProfScope ps(PK_SPECTRAL, L.stream);
       constexpr int SR = SynthRows<PREC>::SR;
       hipLaunchKernelGGL((k_spec_fwd<PREC, C>), dim3(L.M, XS, L.nsys), dim3(256), 0, L.stream, sa);
