@@ -191,7 +191,7 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
     const int C = m->arch.width, M = m->arch.modes, L = m->arch.layers;
     const int MP = round16(2 * M), NP = round16(N);
     const int nyt = NP / 16;
-    const int S = (nyt + TPW - 1) / TPW;
+    const int S = seg_count(N);
     const int esz = op_esize(op), asz = acc_esize(op);
     if (kind == KIND_TRAIN) {
       bwd_geometry(N, op, p.Sb, p.nbs);
@@ -284,6 +284,7 @@ NOLaunch make_no(const fcgno_model* m, const Plan& p, char* base, const SysDev* 
   L.MP = p.MP;
   L.L = m->arch.layers;
   L.S = p.S_seg;
+  L.spw = SPW_HIGH;
   L.prec = op;
   L.basis = m->arch.basis;
   L.tab.E64 = (const double*)(base + p.E64);
@@ -487,9 +488,13 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
   bool split = G > 1;
   NOLaunch NL1 = NL;
   int it = 0;
+  int active = B;   // active systems at the last poll
   while (it < d->max_iter) {
     const int end = std::min(d->max_iter, it + K);
     if (!split) {
+      // few systems left: one row segment per wave (more, shorter waves keep
+      // more of the chip busy); the same bits either way
+      if (is_no(op)) NL1.spw = active <= LOW_ACTIVE ? 1 : SPW_HIGH;
       for (int i = it; i < end; ++i) {
         if (is_no(op)) launch_no_apply(NL1);
         else if (op == PJAC) launch_jacobi(KL, d->precond_steps);
@@ -506,6 +511,7 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
       int total = 0;
       for (int g = 0; g < G; ++g) total += std::max(hn[g], 0);
       if (total <= 0) break;
+      active = total;
       continue;
     }
     for (int g = 0; g < G; ++g) {

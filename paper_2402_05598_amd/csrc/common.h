@@ -13,7 +13,11 @@ constexpr int FLAT_PTS = 2048;  // points per workgroup in the flat Krylov kerne
 constexpr int UPD_PTS = 512;    // points per workgroup of the update kernel (two per thread)
 constexpr int TILE_I = 16;      // stencil tile rows (x1)
 constexpr int TILE_J = 64;      // stencil tile columns (x2, contiguous)
-constexpr int TPW = 32;         // 16-point column tiles per wave in the layer kernel
+constexpr int TPW = 16;         // 16-point column tiles per row segment in the layer kernel
+constexpr int SPW_HIGH = 2;     // row segments per wave while many systems are active
+constexpr int LOW_ACTIVE = 4;   // active systems at or below which a wave takes one segment
+// row segments of the layer kernel for N points per row
+__host__ __device__ inline int seg_count(int N) { return ((N + 15) / 16 + TPW - 1) / TPW; }
 
 enum Prec { P64 = 0, P32 = 1, PBF = 2, PID = 3, PJAC = 4, PSGS = 5 };
 
@@ -231,7 +235,8 @@ struct NOLaunch {
   const SysDev* sys;
   int nsys;
   int N, C, M, MP, L;   // MP = 2M rounded up to 16
-  int S;                // column segments per row in the layer kernel
+  int S;                // row segments (of TPW tiles) per row in the layer kernel
+  int spw;              // row segments per wave (1 or SPW_HIGH): the results do not depend on it
   int prec;             // P64, P32, PBF
   int basis;            // B_FOURIER or B_SINE
   Tables tab;

@@ -2,17 +2,18 @@
 //
 // Per iteration i and system b (after w_i = B(r_i) is available):
 //   k_wdots   partial (w_i, s_k) over the window k = i-m_i .. i-1
-//   k_fin(0)  c_k = (w_i, s_k) / (p_k, s_k)
-//   k_dir     p_i = w_i - sum_k c_k p_k (recomputed on a halo in LDS),
+//   k_dir     c_k = (w_i, s_k) / (p_k, s_k) (formed in every block),
+//             p_i = w_i - sum_k c_k p_k (recomputed on a halo in LDS),
 //             s_i = A p_i, partial (p_i, r_i), (p_i, s_i)
-//   k_fin(1)  alpha_i = (p_i, r_i)/(p_i, s_i), or breakdown
-//   k_update  u += alpha p_i, r -= alpha s_i, partial ||r_{i+1}||^2
+//   k_update  alpha_i = (p_i, r_i)/(p_i, s_i) or breakdown (every block),
+//             u += alpha p_i, r -= alpha s_i, partial ||r_{i+1}||^2
 //   k_fin(2)  ||r_{i+1}|| / ||r_0||, stopping test, i <- i+1
 // Reductions are two-level and deterministic: every block writes its partial
-// sums to a fixed slot and a one-block-per-system kernel sums the slots in
-// block order (the kernel boundary makes the slots visible, so no device-wide
-// fences are needed).  The block -> points mapping depends only on N, so a
-// system gives the same bits alone and inside any batch.
+// sums to a fixed slot, and either a one-block-per-system kernel or every
+// block of the consuming kernel sums the slots in block order (the kernel
+// boundary makes the slots visible, so no device-wide fences are needed).
+// The block -> points mapping depends only on N, so a system gives the same
+// bits alone and inside any batch.
 #include <algorithm>
 
 #include "common.h"
@@ -26,6 +27,14 @@ __device__ __forceinline__ int flat_blocks(int n) { return (n + FLAT_PTS - 1) / 
 __device__ __forceinline__ int upd_blocks(int n) { return (n + UPD_PTS - 1) / UPD_PTS; }
 __device__ __forceinline__ int tile_blocks(int N) {
   return ((N + TILE_I - 1) / TILE_I) * ((N + TILE_J - 1) / TILE_J);
+}
+// Partial-sum slots of a system: slot-major, [NQ][stride], so that one slot's
+// values from every block are contiguous (the kernels that sum them in every
+// block read whole lines).  stride = the most blocks of any partial writer
+// (the same count the host plans: max(n / UPD_PTS, tiles); FLAT_PTS >= UPD_PTS).
+__device__ __forceinline__ size_t pslot(int N, int q, int b) {
+  const int stride = max(upd_blocks(N * N), tile_blocks(N));
+  return (size_t)q * stride + b;
 }
 
 // 5-point operator at interior point (i, j) with neighbour values supplied.
@@ -110,9 +119,9 @@ __global__ __launch_bounds__(256) void k_residual(const SysDev* sys, int N, int 
     ff = block_sum(ff, lds);
   }
   if (threadIdx.x == 0) {
-    sd.part[(size_t)blockIdx.x * NQ + 0] = acc;
-    sd.part[(size_t)blockIdx.x * NQ + 1] = bad;
-    sd.part[(size_t)blockIdx.x * NQ + 2] = ff;
+    sd.part[pslot(N, 0, blockIdx.x)] = acc;
+    sd.part[pslot(N, 1, blockIdx.x)] = bad;
+    sd.part[pslot(N, 2, blockIdx.x)] = ff;
   }
 }
 
@@ -131,7 +140,46 @@ __global__ __launch_bounds__(256) void k_rnorm(const SysDev* sys, int N) {
     }
   }
   acc = block_sum(acc, lds);
-  if (threadIdx.x == 0) sd.part[(size_t)blockIdx.x * NQ] = acc;
+  if (threadIdx.x == 0) sd.part[pslot(N, 0, blockIdx.x)] = acc;
+}
+
+// Loads in these kernels are unconditional, at clamped indices, with the
+// values of out-of-range points masked afterwards: a load under a per-lane
+// condition becomes a branch, and the compiler then waits for each such load
+// before the next one instead of keeping them in flight together.
+
+// Partial-slot slots of the two folded reductions: the direction kernel's
+// (p_i, r_i), (p_i, s_i) and the update kernel's ||r_{i+1}||^2 go to slots
+// that no kernel reading the previous kernel's slots overwrites.
+constexpr int SL_PR = MAXW, SL_PS = MAXW + 1, SL_RR = MAXW + 2;
+
+// Sum of slot q over nb partial blocks in a fixed order (the same in every
+// block that forms it, so every block holds the same bits); all threads
+// return the sum.
+__device__ __forceinline__ double slot_sum(const GLOBAL double* part, int N, int nb, int q, double* lds) {
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) v += part[pslot(N, q, b)];
+  return block_sum(v, lds);
+}
+
+// Window sums over NV (a compile-time count) window vectors for this
+// thread's points.
+template <int NV>
+__device__ __forceinline__ void wdots_pass(const double* __restrict__ S, size_t n, int slot0, int ring,
+                                           const int (&pc)[PPT], const bool (&ok)[PPT], const double (&wv)[PPT],
+                                           double (&acc)[8]) {
+  double sv[NV][PPT];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double* __restrict__ Sv = S + (size_t)((slot0 + q) % ring) * n;
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) sv[q][e] = Sv[pc[e]];
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+#pragma unroll
+    for (int e = 0; e < PPT; ++e)
+      if (ok[e]) acc[q] += wv[e] * sv[q][e];
 }
 
 // Window dot products (w_i, s_k), in passes of up to 8 window vectors.
@@ -145,27 +193,36 @@ __global__ __launch_bounds__(256) void k_wdots(const SysDev* sys, int N) {
   const int n = N * N;
   const int ring = mm + 1;
   const double* __restrict__ w = sd.w;
+  int pc[PPT];
+  bool ok[PPT];
   double wv[PPT];
 #pragma unroll
   for (int e = 0; e < PPT; ++e) {
     const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
-    wv[e] = p < n ? w[p] : 0.0;
+    ok[e] = p < n;
+    pc[e] = ok[e] ? p : n - 1;
+  }
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) {
+    const double t = w[pc[e]];
+    wv[e] = ok[e] ? t : 0.0;
   }
   __shared__ double red[8][4];
   for (int q0 = 0; q0 < m; q0 += 8) {
     const int nq = min(8, m - q0);
     double acc[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      acc[q] = 0.0;
-      if (q < nq) {
-        const double* __restrict__ Sv = sd.S + (size_t)((i - m + q0 + q) % ring) * n;
-#pragma unroll
-        for (int e = 0; e < PPT; ++e) {
-          const int p = blockIdx.x * FLAT_PTS + e * 256 + threadIdx.x;
-          if (p < n) acc[q] += wv[e] * Sv[p];
-        }
-      }
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    const int slot0 = i - m + q0;
+    switch (nq) {
+      case 1: wdots_pass<1>(sd.S, n, slot0, ring, pc, ok, wv, acc); break;
+      case 2: wdots_pass<2>(sd.S, n, slot0, ring, pc, ok, wv, acc); break;
+      case 3: wdots_pass<3>(sd.S, n, slot0, ring, pc, ok, wv, acc); break;
+      case 4: wdots_pass<4>(sd.S, n, slot0, ring, pc, ok, wv, acc); break;
+      case 5: wdots_pass<5>(sd.S, n, slot0, ring, pc, ok, wv, acc); break;
+      case 6: wdots_pass<6>(sd.S, n, slot0, ring, pc, ok, wv, acc); break;
+      case 7: wdots_pass<7>(sd.S, n, slot0, ring, pc, ok, wv, acc); break;
+      default: wdots_pass<8>(sd.S, n, slot0, ring, pc, ok, wv, acc); break;
     }
     // all window sums through LDS at once: wave sums, then lane q of the
     // first wave adds the four waves' values in a fixed order
@@ -180,46 +237,108 @@ __global__ __launch_bounds__(256) void k_wdots(const SysDev* sys, int N) {
     __syncthreads();
     if (threadIdx.x < nq) {
       const int q = threadIdx.x;
-      sd.part[(size_t)blockIdx.x * NQ + q0 + q] = (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
+      sd.part[pslot(N, q0 + q, blockIdx.x)] = (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
     }
     __syncthreads();
   }
 }
 
-// p_i on the tile and a one-point halo, s_i = A p_i, partial (p_i, r_i), (p_i, s_i).
+constexpr int DIR_HW = TILE_J + 2, DIR_HN = (TILE_I + 2) * (TILE_J + 2);
+constexpr int DIR_HR = (DIR_HN + 255) / 256;   // halo slots per thread
+
+// Window vectors P_q at this thread's halo slots, NV of them at once (their
+// loads in flight together), then p -= sum_q c_q P_q.
+constexpr int DIR_PV = 4;   // window vectors per pass
+template <int NV>
+__device__ __forceinline__ void dir_load(const double* __restrict__ P, size_t n, int slot0, int ring,
+                                         const int (&hc)[DIR_HR], double (&pv)[DIR_PV][DIR_HR]) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double* __restrict__ Pq = P + (size_t)((slot0 + q) % ring) * n;
+#pragma unroll
+    for (int e = 0; e < DIR_HR; ++e) pv[q][e] = Pq[hc[e]];
+  }
+}
+template <int NV>
+__device__ __forceinline__ void dir_apply(const double (&pv)[DIR_PV][DIR_HR], const double* cf,
+                                          const bool (&hok)[DIR_HR], double (&hv)[DIR_HR]) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double c = cf[q];
+#pragma unroll
+    for (int e = 0; e < DIR_HR; ++e)
+      if (hok[e]) hv[e] -= c * pv[q][e];
+  }
+}
+__device__ __forceinline__ void dir_load_n(int nq, const double* __restrict__ P, size_t n, int slot0, int ring,
+                                           const int (&hc)[DIR_HR], double (&pv)[DIR_PV][DIR_HR]) {
+  switch (nq) {
+    case 1: dir_load<1>(P, n, slot0, ring, hc, pv); break;
+    case 2: dir_load<2>(P, n, slot0, ring, hc, pv); break;
+    case 3: dir_load<3>(P, n, slot0, ring, hc, pv); break;
+    default: dir_load<4>(P, n, slot0, ring, hc, pv); break;
+  }
+}
+__device__ __forceinline__ void dir_apply_n(int nq, const double (&pv)[DIR_PV][DIR_HR], const double* cf,
+                                            const bool (&hok)[DIR_HR], double (&hv)[DIR_HR]) {
+  switch (nq) {
+    case 1: dir_apply<1>(pv, cf, hok, hv); break;
+    case 2: dir_apply<2>(pv, cf, hok, hv); break;
+    case 3: dir_apply<3>(pv, cf, hok, hv); break;
+    default: dir_apply<4>(pv, cf, hok, hv); break;
+  }
+}
+
+// Window coefficients c_k = (w_i, s_k)/(p_k, s_k) from the window-sum
+// partials, then p_i on the tile and a one-point halo, s_i = A p_i, partial
+// (p_i, r_i), (p_i, s_i).  Every block forms the coefficients itself (the same
+// fixed-order sums) instead of a one-block pass between the two kernels.
 __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
-  constexpr int HW = TILE_J + 2, HN = (TILE_I + 2) * (TILE_J + 2);
-  constexpr int HR = (HN + 255) / 256;
+  constexpr int HW = DIR_HW, HN = DIR_HN, HR = DIR_HR;
   constexpr int IR = TILE_I * TILE_J / 256;
   __shared__ double pl[HN];
   __shared__ double cf[MAXW];
+  __shared__ double lds[4];
   const SysDev sd = sys[blockIdx.y];
-  const GLOBAL SysState* st = sd.st;
+  GLOBAL SysState* st = sd.st;
   if (!st->active) return;
-  const int i = st->i, ring = st->m_max + 1;
-  const int m = st->m;
+  const int i = st->i, mm = st->m_max, ring = mm + 1;
+  const int m = window_size(i, mm);
   const int n = N * N;
   const int tj = (N + TILE_J - 1) / TILE_J;
   const int bi = blockIdx.x / tj, bj = blockIdx.x - bi * tj;
   const int i0 = bi * TILE_I, j0 = bj * TILE_J;
-  if (threadIdx.x < m) cf[threadIdx.x] = st->coef[threadIdx.x];
-  __syncthreads();
-  int hp[HR];
+  int hc[HR];
+  bool hok[HR];
   double hv[HR];
 #pragma unroll
   for (int e = 0; e < HR; ++e) {
     const int t = threadIdx.x + 256 * e;
     const int a = t / HW, c = t - a * HW;
     const int gi = i0 - 1 + a, gj = j0 - 1 + c;
-    hp[e] = (t < HN && gi >= 0 && gi < N && gj >= 0 && gj < N) ? gi * N + gj : -1;
-    hv[e] = hp[e] >= 0 ? sd.w[hp[e]] : 0.0;
+    hok[e] = t < HN && gi >= 0 && gi < N && gj >= 0 && gj < N;
+    hc[e] = hok[e] ? gi * N + gj : 0;
   }
-  for (int q = 0; q < m; ++q) {
-    const double* __restrict__ Pq = sd.P + (size_t)((i - m + q) % ring) * n;
-    const double c = cf[q];
 #pragma unroll
-    for (int e = 0; e < HR; ++e)
-      if (hp[e] >= 0) hv[e] -= c * Pq[hp[e]];
+  for (int e = 0; e < HR; ++e) {
+    const double t = sd.w[hc[e]];
+    hv[e] = hok[e] ? t : 0.0;
+  }
+  // coefficients, then passes of at most DIR_PV window vectors (their loads
+  // in flight together; more would cost occupancy)
+  double pv[DIR_PV][DIR_HR];
+  const int nbw = flat_blocks(n);
+  for (int q = 0; q < m; ++q) {
+    const double d = slot_sum(sd.part, N, nbw, q, lds);
+    if (threadIdx.x == 0) cf[q] = d / st->ps_ring[(i - m + q) % ring];
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x < m) st->coef[threadIdx.x] = cf[threadIdx.x];
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->m = m;
+  for (int q0 = 0; q0 < m; q0 += DIR_PV) {
+    const int nq = min(DIR_PV, m - q0);
+    dir_load_n(nq, sd.P, n, i - m + q0, ring, hc, pv);
+    dir_apply_n(nq, pv, cf + q0, hok, hv);
   }
 #pragma unroll
   for (int e = 0; e < HR; ++e) {
@@ -229,21 +348,33 @@ __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
   __syncthreads();
   double* __restrict__ Pi = sd.P + (size_t)(i % ring) * n;
   double* __restrict__ Si = sd.S + (size_t)(i % ring) * n;
+  // interior points: all coefficient and residual loads first (clamped
+  // indices), then the stencil, the stores and the two sums
+  bool ok[IR];
+  int gic[IR], gjc[IR];
+  double rv[IR];
+#pragma unroll
+  for (int e = 0; e < IR; ++e) {
+    const int t = threadIdx.x + 256 * e;
+    const int a = t / TILE_J, c = t - a * TILE_J;
+    ok[e] = i0 + a < N && j0 + c < N;
+    gic[e] = ok[e] ? i0 + a : 0;
+    gjc[e] = ok[e] ? j0 + c : 0;
+    rv[e] = sd.r[gic[e] * N + gjc[e]];
+  }
   double pr = 0.0, ps = 0.0;
 #pragma unroll
   for (int e = 0; e < IR; ++e) {
     const int t = threadIdx.x + 256 * e;
     const int a = t / TILE_J, c = t - a * TILE_J;
-    const int gi = i0 + a, gj = j0 + c;
-    if (gi < N && gj < N) {
-      const int h = (a + 1) * HW + (c + 1);
-      const double pc = pl[h];
-      const double s = stencil_at(sd.k, N, gi, gj, pc, pl[h + HW], pl[h - HW], pl[h + 1], pl[h - 1]);
-      const int p = gi * N + gj;
-      const double rv = sd.r[p];
+    const int h = (a + 1) * HW + (c + 1);
+    const double pc = pl[h];
+    const double s = stencil_at(sd.k, N, gic[e], gjc[e], pc, pl[h + HW], pl[h - HW], pl[h + 1], pl[h - 1]);
+    if (ok[e]) {
+      const int p = gic[e] * N + gjc[e];
       Pi[p] = pc;
       Si[p] = s;
-      pr += pc * rv;
+      pr += pc * rv[e];
       ps += pc * s;
     }
   }
@@ -258,21 +389,25 @@ __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
   __syncthreads();
   if (threadIdx.x < 2) {
     const int q = threadIdx.x;
-    sd.part[(size_t)blockIdx.x * NQ + q] = (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
+    sd.part[pslot(N, q == 0 ? SL_PR : SL_PS, blockIdx.x)] = (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
   }
 }
 
 // u += alpha p_i, r -= alpha s_i, partial ||r_{i+1}||^2.  Two points per
 // thread: measured the fastest streaming shape for four reads and two writes
 // per point (more blocks in flight beat more loads per thread here).
+//
+// The step length alpha_i = (p_i, r_i)/(p_i, s_i) (or the breakdown test) is
+// formed in every block from the direction kernel's partials, the same fixed-
+// order sums, after this block's vector loads are in flight; block 0 records
+// it.  On breakdown no block updates and block 0 stops the system.
 __global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
   constexpr int UPT = UPD_PTS / 256;
   __shared__ double lds[4];
   const SysDev sd = sys[blockIdx.y];
-  const GLOBAL SysState* st = sd.st;
+  GLOBAL SysState* st = sd.st;
   if (!st->active) return;
   const int i = st->i, ring = st->m_max + 1;
-  const double alpha = st->alpha;
   const int n = N * N;
   const double* __restrict__ Pi = sd.P + (size_t)(i % ring) * n;
   const double* __restrict__ Si = sd.S + (size_t)(i % ring) * n;
@@ -289,6 +424,20 @@ __global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
       sv[e] = Si[p];
     }
   }
+  const int nbd = tile_blocks(N);
+  const double PR = slot_sum(sd.part, N, nbd, SL_PR, lds), PS = slot_sum(sd.part, N, nbd, SL_PS, lds);
+  if (!(isfinite(PS) && isfinite(PR)) || !(PS > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->alpha = 0.0;
+      deactivate(st, sd.n_active, S_BREAK, i);
+    }
+    return;
+  }
+  const double alpha = PR / PS;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->alpha = alpha;
+    st->ps_ring[i % ring] = PS;
+  }
   double acc = 0.0;
 #pragma unroll
   for (int e = 0; e < UPT; ++e) {
@@ -301,14 +450,14 @@ __global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
     }
   }
   acc = block_sum(acc, lds);
-  if (threadIdx.x == 0) sd.part[(size_t)blockIdx.x * NQ] = acc;
+  if (threadIdx.x == 0) sd.part[pslot(N, SL_RR, blockIdx.x)] = acc;
 }
 
 // One block per system: fixed-order sums of the partial slots and the scalar
 // steps of Algorithm 1 that follow them.
-//   mode 0: window coefficients c_k        (after k_wdots)
-//   mode 1: alpha_i or breakdown           (after k_dir)
 //   mode 2: rho_{i+1}, stopping test, i+1  (after k_update)
+// (the window coefficients and the step length are formed inside k_dir and
+// k_update)
 //   mode 3: ||r_0||, input status          (after k_residual mode 0)
 //   mode 4: true relative residual         (after k_residual mode 1)
 //   mode 5: operator input scale           (after k_rnorm)
@@ -317,33 +466,16 @@ __global__ __launch_bounds__(256) void k_fin(const SysDev* sys, int N, int mode)
   const SysDev sd = sys[blockIdx.x];
   GLOBAL SysState* st = sd.st;
   if (mode != 4 && mode != 5 && !st->active) return;
-  const int nb = (mode == 1) ? tile_blocks(N) : (mode == 2 ? upd_blocks(N * N) : flat_blocks(N * N));
+  const int nb = mode == 2 ? upd_blocks(N * N) : flat_blocks(N * N);
   auto fsum = [&](int q) {
     double v = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 256) v += sd.part[(size_t)b * NQ + q];
+    for (int b = threadIdx.x; b < nb; b += 256) v += sd.part[pslot(N, q, b)];
     return block_sum(v, lds);
   };
   const int i = st->i, ring = st->m_max + 1;
-  if (mode == 0) {
-    const int m = window_size(i, st->m_max);
-    for (int q = 0; q < m; ++q) {
-      const double d = fsum(q);
-      if (threadIdx.x == 0) st->coef[q] = d / st->ps_ring[(i - m + q) % ring];
-    }
-    if (threadIdx.x == 0) st->m = m;
-  } else if (mode == 1) {
-    const double PR = fsum(0), PS = fsum(1);
-    if (threadIdx.x == 0) {
-      if (!(isfinite(PS) && isfinite(PR)) || !(PS > 0.0)) {
-        st->alpha = 0.0;
-        deactivate(st, sd.n_active, S_BREAK, i);
-      } else {
-        st->alpha = PR / PS;
-        st->ps_ring[i % ring] = PS;
-      }
-    }
-  } else if (mode == 2) {
-    const double rr = fsum(0);
+  (void)ring;
+  if (mode == 2) {
+    const double rr = fsum(SL_RR);
     if (threadIdx.x == 0) {
       const double rho = sqrt(rr / st->rr0);
       st->rr = rr;
@@ -541,7 +673,6 @@ void launch_wdots(const KrylovLaunch& L) {
     ProfScope ps(PK_WDOTS, L.stream);
     hipLaunchKernelGGL(k_wdots, dim3(flat_nb(L.N), L.nsys), dim3(256), 0, L.stream, L.sys, L.N);
   }
-  fin(L, 0);
 }
 void launch_dir(const KrylovLaunch& L) {
   const int nb = ((L.N + TILE_I - 1) / TILE_I) * ((L.N + TILE_J - 1) / TILE_J);
@@ -549,7 +680,6 @@ void launch_dir(const KrylovLaunch& L) {
     ProfScope ps(PK_DIR, L.stream);
     hipLaunchKernelGGL(k_dir, dim3(nb, L.nsys), dim3(256), 0, L.stream, L.sys, L.N);
   }
-  fin(L, 1);
 }
 void launch_update(const KrylovLaunch& L) {
   {

@@ -687,106 +687,165 @@ __global__ __launch_bounds__(256) void k_tables_bfx(int N, int M, int basis, con
 }
 
 // Forward transform along x and mode mixing of one layer, one block per
-// (ky, system), bfloat16 operator:
+// (ky, group of 16 kept x-modes, system), bfloat16 operator:
 //   V^[c][a] = sum_x (Gc - i Gs)[x][c] e^{-2 pi i kx_a x / N}   (matrix cores)
 //   W^[o][a] = sum_c V^[c][a] R[c][o][a][ky]                      (vector ALU)
-// written as the synthesis operand WT[h][o*M + ky][2a + t] (zero for a >= 2M).
-// Eight waves split the 16-row steps of x; each issues the loads of up to
-// four steps before their products, and the eight partial tiles are added
+// The mixing of mode a needs V^ of that mode only, so the blocks of one
+// (ky, system) split the modes and need no exchange.  The mixed spectrum is
+// written as the synthesis operand WT[h][o*M + ky][2a + t] (zero for
+// a >= 2M).  Eight waves split the 16-row steps of x; each issues the loads
+// of its steps before their products, and the eight partial tiles are added
 // in a fixed order through LDS.  Layer 0 transforms the single channel of
 // r's row partials instead and adds the per-solve constant part.
+// SEG: the row-segment count a.S as a compile-time constant (1, 2 or 4, so
+// that the loads of every segment issue together), or 0 for any count.
 constexpr int XFM_THREADS = 512;
-template <int C>
+template <int C, int SEG>
 __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16* FA) {
-  constexpr int NW = XFM_THREADS / 64, NCT = C / 16, SPW = 4;
-  __shared__ float red[NW][8][256];   // [wave][(kt, re/im, ct)][element]
-  __shared__ float Vr_[C][33], Vi_[C][33];
-  const int ky = blockIdx.x;
-  const SysDev sd = a.sys[blockIdx.y];
+  constexpr int NW = XFM_THREADS / 64, NCT = C / 16, SPW = SEG == 4 ? 2 : 4;
+  constexpr int SEG0 = SEG > 0 ? SEG : 1;   // segments summed in the first pass
+  __shared__ float red[NW][4][256];   // [wave][(re/im, ct)][element]
+  __shared__ float Vr_[C][17], Vi_[C][17];
+  const int ky = blockIdx.x, kg = blockIdx.y;   // modes a = 16 kg .. 16 kg + 15
+  const SysDev sd = a.sys[blockIdx.z];
   if (!sd.st->active) return;
   const int N = a.N, M = a.M, twoM = 2 * M, MP = round16(twoM), NP = round16(N);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, n16 = lane & 15, g = lane >> 4;
   const int nkt = (twoM + 15) >> 4;
   if (a.layer0) {
-    // S[a] = sum_x (Gr - i Gi)[x] e^{-i theta}, float32, 16 row parts per mode
-    __shared__ float pr_[16][33], pi_[16][33];
+    // S[a] = sum_x (Gr - i Gi)[x] e^{-i theta}, float32, 32 row parts per mode
+    constexpr int XR = XFM_THREADS / 16, CHR = 8;
+    __shared__ float pr_[XR][17], pi_[XR][17];
     const float* E = (const float*)a.Eacc;
-    const int ka = t & 31, part = t >> 5;
+    const int kl = t & 15, ka = kg * 16 + kl, part = t >> 4;
     float sr = 0.f, si = 0.f;
     if (ka < twoM) {
-      for (int x = part; x < N; x += XFM_THREADS / 32) {
-        const float gr = (float)sd.Gr[(size_t)x * MP + 2 * ky], gi = -(float)sd.Gr[(size_t)x * MP + 2 * ky + 1];
-        const unsigned idx = tw_index(a.basis, N, M, ka, x);
-        const float er = E[2 * idx], ei = -E[2 * idx + 1];
-        sr += gr * er - gi * ei;
-        si += gr * ei + gi * er;
+      // chunks of eight rows per thread: every load of a chunk is issued
+      // before its sums (a runtime loop would wait on each load in turn)
+      for (int x0 = part; x0 < N; x0 += XR * CHR) {
+        double g0[CHR], g1[CHR];
+        float er[CHR], ei[CHR];
+#pragma unroll
+        for (int e = 0; e < CHR; ++e) {
+          // rows past N read row 0 (unconditional loads, no branches) and
+          // are zeroed below
+          const int x = x0 + e * XR;
+          const int xc = x < N ? x : 0;
+          g0[e] = sd.Gr[(size_t)xc * MP + 2 * ky];
+          g1[e] = sd.Gr[(size_t)xc * MP + 2 * ky + 1];
+          const unsigned idx = tw_index(a.basis, N, M, ka, xc);
+          er[e] = E[2 * idx];
+          ei[e] = -E[2 * idx + 1];
+        }
+#pragma unroll
+        for (int e = 0; e < CHR; ++e) {
+          const bool v = x0 + e * XR < N;
+          const float gr = v ? (float)g0[e] : 0.f, gi = v ? -(float)g1[e] : 0.f;
+          sr += gr * er[e] - gi * ei[e];
+          si += gr * ei[e] + gi * er[e];
+        }
       }
     }
-    pr_[part][ka] = sr;
-    pi_[part][ka] = si;
+    pr_[part][kl] = sr;
+    pi_[part][kl] = si;
     __syncthreads();
     const double snorm = sd.st->snorm;
     const double inv_s = snorm > 0.0 ? 1.0 / snorm : 0.0;
-    for (int q = t; q < C * twoM; q += XFM_THREADS) {
-      const int c = q / twoM, kx = q - c * twoM;
+    for (int q = t; q < C * 16; q += XFM_THREADS) {
+      const int c = q >> 4, k2 = q & 15, kx = kg * 16 + k2;
+      if (kx >= twoM) continue;
       float vr = 0.f, vi = 0.f;
 #pragma unroll
-      for (int p = 0; p < 16; ++p) {
-        vr += pr_[p][kx];
-        vi += pi_[p][kx];
+      for (int p = 0; p < XR; ++p) {
+        vr += pr_[p][k2];
+        vi += pi_[p][k2];
       }
       const double wl = (double)((const float*)a.WL0)[c] * inv_s;
       const float* vc = (const float*)sd.Vc + 2 * ((size_t)(c * twoM + kx) * M + ky);
-      Vr_[c][kx] = (float)(wl * (double)vr) + vc[0];
-      Vi_[c][kx] = (float)(wl * (double)vi) + vc[1];
+      Vr_[c][k2] = (float)(wl * (double)vr) + vc[0];
+      Vi_[c][k2] = (float)(wl * (double)vi) + vc[1];
     }
   } else {
     const float* Gp = (const float*)sd.Gp;
-    const __bf16* FAl = FA + (size_t)32 * 2 * NP;
-    float4_t acc[2][2][NCT];
+    const __bf16* FAh = FA + (size_t)(kg * 16 + n16) * 2 * NP;
+    const __bf16* FAl = FAh + (size_t)32 * 2 * NP;
+    float4_t acc[2][NCT];
 #pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
+    for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
-      for (int ri = 0; ri < 2; ++ri)
-#pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) acc[kt][ri][ct] = float4_t{0.f, 0.f, 0.f, 0.f};
+      for (int ct = 0; ct < NCT; ++ct) acc[ri][ct] = float4_t{0.f, 0.f, 0.f, 0.f};
     const int nsteps = NP >> 4;
     for (int s0 = w; s0 < nsteps; s0 += NW * SPW) {
-      // loads of up to SPW steps (s0, s0 + NW, ...) before any product
-      float gv[SPW][NCT][8];
-      bf16x8_t ah[SPW][2], al[SPW][2];
+      // loads of up to SPW steps (s0, s0 + NW, ...) before any product: the
+      // first SEG0 segments of every (step, channel, row, Gc/Gs); rows past
+      // N and dead steps read row 0 and are zeroed after
+      float raw[SPW][NCT][8][SEG0];
+      bf16x8_t ah[SPW], al[SPW];
 #pragma unroll
       for (int u = 0; u < SPW; ++u) {
         const int st = s0 + u * NW;
-        const bool live = st < nsteps;
-        const int x0 = st * 16 + 4 * g;
+        const int x0 = (st < nsteps ? st : 0) * 16 + 4 * g;
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) {
           const int c = ct * 16 + n16;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            float gc = 0.f, gs = 0.f;
-            const int x = x0 + r;
-            if (live && x < N) {
-              for (int sg = 0; sg < a.S; ++sg) {
-                const float* row = Gp + (size_t)((x * a.S + sg) * MP + 2 * ky) * C;
-                gc += row[c];
-                gs += row[C + c];
-              }
+            const int x = x0 + r < N ? x0 + r : 0;
+#pragma unroll
+            for (int sg = 0; sg < SEG0; ++sg) {
+              const float* row = Gp + (size_t)((x * a.S + sg) * MP + 2 * ky) * C;
+              raw[u][ct][2 * r][sg] = row[c];
+              raw[u][ct][2 * r + 1][sg] = row[C + c];
             }
-            gv[u][ct][2 * r] = gc;
-            gv[u][ct][2 * r + 1] = gs;
           }
         }
+        ah[u] = *(const bf16x8_t*)(FAh + 2 * (size_t)x0);
+        al[u] = *(const bf16x8_t*)(FAl + 2 * (size_t)x0);
+      }
+      // every load above completes here, before any sum or product (the
+      // compiler would otherwise issue each step's loads after the previous
+      // step's products, one round trip per step)
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt) {
-          const size_t o = (size_t)(kt * 16 + n16) * 2 * NP + 2 * (size_t)x0;
-          if (live && kt < nkt) {
-            ah[u][kt] = *(const bf16x8_t*)(FA + o);
-            al[u][kt] = *(const bf16x8_t*)(FAl + o);
-          } else {
-            ah[u][kt] = bf16x8_t{};
-            al[u][kt] = bf16x8_t{};
+      for (int u = 0; u < SPW; ++u) {
+        asm volatile("" : "+v"(ah[u]), "+v"(al[u]));
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+#pragma unroll
+            for (int sg = 0; sg < SEG0; ++sg) asm volatile("" : "+v"(raw[u][ct][e][sg]));
+      }
+      float gv[SPW][NCT][8];
+#pragma unroll
+      for (int u = 0; u < SPW; ++u) {
+        const int st = s0 + u * NW;
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            float v = 0.f;
+#pragma unroll
+            for (int sg = 0; sg < SEG0; ++sg) v += raw[u][ct][e][sg];
+            const bool ok = st < nsteps && st * 16 + 4 * g + (e >> 1) < N;
+            gv[u][ct][e] = ok ? v : 0.f;
+          }
+      }
+      for (int sg = SEG0; SEG == 0 && sg < a.S; ++sg) {
+#pragma unroll
+        for (int u = 0; u < SPW; ++u) {
+          const int st = s0 + u * NW;
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) {
+            const int c = ct * 16 + n16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int x = st * 16 + 4 * g + r;
+              const bool v = st < nsteps && x < N;
+              const float* row = Gp + (size_t)(((v ? x : 0) * a.S + sg) * MP + 2 * ky) * C;
+              const float gc = row[c], gs = row[C + c];
+              gv[u][ct][2 * r] += v ? gc : 0.f;
+              gv[u][ct][2 * r + 1] += v ? gs : 0.f;
+            }
           }
         }
       }
@@ -803,41 +862,33 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
             bh[ct][e] = h;
             bl[ct][e] = l;
           }
+        const bf16x8_t aih = pairs_fwd(ah[u]), ail = pairs_fwd(al[u]);
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt) {
-          if (kt >= nkt) break;
-          const bf16x8_t aih = pairs_fwd(ah[u][kt]), ail = pairs_fwd(al[u][kt]);
-#pragma unroll
-          for (int ct = 0; ct < NCT; ++ct) {
-            acc[kt][0][ct] = mfma_bf3(ah[u][kt], al[u][kt], bh[ct], bl[ct], acc[kt][0][ct]);
-            acc[kt][1][ct] = mfma_bf3(aih, ail, bh[ct], bl[ct], acc[kt][1][ct]);
-          }
+        for (int ct = 0; ct < NCT; ++ct) {
+          acc[0][ct] = mfma_bf3(ah[u], al[u], bh[ct], bl[ct], acc[0][ct]);
+          acc[1][ct] = mfma_bf3(aih, ail, bh[ct], bl[ct], acc[1][ct]);
         }
       }
     }
     // partial tiles -> LDS; element index i * 64 + lane (row 4 g + i, column n16)
 #pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
+    for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
-      for (int ri = 0; ri < 2; ++ri)
+      for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) red[w][(kt * 2 + ri) * NCT + ct][i * 64 + lane] = acc[kt][ri][ct][i];
+        for (int i = 0; i < 4; ++i) red[w][ri * NCT + ct][i * 64 + lane] = acc[ri][ct][i];
     __syncthreads();
-    // fixed-order sum over the waves, then V^[c][a]
-    for (int q = t; q < nkt * 2 * NCT * 256; q += XFM_THREADS) {
+    // fixed-order sum over the waves, then V^[c][a] of this block's modes
+    for (int q = t; q < 2 * NCT * 256; q += XFM_THREADS) {
       const int tile = q >> 8, el = q & 255;
       float v = 0.f;
 #pragma unroll
       for (int ww = 0; ww < NW; ++ww) v += red[ww][tile][el];
-      const int ct = tile % NCT, ri = (tile / NCT) & 1, kt = tile / (2 * NCT);
+      const int ct = tile % NCT, ri = tile / NCT;
       const int i = el >> 6, ln = el & 63;
-      const int kx = kt * 16 + 4 * (ln >> 4) + i, c = ct * 16 + (ln & 15);
-      if (kx < twoM) {
-        if (ri == 0) Vr_[c][kx] = v;
-        else Vi_[c][kx] = v;
-      }
+      const int k2 = 4 * (ln >> 4) + i, c = ct * 16 + (ln & 15);
+      if (ri == 0) Vr_[c][k2] = v;
+      else Vi_[c][k2] = v;
     }
   }
   __syncthreads();
@@ -845,8 +896,10 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
   const float* Rk0 = (const float*)a.R + (size_t)ky * twoM * C * C * 2;
   __bf16* WTh = (__bf16*)sd.WT;
   __bf16* WTl = WTh + (size_t)C * M * 64;
-  for (int q = t; q < 32 * C; q += XFM_THREADS) {
-    const int kx = q / C, o = q - kx * C;
+  // this block's 16 modes; the last group also clears the slots 16 nkt .. 31
+  const int kend = kg == nkt - 1 ? 32 : kg * 16 + 16;
+  for (int q = t; q < (kend - kg * 16) * C; q += XFM_THREADS) {
+    const int kx = kg * 16 + q / C, o = q % C, k2 = kx - kg * 16;
     float sr = 0.f, si = 0.f;
     if (kx < twoM) {
       const float* Rk = Rk0 + (size_t)kx * C * C * 2;
@@ -858,8 +911,8 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
       }
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        sr += Vr_[c][kx] * rr[c] - Vi_[c][kx] * rim[c];
-        si += Vr_[c][kx] * rim[c] + Vi_[c][kx] * rr[c];
+        sr += Vr_[c][k2] * rr[c] - Vi_[c][k2] * rim[c];
+        si += Vr_[c][k2] * rim[c] + Vi_[c][k2] * rr[c];
       }
     }
     __bf16 h, l;
@@ -873,21 +926,28 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
   }
 }
 
-// x-direction synthesis, bfloat16 operator, one block per 16 rows:
+// x-direction synthesis, bfloat16 operator, one block per (16 rows, half of
+// the output channels when the column tiles split evenly):
 // H[x][j] = sum_a W^[a][j] e^{+2 pi i kx_a x / N}, j = o*M + ky, on the matrix
-// cores, written as the complete rows Hc[x][o][.] = (s Re H, -s Im H) with the
-// inverse normalisation s of the basis (Fourier N^-2 g_ky, g_0 = 1 else 2;
-// sine (2/(N+1))^2), zero past 2M.  Waves take the 16-column tiles of j in
-// turn; the rows pass through LDS for contiguous stores.
+// cores, written as the rows Hc[x][o][.] = (s Re H, -s Im H) of the block's
+// channels with the inverse normalisation s of the basis (Fourier N^-2 g_ky,
+// g_0 = 1 else 2; sine (2/(N+1))^2), zero past 2M.  Column tile jt covers
+// j = 16 jt .. 16 jt + 15, so the first half of the tiles holds exactly the
+// channels o < C/2.  Waves take the block's tiles in turn; the rows pass
+// through LDS for contiguous stores.
 template <int C, int MP>
 __global__ __launch_bounds__(256) void k_xinv_bf(SpecArgs a, const __bf16* SA) {
   __shared__ __attribute__((aligned(16))) uint16_t tile[16 * C * MP];
-  const SysDev sd = a.sys[blockIdx.y];
+  const SysDev sd = a.sys[blockIdx.z];
   if (!sd.st->active) return;
   const int N = a.N, M = a.M, NP = round16(N);
   const int x0 = blockIdx.x * 16;
   const int nx = min(16, N - x0);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, n16 = lane & 15, g = lane >> 4;
+  const int ntile = C * M / 16;   // at most 32 (C, M <= 32, 16)
+  const int nh = gridDim.y;       // 1, or 2 when ntile is even
+  const int jt0 = blockIdx.y * (ntile / nh), jt1 = jt0 + ntile / nh;
+  const int o0 = blockIdx.y * (C / nh), o1 = o0 + C / nh;
   for (int q = t; q < 16 * C * MP / 8; q += 256) ((uint4*)tile)[q] = uint4{0u, 0u, 0u, 0u};
   // A operands of this lane's row x0 + n16, both contraction steps (k = 32 ks + 8 g ..)
   const __bf16* SAl = SA + (size_t)NP * 64;
@@ -905,16 +965,30 @@ __global__ __launch_bounds__(256) void k_xinv_bf(SpecArgs a, const __bf16* SA) {
   const __bf16* WTl = WTh + (size_t)C * M * 64;
   const float scale0 = a.basis == B_SINE ? (float)(4.0 / ((double)(N + 1) * (double)(N + 1)))
                                          : (float)(1.0 / ((double)N * (double)N));
-  const int ntile = C * M / 16;
-  for (int jt = w; jt < ntile; jt += 4) {
+  // a wave takes tiles jt0 + w, jt0 + w + 4, ...
+  constexpr int TPWV = 8;
+  bf16x8_t bh[TPWV][2], bl[TPWV][2];
+#pragma unroll
+  for (int u = 0; u < TPWV; ++u) {
+    const int jt = jt0 + w + 4 * u;
+    const int j = (jt < jt1 ? jt : jt0) * 16 + n16;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const size_t o = (size_t)j * 64 + 32 * ks + 8 * g;
+      bh[u][ks] = *(const bf16x8_t*)(WTh + o);
+      bl[u][ks] = *(const bf16x8_t*)(WTl + o);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < TPWV; ++u) {
+    const int jt = jt0 + w + 4 * u;
+    if (jt >= jt1) break;
     const int j = jt * 16 + n16;
     float4_t hr = {0.f, 0.f, 0.f, 0.f}, hi = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
-      const size_t o = (size_t)j * 64 + 32 * ks + 8 * g;
-      const bf16x8_t bh = *(const bf16x8_t*)(WTh + o), bl = *(const bf16x8_t*)(WTl + o);
-      hr = mfma_bf3(sh[ks], sl[ks], bh, bl, hr);
-      hi = mfma_bf3(ih[ks], il[ks], bh, bl, hi);
+      hr = mfma_bf3(sh[ks], sl[ks], bh[u][ks], bl[u][ks], hr);
+      hi = mfma_bf3(ih[ks], il[ks], bh[u][ks], bl[u][ks], hi);
     }
     // lane holds rows 4 g + i of column j
     const int o = j / M, ky = j - o * M;
@@ -927,9 +1001,13 @@ __global__ __launch_bounds__(256) void k_xinv_bf(SpecArgs a, const __bf16* SA) {
     }
   }
   __syncthreads();
-  const int nchunk = nx * C * MP / 8;   // 16-byte chunks of the block's rows
-  uint4* dst = (uint4*)((uint16_t*)sd.Hc + (size_t)x0 * C * MP);
-  for (int q = t; q < nchunk; q += 256) dst[q] = ((const uint4*)tile)[q];
+  // rows x0 .. x0 + nx - 1, channels o0 .. o1 - 1: one contiguous run per row
+  const int nrow = (o1 - o0) * MP / 8;   // 16-byte chunks per row
+  for (int q = t; q < nx * nrow; q += 256) {
+    const int xl = q / nrow, c = q - xl * nrow;
+    const size_t e = (size_t)(xl * C + o0) * MP + (size_t)c * 8;
+    *(uint4*)((uint16_t*)sd.Hc + (size_t)x0 * C * MP + e) = *(const uint4*)(tile + e);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -955,10 +1033,11 @@ struct LayerArgs {
   const double* bP; // float64 projection bias (device)
   void* zout;       // training: pre-activation z of this layer, [sys][N^2][C] op precision (nullable)
   size_t z_sys;     // elements per system in zout
+  int spw;          // row segments (of TPW tiles) per wave
 };
 
 template <int PREC, int C, int MP, bool FEAT, bool PROJ>
-__global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT && PREC == PBF ? 4 : 1))) void k_layer(LayerArgs a) {
   using M_ = Mf<PREC>;
   using in_t = typename M_::in_t;
   using acc_t = typename M_::acc_t;
@@ -982,11 +1061,14 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
   const SysDev sd = a.sys[blockIdx.y];
   if (!sd.st->active) return;
   const int N = a.N, NP = round16(N);
+  // A wave takes a.spw consecutive row segments of TPW tiles each and writes
+  // one partial spectrum per segment, so the results do not depend on spw.
+  const int ngrp = (a.S + a.spw - 1) / a.spw;
   const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (item >= N * a.S) return;
-  const int x = item / a.S, seg = item - x * a.S;
+  if (item >= N * ngrp) return;
+  const int x = item / ngrp, grp = item - x * ngrp;
   const int nyt = NP >> 4;
-  const int t0 = seg * TPW, t1 = min(nyt, t0 + TPW);
+  const int sg0 = grp * a.spw, sg1 = min(a.S, sg0 + a.spw);
   const double snorm = sd.st->snorm;
   const int twoM = a.twoM;
 
@@ -1211,12 +1293,31 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
   // largest share of its time), two elsewhere (more sets cost more than they
   // hide there).
   constexpr int DEPTH = (PREC == PBF && !FEAT && !PROJ) ? 4 : 2;
-  const int tf = min(t1, N >> 4);
+  // the wave's tiles T0 .. T1-1 run through one ring across its segments; at
+  // the end of each segment its partial spectrum is written and restarted
+  const int T0 = sg0 * TPW, T1 = min(nyt, sg1 * TPW);
+  const int tf = min(T1, N >> 4);
+  static_assert(TPW % DEPTH == 0, "segments must hold whole ring passes");
+  auto seg_done = [&](int t) __attribute__((always_inline)) {
+    if constexpr (!PROJ) {
+      if ((t + 1) % TPW == 0 || t + 1 == T1) {
+        acc_t* Gp = (acc_t*)sd.Gp + (size_t)(x * a.S + t / TPW) * MP * C;
+#pragma unroll
+        for (int jb = 0; jb < MB; ++jb)
+#pragma unroll
+          for (int ob = 0; ob < NOB; ++ob) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Gp[(jb * 16 + M_::row(g, i)) * C + ob * 16 + n16] = G2[jb][ob][i];
+            G2[jb][ob] = accv_t{0, 0, 0, 0};
+          }
+      }
+    }
+  };
   TileIn ring[DEPTH];
 #pragma unroll
   for (int i = 0; i < DEPTH; ++i)
-    if (t0 + i < tf) load_tile(t0 + i, ring[i], full_t{});
-  for (int t = t0; t < tf; t += DEPTH) {
+    if (T0 + i < tf) load_tile(T0 + i, ring[i], full_t{});
+  for (int t = T0; t < tf; t += DEPTH) {
 #pragma unroll
     for (int i = 0; i < DEPTH; ++i) {
       if (t + i < tf) {
@@ -1225,20 +1326,15 @@ __global__ __launch_bounds__(256) void k_layer(LayerArgs a) {
         process(t + i, cur, full_t{});
       }
     }
+    // DEPTH divides TPW and T0 is a segment start, so a segment can end only
+    // after a whole ring pass (or at the wave's last full tile)
+    seg_done(min(t + DEPTH, tf) - 1);
   }
-  if (tf < t1) {
+  if (tf < T1) {
     TileIn tl;
     load_tile(tf, tl, part_t{});
     process(tf, tl, part_t{});
-  }
-  if constexpr (!PROJ) {
-    acc_t* Gp = (acc_t*)sd.Gp + (size_t)(x * a.S + seg) * MP * C;
-#pragma unroll
-    for (int jb = 0; jb < MB; ++jb)
-#pragma unroll
-      for (int ob = 0; ob < NOB; ++ob)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) Gp[(jb * 16 + M_::row(g, i)) * C + ob * 16 + n16] = G2[jb][ob][i];
+    seg_done(tf);
   }
 }
 
@@ -1288,7 +1384,7 @@ void launch_no_setup(const NOLaunch& L, double* scratch) {
 
 template <int PREC, int C, int MP>
 static void layer_dispatch(const NOLaunch& L, const LayerArgs& la, bool feat, bool proj) {
-  const dim3 grid((L.N * L.S + 3) / 4, L.nsys);
+  const dim3 grid((L.N * ((L.S + L.spw - 1) / L.spw) + 3) / 4, L.nsys);
   if (feat && proj) hipLaunchKernelGGL((k_layer<PREC, C, MP, true, true>), grid, dim3(256), 0, L.stream, la);
   else if (feat) hipLaunchKernelGGL((k_layer<PREC, C, MP, true, false>), grid, dim3(256), 0, L.stream, la);
   else if (proj) hipLaunchKernelGGL((k_layer<PREC, C, MP, false, true>), grid, dim3(256), 0, L.stream, la);
@@ -1335,13 +1431,24 @@ static void apply_pc(const NOLaunch& L) {
     if constexpr (PREC == PBF) {
       // matrix-core x transforms (inference only: training runs FP32/FP64)
       ProfScope ps(PK_SPECTRAL, L.stream);
-      hipLaunchKernelGGL((k_xfm_bf<C>), dim3(L.M, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
-                         (const __bf16*)L.tab.FA);
+      if (L.S == 1)
+        hipLaunchKernelGGL((k_xfm_bf<C, 1>), dim3(L.M, (2 * L.M + 15) / 16, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
+                           (const __bf16*)L.tab.FA);
+      else if (L.S == 2)
+        hipLaunchKernelGGL((k_xfm_bf<C, 2>), dim3(L.M, (2 * L.M + 15) / 16, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
+                           (const __bf16*)L.tab.FA);
+      else if (L.S == 4)
+        hipLaunchKernelGGL((k_xfm_bf<C, 4>), dim3(L.M, (2 * L.M + 15) / 16, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
+                           (const __bf16*)L.tab.FA);
+      else
+        hipLaunchKernelGGL((k_xfm_bf<C, 0>), dim3(L.M, (2 * L.M + 15) / 16, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
+                           (const __bf16*)L.tab.FA);
+      const int halves = (C * L.M / 16) % 2 == 0 ? 2 : 1;   // output-channel halves per 16 rows
       if (L.MP == 16)
-        hipLaunchKernelGGL((k_xinv_bf<C, 16>), dim3(round16(L.N) / 16, L.nsys), dim3(256), 0, L.stream, sa,
+        hipLaunchKernelGGL((k_xinv_bf<C, 16>), dim3(round16(L.N) / 16, halves, L.nsys), dim3(256), 0, L.stream, sa,
                            (const __bf16*)L.tab.SA);
       else
-        hipLaunchKernelGGL((k_xinv_bf<C, 32>), dim3(round16(L.N) / 16, L.nsys), dim3(256), 0, L.stream, sa,
+        hipLaunchKernelGGL((k_xinv_bf<C, 32>), dim3(round16(L.N) / 16, halves, L.nsys), dim3(256), 0, L.stream, sa,
                            (const __bf16*)L.tab.SA);
     } else {
       ProfScope ps(PK_SPECTRAL, L.stream);
@@ -1360,7 +1467,7 @@ static void apply_pc(const NOLaunch& L) {
     // v_{l+1} in slot l so the backward pass can read every layer's input
     const int sin = L.zsave ? (l > 0 ? l - 1 : 0) : 0, sout = L.zsave ? l : 0;
     LayerArgs la{L.sys, L.N, L.S, 2 * L.M, sin, sout, L.tab.T, L.tab.TT, L.Wfrag[l], L.bias[l], L.WP, L.bP,
-                 L.zsave ? (char*)L.zsave + L.z_layer * l * L.op_bytes : nullptr, L.z_sys};
+                 L.zsave ? (char*)L.zsave + L.z_layer * l * L.op_bytes : nullptr, L.z_sys, L.spw};
     const bool feat = l == 0, proj = l == L.L - 1;
     ProfScope ps(feat ? PK_LAYER_FEAT : (proj ? PK_LAYER_PROJ : PK_LAYER), L.stream);
     if (L.MP == 16) layer_dispatch<PREC, C, 16>(L, la, feat, proj);

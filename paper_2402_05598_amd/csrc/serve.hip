@@ -139,7 +139,9 @@ NOLaunch group_no(const fcgno_engine* e, const EngGroup& g, const SysDev* table,
   L.M = m->arch.modes;
   L.MP = round16(2 * L.M);
   L.L = m->arch.layers;
-  L.S = ((round16(g.N) / 16) + TPW - 1) / TPW;
+  // groups of few requests run one row segment per wave (the same bits)
+  L.S = seg_count(g.N);
+  L.spw = nsys > 0 && nsys <= LOW_ACTIVE ? 1 : SPW_HIGH;
   L.prec = op;
   L.basis = m->arch.basis;
   L.tab.E64 = (const double*)(base + g.E64);
