@@ -401,6 +401,40 @@ struct EventSet {
   }
 };
 
+// Pinned host slots for the overlapped convergence polls of one host thread
+// (two chunks' active counts) and their events; created on first use and
+// kept (like the library streams, never released: a release at process exit
+// could run after the HIP runtime has gone).  nullptr if pinned memory or
+// events are unavailable: the solve then polls synchronously.
+struct PollBuf {
+  int* count = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int device = -1;
+};
+PollBuf* poll_buffer() {
+  thread_local PollBuf pb;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  if (pb.count && pb.device == dev) return &pb;
+  if (pb.count) {   // events belong to the device that created them
+    for (hipEvent_t& e : pb.ev)
+      if (e) (void)hipEventDestroy(e), e = nullptr;
+    (void)hipHostFree(pb.count);
+    pb.count = nullptr;
+  }
+  if (hipHostMalloc((void**)&pb.count, 2 * MAX_SUB * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    pb.count = nullptr;
+    return nullptr;
+  }
+  for (hipEvent_t& e : pb.ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      e = nullptr;
+      return nullptr;
+    }
+  pb.device = dev;
+  return &pb;
+}
+
 fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const double* k, const double* f,
                         double* u, double* r_out, int32_t* iters, int32_t* sys_status, double* rel_hist,
                         double* true_rel_res, double* true_rel_res_f, void* ws, size_t ws_bytes, void* stream,
@@ -489,8 +523,41 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
   NOLaunch NL1 = NL;
   int it = 0;
   int active = B;   // active systems at the last poll
+  // Single-stream polling overlaps the device: after queuing a chunk the host
+  // reads the previous chunk's active count (copied into pinned memory behind
+  // that chunk), so the device starts the next chunk while the host waits.  A
+  // chunk queued after every system stopped runs only the kernels' early
+  // exits.
+  PollBuf* pb = poll_buffer();
+  int pending = -1, chunks = 0;
   while (it < d->max_iter) {
     const int end = std::min(d->max_iter, it + K);
+    if (!split && pb) {
+      if (is_no(op)) NL1.spw = active <= LOW_ACTIVE ? 1 : SPW_HIGH;
+      for (int i = it; i < end; ++i) {
+        if (is_no(op)) launch_no_apply(NL1);
+        else if (op == PJAC) launch_jacobi(KL, d->precond_steps);
+        else if (op == PSGS) launch_rbsgs(KL, d->precond_steps);
+        launch_wdots(KL);
+        launch_dir(KL);
+        launch_update(KL);
+        if (rec && i < rec->m) launch_record(KL, i, rec->m, rec->rec_r, rec->rec_e, rec->ustar);
+      }
+      it = end;
+      HIPCHK(hipGetLastError());
+      const int slot = chunks++ & 1;
+      HIPCHK(hipMemcpyAsync(pb->count + slot * MAX_SUB, counter, G * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipEventRecord(pb->ev[slot], s));
+      if (pending >= 0) {
+        HIPCHK(hipEventSynchronize(pb->ev[pending]));
+        int total = 0;
+        for (int g = 0; g < G; ++g) total += std::max(pb->count[pending * MAX_SUB + g], 0);
+        if (total <= 0) break;
+        active = total;
+      }
+      pending = slot;
+      continue;
+    }
     if (!split) {
       // few systems left: one row segment per wave (more, shorter waves keep
       // more of the chip busy); the same bits either way

@@ -246,46 +246,26 @@ __global__ __launch_bounds__(256) void k_wdots(const SysDev* sys, int N) {
 constexpr int DIR_HW = TILE_J + 2, DIR_HN = (TILE_I + 2) * (TILE_J + 2);
 constexpr int DIR_HR = (DIR_HN + 255) / 256;   // halo slots per thread
 
-// Window vectors P_q at this thread's halo slots, NV of them at once (their
-// loads in flight together), then p -= sum_q c_q P_q.
-constexpr int DIR_PV = 4;   // window vectors per pass
+// p -= sum_q c_q P_q on this thread's halo slots, NV window vectors at once
+// (their loads in flight together).
+constexpr int DIR_PV = 4;   // window vectors per pass (more would cost occupancy)
 template <int NV>
-__device__ __forceinline__ void dir_load(const double* __restrict__ P, size_t n, int slot0, int ring,
-                                         const int (&hc)[DIR_HR], double (&pv)[DIR_PV][DIR_HR]) {
+__device__ __forceinline__ void dir_pass(const double* __restrict__ P, size_t n, int slot0, int ring,
+                                         const double* cf, const int (&hc)[DIR_HR], const bool (&hok)[DIR_HR],
+                                         double (&hv)[DIR_HR]) {
+  double pv[NV][DIR_HR];
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     const double* __restrict__ Pq = P + (size_t)((slot0 + q) % ring) * n;
 #pragma unroll
     for (int e = 0; e < DIR_HR; ++e) pv[q][e] = Pq[hc[e]];
   }
-}
-template <int NV>
-__device__ __forceinline__ void dir_apply(const double (&pv)[DIR_PV][DIR_HR], const double* cf,
-                                          const bool (&hok)[DIR_HR], double (&hv)[DIR_HR]) {
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     const double c = cf[q];
 #pragma unroll
     for (int e = 0; e < DIR_HR; ++e)
       if (hok[e]) hv[e] -= c * pv[q][e];
-  }
-}
-__device__ __forceinline__ void dir_load_n(int nq, const double* __restrict__ P, size_t n, int slot0, int ring,
-                                           const int (&hc)[DIR_HR], double (&pv)[DIR_PV][DIR_HR]) {
-  switch (nq) {
-    case 1: dir_load<1>(P, n, slot0, ring, hc, pv); break;
-    case 2: dir_load<2>(P, n, slot0, ring, hc, pv); break;
-    case 3: dir_load<3>(P, n, slot0, ring, hc, pv); break;
-    default: dir_load<4>(P, n, slot0, ring, hc, pv); break;
-  }
-}
-__device__ __forceinline__ void dir_apply_n(int nq, const double (&pv)[DIR_PV][DIR_HR], const double* cf,
-                                            const bool (&hok)[DIR_HR], double (&hv)[DIR_HR]) {
-  switch (nq) {
-    case 1: dir_apply<1>(pv, cf, hok, hv); break;
-    case 2: dir_apply<2>(pv, cf, hok, hv); break;
-    case 3: dir_apply<3>(pv, cf, hok, hv); break;
-    default: dir_apply<4>(pv, cf, hok, hv); break;
   }
 }
 
@@ -324,9 +304,7 @@ __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
     const double t = sd.w[hc[e]];
     hv[e] = hok[e] ? t : 0.0;
   }
-  // coefficients, then passes of at most DIR_PV window vectors (their loads
-  // in flight together; more would cost occupancy)
-  double pv[DIR_PV][DIR_HR];
+  // coefficients, then passes of at most DIR_PV window vectors
   const int nbw = flat_blocks(n);
   for (int q = 0; q < m; ++q) {
     const double d = slot_sum(sd.part, N, nbw, q, lds);
@@ -337,8 +315,13 @@ __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
   if (blockIdx.x == 0 && threadIdx.x == 0) st->m = m;
   for (int q0 = 0; q0 < m; q0 += DIR_PV) {
     const int nq = min(DIR_PV, m - q0);
-    dir_load_n(nq, sd.P, n, i - m + q0, ring, hc, pv);
-    dir_apply_n(nq, pv, cf + q0, hok, hv);
+    const int slot0 = i - m + q0;
+    switch (nq) {
+      case 1: dir_pass<1>(sd.P, n, slot0, ring, cf + q0, hc, hok, hv); break;
+      case 2: dir_pass<2>(sd.P, n, slot0, ring, cf + q0, hc, hok, hv); break;
+      case 3: dir_pass<3>(sd.P, n, slot0, ring, cf + q0, hc, hok, hv); break;
+      default: dir_pass<4>(sd.P, n, slot0, ring, cf + q0, hc, hok, hv); break;
+    }
   }
 #pragma unroll
   for (int e = 0; e < HR; ++e) {
