@@ -98,7 +98,8 @@ struct Vec {
 // Tables.  Fourier: E64/Eacc[m] = (cos, sin)(2 pi m / N); T[y][2q], T[y][2q+1]
 // = cos, sin of 2 pi q y / N for q < M.  Sine: E64/Eacc[m] = (sin(pi m/(N+1)),
 // 0) for m < 2N + 2; T[y][2q] = sin(pi (q+1)(y+1)/(N+1)), T[y][2q+1] = 0.
-// Zero elsewhere (and for y >= N); TT = T^T.
+// Zero elsewhere (and for y >= N); TT = T^T.  BF16 stores both in the layer
+// kernel's fragment order (below).
 // ---------------------------------------------------------------------------
 template <int PREC>
 __global__ void k_tables(int N, int M, int basis, double* E64, void* Eacc, void* T, void* TT) {
@@ -136,8 +137,21 @@ __global__ void k_tables(int N, int M, int basis, double* E64, void* Eacc, void*
         v = (k & 1) ? s : c;
       }
     }
-    ((in_t*)T)[y * MP + k] = M_::cvt((acc_t)v);
-    ((in_t*)TT)[k * NP + y] = M_::cvt((acc_t)v);
+    if constexpr (PREC == PBF) {
+      // Fragment order of the layer kernel's two products, so that a wave
+      // reads each 16-point tile's operands as one contiguous block: lane
+      // (n, g) = 16 g + n of tile y / 16 holds, for GEMM1 fragment ks,
+      // T[16 tile + n][16 ks + 4 g + e] at T[((tile * 64 + lane) * KT + ks) * 4 + e]
+      // and, for GEMM2 fragment jb, T[16 tile + 4 g + e][16 jb + n] at
+      // TT[((tile * 64 + lane) * KT + jb) * 4 + e]  (KT = MP / 16).
+      const int KT = MP >> 4, tile = y >> 4, yr = y & 15, kb = k >> 4, kr = k & 15;
+      const int l1 = 16 * (kr >> 2) + yr, l2 = 16 * (yr >> 2) + kr;
+      ((in_t*)T)[((tile * 64 + l1) * KT + kb) * 4 + (kr & 3)] = M_::cvt((acc_t)v);
+      ((in_t*)TT)[((tile * 64 + l2) * KT + kb) * 4 + (yr & 3)] = M_::cvt((acc_t)v);
+    } else {
+      ((in_t*)T)[y * MP + k] = M_::cvt((acc_t)v);
+      ((in_t*)TT)[k * NP + y] = M_::cvt((acc_t)v);
+    }
   }
 }
 
@@ -1037,7 +1051,7 @@ struct LayerArgs {
 };
 
 template <int PREC, int C, int MP, bool FEAT, bool PROJ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT && PREC == PBF ? 4 : 1))) void k_layer(LayerArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF ? (FEAT ? 4 : 3) : 1))) void k_layer(LayerArgs a) {
   using M_ = Mf<PREC>;
   using in_t = typename M_::in_t;
   using acc_t = typename M_::acc_t;
@@ -1064,7 +1078,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT && PRE
   // A wave takes a.spw consecutive row segments of TPW tiles each and writes
   // one partial spectrum per segment, so the results do not depend on spw.
   const int ngrp = (a.S + a.spw - 1) / a.spw;
-  const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+  // wave-uniform: kept in scalar registers, with every index derived from it
+  const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (item >= N * ngrp) return;
   const int x = item / ngrp, grp = item - x * ngrp;
   const int nyt = NP >> 4;
@@ -1102,8 +1117,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT && PRE
 
   // Lane-constant parts of every per-tile address; a tile adds the uniform
   // offset of its first point y0.
-  const in_t* Tl = T + n16 * MP + g * KPL;                       // A operand rows of GEMM1
-  const in_t* TTl = TT + n16 * NP + 4 * g;                        // A operand of GEMM2 (KPL == 4)
+  // A operands of GEMM1 and GEMM2 (bfloat16: this lane's fragments, KT of
+  // each per tile, contiguous; tile t's start at 16 t MP)
+  const in_t* Tl = KPL == 4 ? T + lane * KT * 4 : T + n16 * MP + g * KPL;
+  const in_t* TTl = KPL == 4 ? TT + lane * KT * 4 : TT;
   const in_t* act_l = act_in + n16 * C + g * CB;                  // this lane's input channels
   constexpr int CPR = C * (int)sizeof(in_t) / 16;                 // 16-byte chunks per point
   static_assert(16 * CPR <= 64 || (16 * CPR) % 64 == 0, "store chunks per lane");
@@ -1119,23 +1136,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT && PRE
     double rr;
     acc_t lk;
   };
-  auto load_tile = [&](int t, TileIn& ti, auto fullc) __attribute__((always_inline)) {
+  using full_t = std::integral_constant<bool, true>;
+  using part_t = std::integral_constant<bool, false>;
+  // A operands of GEMM1 (twiddle rows and inputs, or the raw features) ...
+  auto load_a = [&](int t, TileIn& ti, auto fullc) __attribute__((always_inline)) {
     constexpr bool FULL = decltype(fullc)::value;
     const int y0 = t * 16;
     const int ya = y0 + n16;
     const bool va = FULL || ya < N;
+    if constexpr (KPL == 4) {
+      const in_t* tp = Tl + y0 * MP;
+      if constexpr (KT % 2 == 0) {
 #pragma unroll
-    for (int ks = 0; ks < KT; ++ks) ti.Af[ks] = M_::ld(Tl + y0 * MP + ks * KSTEP);
-    if constexpr (!PROJ) {
-      if constexpr (KPL == 4) {
-#pragma unroll
-        for (int jb = 0; jb < MB; ++jb) ti.A2[jb] = M_::ld(TTl + jb * 16 * NP + y0);
+        for (int ks = 0; ks < KT; ks += 2) {
+          const short8_t v = *(const short8_t*)(tp + ks * 4);
+          ti.Af[ks] = short4_t{v[0], v[1], v[2], v[3]};
+          ti.Af[ks + 1] = short4_t{v[4], v[5], v[6], v[7]};
+        }
       } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int jb = 0; jb < MB; ++jb) ti.A2[i * MB + jb] = T[(y0 + M_::row(g, i)) * MP + jb * 16 + n16];
+        for (int ks = 0; ks < KT; ++ks) ti.Af[ks] = M_::ld(tp + ks * 4);
       }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < KT; ++ks) ti.Af[ks] = M_::ld(Tl + y0 * MP + ks * KSTEP);
     }
     if constexpr (FEAT) {
       ti.rr = va ? sd.r[(size_t)x * N + ya] : 0.0;
@@ -1155,9 +1179,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT && PRE
       }
     }
   };
-  // One 16-point tile: GEMM1, GELU, store, GEMM2 (or the projection).
-  auto process = [&](int t, const TileIn& cur, auto fullc) __attribute__((always_inline)) {
+  // ... and the twiddle operand of GEMM2
+  auto load_b = [&](int t, TileIn& ti) __attribute__((always_inline)) {
+    const int y0 = t * 16;
+    if constexpr (!PROJ) {
+      if constexpr (KPL == 4) {
+        const in_t* tp = TTl + y0 * MP;
+        if constexpr (MB % 2 == 0) {
+#pragma unroll
+          for (int jb = 0; jb < MB; jb += 2) {
+            const short8_t v = *(const short8_t*)(tp + jb * 4);
+            ti.A2[jb] = short4_t{v[0], v[1], v[2], v[3]};
+            ti.A2[jb + 1] = short4_t{v[4], v[5], v[6], v[7]};
+          }
+        } else {
+#pragma unroll
+          for (int jb = 0; jb < MB; ++jb) ti.A2[jb] = M_::ld(tp + jb * 4);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int jb = 0; jb < MB; ++jb) ti.A2[i * MB + jb] = T[(y0 + M_::row(g, i)) * MP + jb * 16 + n16];
+      }
+    }
+  };
+  // One 16-point tile: GEMM1, GELU, store, GEMM2 (or the projection).  With
+  // RELOAD, each operand set of the slot is refilled with tile tn's right
+  // after its last use, into the same registers: a refill issued before that
+  // use would need a second register set and a copy of the in-flight load,
+  // and the copy waits for it (and, the counter draining in order, for every
+  // memory operation issued before it).
+  auto process = [&](int t, TileIn& cur, int tn, auto fullc, auto reloadc) __attribute__((always_inline)) {
     constexpr bool FULL = decltype(fullc)::value;
+    constexpr bool RELOAD = decltype(reloadc)::value;
     const int y0 = t * 16;
     const int ya = y0 + n16;
     const bool va = FULL || ya < N;
@@ -1190,6 +1245,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT && PRE
 #pragma unroll
       for (int ks = 0; ks < KIN; ++ks) acc[ob] = M_::mma(Af[KT + ks], Bf[KT + ks][ob], acc[ob]);
     }
+    if constexpr (RELOAD) load_a(tn, cur, full_t{});
     // lane holds z[y0 + row(g, i)][ob*16 + n16]
     if (a.zout) {
       // training: keep the pre-activation (same LDS transpose as the activations)
@@ -1282,16 +1338,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT && PRE
           }
         }
       }
+      if constexpr (RELOAD) load_b(tn, cur);
     }
   };
-  using full_t = std::integral_constant<bool, true>;
-  using part_t = std::integral_constant<bool, false>;
   // Tiles t0 .. tf-1 hold 16 points each; at most one partial tile (the
   // row's last, when 16 does not divide N) follows.  Full tiles rotate
-  // through DEPTH register sets, each refilled DEPTH tiles ahead of its use:
-  // four for the inner bfloat16 layer (measured faster: its loads are the
-  // largest share of its time), two elsewhere (more sets cost more than they
-  // hide there).
+  // through DEPTH register sets, each refilled, after its use, with the tile
+  // DEPTH places later: four for the inner bfloat16 layer, two elsewhere.
   constexpr int DEPTH = (PREC == PBF && !FEAT && !PROJ) ? 4 : 2;
   // the wave's tiles T0 .. T1-1 run through one ring across its segments; at
   // the end of each segment its partial spectrum is written and restarted
@@ -1313,27 +1366,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FEAT && PRE
       }
     }
   };
-  TileIn ring[DEPTH];
-#pragma unroll
-  for (int i = 0; i < DEPTH; ++i)
-    if (T0 + i < tf) load_tile(T0 + i, ring[i], full_t{});
-  for (int t = T0; t < tf; t += DEPTH) {
+  if (T0 < tf) {
+    // refills past the wave's last full tile read that tile again (in
+    // bounds, unused), so that no refill is conditional
+    TileIn ring[DEPTH];
 #pragma unroll
     for (int i = 0; i < DEPTH; ++i) {
-      if (t + i < tf) {
-        const TileIn cur = ring[i];
-        if (t + i + DEPTH < tf) load_tile(t + i + DEPTH, ring[i], full_t{});
-        process(t + i, cur, full_t{});
-      }
+      load_a(min(T0 + i, tf - 1), ring[i], full_t{});
+      load_b(min(T0 + i, tf - 1), ring[i]);
     }
-    // DEPTH divides TPW and T0 is a segment start, so a segment can end only
-    // after a whole ring pass (or at the wave's last full tile)
-    seg_done(min(t + DEPTH, tf) - 1);
+    // whole ring passes, then the wave's last few full tiles
+    int t = T0;
+    for (; t + DEPTH <= tf; t += DEPTH) {
+#pragma unroll
+      for (int i = 0; i < DEPTH; ++i) process(t + i, ring[i], min(t + i + DEPTH, tf - 1), full_t{}, std::true_type{});
+      // DEPTH divides TPW and T0 is a segment start, so a segment can end
+      // only after a whole ring pass (or at the wave's last full tile)
+      seg_done(t + DEPTH - 1);
+    }
+    if (t < tf) {
+#pragma unroll
+      for (int i = 0; i < DEPTH - 1; ++i)
+        if (t + i < tf) process(t + i, ring[i], 0, full_t{}, std::false_type{});
+      seg_done(tf - 1);
+    }
   }
   if (tf < T1) {
     TileIn tl;
-    load_tile(tf, tl, part_t{});
-    process(tf, tl, part_t{});
+    load_a(tf, tl, part_t{});
+    load_b(tf, tl);
+    process(tf, tl, 0, part_t{}, std::false_type{});
     seg_done(tf);
   }
 }
