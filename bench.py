@@ -99,11 +99,14 @@ def kernel_hash():
 def layer_bytes_per_launch(N, B, C, M, esize, asize, S):
     """Algorithmic HBM bytes of one inner-layer kernel launch: read the layer
     input v_l and write v_{l+1} ([point][C], op precision), read the per-row
-    synthesis operand [N][C][MP] and write the per-row partial spectra
-    [N][S][MP][C] (accumulate precision), for B systems."""
+    synthesis operand [N][C][MP] and write the per-row partial spectra,
+    S segments x C channels x the kept mode slots (accumulate precision: the
+    bfloat16 operator stores the 2M kept slots, the others all MP), for B
+    systems."""
     MP = (2 * M + 15) // 16 * 16
+    kept = 2 * M if esize == 2 else MP
     per_point = 2 * C * esize
-    per_row = C * MP * esize + S * MP * C * asize
+    per_row = C * MP * esize + S * kept * C * asize
     return B * (N * N * per_point + N * per_row)
 
 

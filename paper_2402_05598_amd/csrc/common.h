@@ -79,7 +79,8 @@ struct SysDev {
   size_t act_stride;        // elements per activation slot
   GLOBAL void* logk;        // [N^2]
   GLOBAL double* Gr;        // [N][MP] row DFT partials of r, float64
-  GLOBAL void* Gp;          // [N][S][MP][C] row DFT partials of activations, accumulate precision
+  GLOBAL void* Gp;          // row DFT partials of activations, accumulate precision: [N][S][MP][C]
+                            // (bfloat16 operator: [M][N][S][C][2], see gp_index)
   GLOBAL void* Hc;          // [N][C][MP] synthesis rows for the layer kernel
   GLOBAL void* Vc;          // [C][2M][M] complex, accumulate precision: constant part of layer-0 spectrum
   GLOBAL void* Wh;          // [M][C][MP] complex, accumulate precision: mixed spectrum of the current layer (zero past 2M)

@@ -679,8 +679,16 @@ __device__ __forceinline__ void split_bf(float v, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(v - (float)hi);
 }
 
-// FA[h][a][2x + t] and SA[h][x][2a + t] (h: 0 hi, 1 lo; a < 32, x < NP):
-// t = 0 cos, t = 1 -sin of mode a at row x for a < 2M and x < N, else 0.
+// Twiddle A operands of the x-direction products, value (h, a, x, t) = part h
+// (0 hi, 1 lo) of t = 0: cos, t = 1: -sin of mode a < 32 at row x < NP (zero
+// for a >= 2M or x >= N), each in the fragment order of its product so that
+// a wave reads one contiguous kilobyte per fragment:
+//   FA (forward, lane (n, g) of row step s and mode group kg holds a = 16 kg
+//       + n, x = 16 s + 4 g + e / 2, t = e % 2, e < 8):
+//       FA[(((h * 2 + kg) * NP / 16 + s) * 64 + 16 g + n) * 8 + e]
+//   SA (synthesis, lane (n, g) of row tile xt and step ks holds x = 16 xt + n,
+//       2a + t = 32 ks + 8 g + e):
+//       SA[(((h * NP / 16 + xt) * 2 + ks) * 64 + 16 g + n) * 8 + e]
 __global__ __launch_bounds__(256) void k_tables_bfx(int N, int M, int basis, const double* E64, __bf16* FA,
                                                    __bf16* SA) {
   const int NP = round16(N);
@@ -694,10 +702,29 @@ __global__ __launch_bounds__(256) void k_tables_bfx(int N, int M, int basis, con
   }
   const __bf16 hi = (__bf16)(float)v;
   const __bf16 lo = (__bf16)(float)(v - (double)(float)hi);
-  FA[(size_t)a * 2 * NP + 2 * x + t] = hi;
-  FA[(size_t)32 * 2 * NP + (size_t)a * 2 * NP + 2 * x + t] = lo;
-  SA[(size_t)x * 64 + 2 * a + t] = hi;
-  SA[(size_t)NP * 64 + (size_t)x * 64 + 2 * a + t] = lo;
+  const int ns = NP >> 4;
+  const size_t fa = ((size_t)((a >> 4) * ns + (x >> 4)) * 64 + 16 * ((x & 15) >> 2) + (a & 15)) * 8 + 2 * (x & 3) + t;
+  const int col = 2 * a + t;
+  const size_t sa = ((size_t)((x >> 4) * 2 + (col >> 5)) * 64 + 16 * ((col & 31) >> 3) + (x & 15)) * 8 + (col & 7);
+  FA[fa] = hi;
+  FA[(size_t)2 * ns * 512 + fa] = lo;
+  SA[sa] = hi;
+  SA[(size_t)ns * 1024 + sa] = lo;
+}
+
+// Synthesis operand WT[h] of the mixed spectrum, value (j = o M + ky,
+// column 2a + t) in the fragment order of the synthesis product: lane
+// (n, g) of column tile jt and step ks holds j = 16 jt + n, column 32 ks +
+// 8 g + e.
+__device__ __forceinline__ size_t wt_index(int j, int col) {
+  return ((size_t)((j >> 4) * 2 + (col >> 5)) * 64 + 16 * ((col & 31) >> 3) + (j & 15)) * 8 + (col & 7);
+}
+
+// Row partial spectra of the bfloat16 layer kernel, Gp[ky][x][seg][c][t]
+// (t = 0: the cos part, 1: the sin part of mode ky; modes ky < M only):
+// the forward transform of mode ky reads one contiguous block.
+__device__ __forceinline__ size_t gp_index(int N, int S, int C, int ky, int x, int seg, int c) {
+  return ((((size_t)ky * N + x) * S + seg) * C + c) * 2;
 }
 
 // Forward transform along x and mode mixing of one layer, one block per
@@ -706,8 +733,7 @@ __global__ __launch_bounds__(256) void k_tables_bfx(int N, int M, int basis, con
 //   W^[o][a] = sum_c V^[c][a] R[c][o][a][ky]                      (vector ALU)
 // The mixing of mode a needs V^ of that mode only, so the blocks of one
 // (ky, system) split the modes and need no exchange.  The mixed spectrum is
-// written as the synthesis operand WT[h][o*M + ky][2a + t] (zero for
-// a >= 2M).  Eight waves split the 16-row steps of x; each issues the loads
+// written as the synthesis operand WT (zero for a >= 2M).  Eight waves split the 16-row steps of x; each issues the loads
 // of its steps before their products, and the eight partial tiles are added
 // in a fixed order through LDS.  Layer 0 transforms the single channel of
 // r's row partials instead and adds the per-solve constant part.
@@ -781,8 +807,9 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
     }
   } else {
     const float* Gp = (const float*)sd.Gp;
-    const __bf16* FAh = FA + (size_t)(kg * 16 + n16) * 2 * NP;
-    const __bf16* FAl = FAh + (size_t)32 * 2 * NP;
+    const int ns = NP >> 4;
+    const __bf16* FAh = FA + ((size_t)kg * ns * 64 + lane) * 8;
+    const __bf16* FAl = FAh + (size_t)2 * ns * 512;
     float4_t acc[2][NCT];
 #pragma unroll
     for (int ri = 0; ri < 2; ++ri)
@@ -798,7 +825,8 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
 #pragma unroll
       for (int u = 0; u < SPW; ++u) {
         const int st = s0 + u * NW;
-        const int x0 = (st < nsteps ? st : 0) * 16 + 4 * g;
+        const int stc = st < nsteps ? st : 0;
+        const int x0 = stc * 16 + 4 * g;
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) {
           const int c = ct * 16 + n16;
@@ -807,14 +835,14 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
             const int x = x0 + r < N ? x0 + r : 0;
 #pragma unroll
             for (int sg = 0; sg < SEG0; ++sg) {
-              const float* row = Gp + (size_t)((x * a.S + sg) * MP + 2 * ky) * C;
-              raw[u][ct][2 * r][sg] = row[c];
-              raw[u][ct][2 * r + 1][sg] = row[C + c];
+              const float2 v = *(const float2*)(Gp + gp_index(N, a.S, C, ky, x, sg, c));
+              raw[u][ct][2 * r][sg] = v.x;
+              raw[u][ct][2 * r + 1][sg] = v.y;
             }
           }
         }
-        ah[u] = *(const bf16x8_t*)(FAh + 2 * (size_t)x0);
-        al[u] = *(const bf16x8_t*)(FAl + 2 * (size_t)x0);
+        ah[u] = *(const bf16x8_t*)(FAh + (size_t)stc * 512);
+        al[u] = *(const bf16x8_t*)(FAl + (size_t)stc * 512);
       }
       // every load above completes here, before any sum or product (the
       // compiler would otherwise issue each step's loads after the previous
@@ -855,10 +883,9 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
             for (int r = 0; r < 4; ++r) {
               const int x = st * 16 + 4 * g + r;
               const bool v = st < nsteps && x < N;
-              const float* row = Gp + (size_t)(((v ? x : 0) * a.S + sg) * MP + 2 * ky) * C;
-              const float gc = row[c], gs = row[C + c];
-              gv[u][ct][2 * r] += v ? gc : 0.f;
-              gv[u][ct][2 * r + 1] += v ? gs : 0.f;
+              const float2 gcs = *(const float2*)(Gp + gp_index(N, a.S, C, ky, v ? x : 0, sg, c));
+              gv[u][ct][2 * r] += v ? gcs.x : 0.f;
+              gv[u][ct][2 * r + 1] += v ? gcs.y : 0.f;
             }
           }
         }
@@ -930,7 +957,7 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
       }
     }
     __bf16 h, l;
-    const size_t e = (size_t)(o * M + ky) * 64 + 2 * kx;
+    const size_t e = wt_index(o * M + ky, 2 * kx);
     split_bf(sr, h, l);
     WTh[e] = h;
     WTl[e] = l;
@@ -968,7 +995,7 @@ __global__ __launch_bounds__(256) void k_xinv_bf(SpecArgs a, const __bf16* SA) {
   bf16x8_t sh[2], sl[2], ih[2], il[2];
 #pragma unroll
   for (int ks = 0; ks < 2; ++ks) {
-    const size_t o = (size_t)(x0 + n16) * 64 + 32 * ks + 8 * g;
+    const size_t o = ((size_t)(blockIdx.x * 2 + ks) * 64 + lane) * 8;
     sh[ks] = *(const bf16x8_t*)(SA + o);
     sl[ks] = *(const bf16x8_t*)(SAl + o);
     ih[ks] = pairs_inv(sh[ks]);
@@ -985,10 +1012,10 @@ __global__ __launch_bounds__(256) void k_xinv_bf(SpecArgs a, const __bf16* SA) {
 #pragma unroll
   for (int u = 0; u < TPWV; ++u) {
     const int jt = jt0 + w + 4 * u;
-    const int j = (jt < jt1 ? jt : jt0) * 16 + n16;
+    const int jc = jt < jt1 ? jt : jt0;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
-      const size_t o = (size_t)j * 64 + 32 * ks + 8 * g;
+      const size_t o = ((size_t)(jc * 2 + ks) * 64 + lane) * 8;
       bh[u][ks] = *(const bf16x8_t*)(WTh + o);
       bl[u][ks] = *(const bf16x8_t*)(WTl + o);
     }
@@ -1354,15 +1381,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
   auto seg_done = [&](int t) __attribute__((always_inline)) {
     if constexpr (!PROJ) {
       if ((t + 1) % TPW == 0 || t + 1 == T1) {
-        acc_t* Gp = (acc_t*)sd.Gp + (size_t)(x * a.S + t / TPW) * MP * C;
+        if constexpr (PREC == PBF) {
+          // lane holds j = 16 jb + 4 g + i, i.e. mode 8 jb + 2 g + i / 2, part i % 2
+          float* Gp = (float*)sd.Gp;
 #pragma unroll
-        for (int jb = 0; jb < MB; ++jb)
+          for (int jb = 0; jb < MB; ++jb)
 #pragma unroll
-          for (int ob = 0; ob < NOB; ++ob) {
+            for (int ob = 0; ob < NOB; ++ob) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) Gp[(jb * 16 + M_::row(g, i)) * C + ob * 16 + n16] = G2[jb][ob][i];
-            G2[jb][ob] = accv_t{0, 0, 0, 0};
-          }
+              for (int ip = 0; ip < 2; ++ip) {
+                const int ky = 8 * jb + 2 * g + ip;
+                if (2 * ky < twoM)
+                  *(float2*)(Gp + gp_index(N, a.S, C, ky, x, t / TPW, ob * 16 + n16)) =
+                      float2{G2[jb][ob][2 * ip], G2[jb][ob][2 * ip + 1]};
+              }
+              G2[jb][ob] = accv_t{0, 0, 0, 0};
+            }
+        } else {
+          acc_t* Gp = (acc_t*)sd.Gp + (size_t)(x * a.S + t / TPW) * MP * C;
+#pragma unroll
+          for (int jb = 0; jb < MB; ++jb)
+#pragma unroll
+            for (int ob = 0; ob < NOB; ++ob) {
+#pragma unroll
+              for (int i = 0; i < 4; ++i) Gp[(jb * 16 + M_::row(g, i)) * C + ob * 16 + n16] = G2[jb][ob][i];
+              G2[jb][ob] = accv_t{0, 0, 0, 0};
+            }
+        }
       }
     }
   };
