@@ -34,7 +34,8 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "layer_bf16_512x512x16_traffic.json")
 BENCH_WEIGHTS = os.path.join(ROOT, "weights", "bench_operator_c32_m12_l4.npy")
-KERNEL_SOURCES = ("paper_2402_05598_amd/csrc/no_fwd.hip", "paper_2402_05598_amd/csrc/common.h")
+KERNEL_SOURCES = ("paper_2402_05598_amd/csrc/no_fwd.hip", "paper_2402_05598_amd/csrc/common.h",
+                  "paper_2402_05598_amd/csrc/mfma.h")
 
 
 def parse():

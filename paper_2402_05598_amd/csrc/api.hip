@@ -157,17 +157,12 @@ size_t part_blocks(int N) {
   return std::max(flat, tile);
 }
 
-// backward row-kernel geometry for N points per row
+// backward kernel geometry: Sb row segments of TPW tiles per row, nbs = N Sb
+// row segments per system (one wave each)
 void bwd_geometry(int N, int prec, int& Sb, int& nbs) {
-  const int PB = prec == P64 ? PtsPerBlock<double>::value : PtsPerBlock<float>::value;
-  if (N <= PB) {
-    const int RB = PB / N;
-    Sb = 1;
-    nbs = (N + RB - 1) / RB;
-  } else {
-    Sb = (N + PB - 1) / PB;
-    nbs = N * Sb;
-  }
+  (void)prec;
+  Sb = seg_count(N);
+  nbs = N * Sb;
 }
 
 Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int op, int kind) {
@@ -195,7 +190,7 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
     const int esz = op_esize(op), asz = acc_esize(op);
     if (kind == KIND_TRAIN) {
       bwd_geometry(N, op, p.Sb, p.nbs);
-      p.nblk = B * p.nbs;
+      p.nblk = (int)(((size_t)B * p.nbs + 3) / 4);   // four row segments per block
     }
     p.S_seg = S;
     p.MP = MP;

@@ -25,66 +25,10 @@
 #include <type_traits>
 
 #include "common.h"
+#include "mfma.h"
 #include "prof.h"
 
 namespace fcgno {
-
-typedef short short4_t __attribute__((ext_vector_type(4)));
-typedef float float4_t __attribute__((ext_vector_type(4)));
-typedef double double4_t __attribute__((ext_vector_type(4)));
-
-template <int PREC> struct Mf;
-
-template <> struct Mf<P64> {
-  using in_t = double;
-  using acc_t = double;
-  using frag_t = double;
-  using accv_t = double4_t;
-  static constexpr int KPL = 1;
-  // accumulator item i of lane (n, g) holds row 4*i + g (rows interleaved)
-  static __device__ __forceinline__ int row(int g, int i) { return 4 * i + g; }
-  static __device__ __forceinline__ accv_t mma(frag_t a, frag_t b, accv_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ in_t cvt(acc_t v) { return v; }
-  static __device__ __forceinline__ acc_t up(in_t v) { return v; }
-  static __device__ __forceinline__ frag_t ld(const in_t* p) { return *p; }
-  static __device__ __forceinline__ frag_t zero() { return 0.0; }
-};
-
-template <> struct Mf<P32> {
-  using in_t = float;
-  using acc_t = float;
-  using frag_t = float;
-  using accv_t = float4_t;
-  static constexpr int KPL = 1;
-  // accumulator item i of lane (n, g) holds row 4*g + i
-  static __device__ __forceinline__ int row(int g, int i) { return 4 * g + i; }
-  static __device__ __forceinline__ accv_t mma(frag_t a, frag_t b, accv_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ in_t cvt(acc_t v) { return v; }
-  static __device__ __forceinline__ acc_t up(in_t v) { return v; }
-  static __device__ __forceinline__ frag_t ld(const in_t* p) { return *p; }
-  static __device__ __forceinline__ frag_t zero() { return 0.0f; }
-};
-
-template <> struct Mf<PBF> {
-  using in_t = uint16_t;
-  using acc_t = float;
-  using frag_t = short4_t;
-  using accv_t = float4_t;
-  static constexpr int KPL = 4;
-  // accumulator item i of lane (n, g) holds row 4*g + i
-  static __device__ __forceinline__ int row(int g, int i) { return 4 * g + i; }
-  static __device__ __forceinline__ accv_t mma(frag_t a, frag_t b, accv_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ in_t cvt(acc_t v) { return f2bf(v); }
-  static __device__ __forceinline__ acc_t up(in_t v) { return bf2f(v); }
-  static __device__ __forceinline__ frag_t ld(const in_t* p) { return *(const short4_t*)p; }
-  static __device__ __forceinline__ frag_t zero() { return short4_t{0, 0, 0, 0}; }
-};
 
 __host__ __device__ inline int round16(int v) { return (v + 15) & ~15; }
 
@@ -976,7 +920,7 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
 // j = 16 jt .. 16 jt + 15, so the first half of the tiles holds exactly the
 // channels o < C/2.  Waves take the block's tiles in turn; the rows pass
 // through LDS for contiguous stores.
-template <int C, int MP>
+template <int C, int MP, int TPWV>
 __global__ __launch_bounds__(256) void k_xinv_bf(SpecArgs a, const __bf16* SA) {
   __shared__ __attribute__((aligned(16))) uint16_t tile[16 * C * MP];
   const SysDev sd = a.sys[blockIdx.z];
@@ -1006,8 +950,7 @@ __global__ __launch_bounds__(256) void k_xinv_bf(SpecArgs a, const __bf16* SA) {
   const __bf16* WTl = WTh + (size_t)C * M * 64;
   const float scale0 = a.basis == B_SINE ? (float)(4.0 / ((double)(N + 1) * (double)(N + 1)))
                                          : (float)(1.0 / ((double)N * (double)N));
-  // a wave takes tiles jt0 + w, jt0 + w + 4, ...
-  constexpr int TPWV = 8;
+  // a wave takes tiles jt0 + w, jt0 + w + 4, ... (at most TPWV of them)
   bf16x8_t bh[TPWV][2], bl[TPWV][2];
 #pragma unroll
   for (int u = 0; u < TPWV; ++u) {
@@ -1551,12 +1494,18 @@ static void apply_pc(const NOLaunch& L) {
         hipLaunchKernelGGL((k_xfm_bf<C, 0>), dim3(L.M, (2 * L.M + 15) / 16, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
                            (const __bf16*)L.tab.FA);
       const int halves = (C * L.M / 16) % 2 == 0 ? 2 : 1;   // output-channel halves per 16 rows
-      if (L.MP == 16)
-        hipLaunchKernelGGL((k_xinv_bf<C, 16>), dim3(round16(L.N) / 16, halves, L.nsys), dim3(256), 0, L.stream, sa,
-                           (const __bf16*)L.tab.SA);
-      else
-        hipLaunchKernelGGL((k_xinv_bf<C, 32>), dim3(round16(L.N) / 16, halves, L.nsys), dim3(256), 0, L.stream, sa,
-                           (const __bf16*)L.tab.SA);
+      // column tiles per wave (four waves), rounded up to a power of two
+      const int tpw = (C * L.M / 16 / halves + 3) / 4;
+      const dim3 xg(round16(L.N) / 16, halves, L.nsys);
+      auto xinv = [&](auto mpc) {
+        constexpr int MPC = decltype(mpc)::value;
+        if (tpw <= 1) hipLaunchKernelGGL((k_xinv_bf<C, MPC, 1>), xg, dim3(256), 0, L.stream, sa, (const __bf16*)L.tab.SA);
+        else if (tpw <= 2) hipLaunchKernelGGL((k_xinv_bf<C, MPC, 2>), xg, dim3(256), 0, L.stream, sa, (const __bf16*)L.tab.SA);
+        else if (tpw <= 4) hipLaunchKernelGGL((k_xinv_bf<C, MPC, 4>), xg, dim3(256), 0, L.stream, sa, (const __bf16*)L.tab.SA);
+        else hipLaunchKernelGGL((k_xinv_bf<C, MPC, 8>), xg, dim3(256), 0, L.stream, sa, (const __bf16*)L.tab.SA);
+      };
+      if (L.MP == 16) xinv(std::integral_constant<int, 16>{});
+      else xinv(std::integral_constant<int, 32>{});
     } else {
       ProfScope ps(PK_SPECTRAL, L.stream);
       constexpr int SR = SynthRows<PREC>::SR;

@@ -6,9 +6,6 @@ namespace fcgno {
 
 __host__ __device__ inline int round16_t(int v) { return (v + 15) & ~15; }
 
-// points per block of the backward row kernel (LDS holds two [PB][C+1] tiles)
-template <typename T> struct PtsPerBlock { static constexpr int value = 128; };
-template <> struct PtsPerBlock<double> { static constexpr int value = 64; };
 
 struct LossArgs {
   int N, B, nb;            // nb: flat blocks per system
@@ -24,12 +21,14 @@ struct LossArgs {
 };
 
 struct BwdArgs {
-  int N, M, MP, L, mode, l, nbs, S;   // S: row segments (N > points per block)
+  int N, M, MP, L, mode, l, nbs, S;   // S: row segments of TPW tiles; nbs = N S row segments per system
+  int B;                              // systems
   const SysState* st;                 // per system: snorm
   const double* gscale;               // [B]
   const double* gw;                   // [B][N^2] upstream gradient of w (before gscale)
   const double* r;                    // [B][N^2]
   const double* k;                    // [B][N+2]^2
+  const void* logk;                   // [B][N^2] log k in the op precision (forward set-up)
   const void* z;                      // saved pre-activations [L][B][N^2][C]
   size_t z_sys, z_layer;
   const void* act;                    // saved activations, slot s = v_{s+1}
@@ -43,7 +42,7 @@ struct BwdArgs {
   size_t off_W, off_WP, off_WL, off_bL;
   void* Gb;                           // [B][N][S][MP][C] row partials of dz (accumulate precision)
   size_t gb_sys;
-  // per-block partial gradients (accumulate precision)
+  // partial gradients, one set per block of four row segments (accumulate precision)
   void* pdW; void* pdb; void* pdWP; void* pdbP; void* pdWL; void* pdbL;
   double* dphi0;                      // nullable [B][N^2]: gradient w.r.t. the feature r/s (float64)
 };

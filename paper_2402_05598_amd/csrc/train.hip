@@ -16,6 +16,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "mfma.h"
 #include "prof.h"
 #include "train.h"
 
@@ -123,197 +124,339 @@ __global__ __launch_bounds__(256) void k_loss_fin(LossArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Backward row kernel.  One thread per point; a block covers RB whole rows
-// (N <= PB) or one PB-point segment of a row (N > PB).
-//   mode 0 (start):  dv = s * scale * A(w-e) * W_P, plus dW_P, db_P
+// Backward layer kernel (matrix cores).  One wave per row segment of TPW
+// 16-point tiles (x = row, y = column, p = x N + y), four waves per block:
+//   mode 0 (start):  dv = s * scale_b * gw * W_P            (outer product)
 //   mode 1 (layer l): dv = W_l^T dz_l + sum_j T[y][j] Hc_b[x][c][j]
-// then for the target layer tl = (start ? L-1 : l-1):
-//   tl >= 0: dz_tl = dv * GELU'(z_tl), dW_tl, db_tl, row DFT partials of dz_tl
-//   tl < 0 : dW_L, db_L of the lift (features phi)
+//       per tile [16 y] x [C]: A operands dz_l and T rows, B operands W_l and
+//       the row's adjoint synthesis Hc_b[x] (held for the whole segment)
+// then for the target layer tl = (mode 0 ? L-1 : l-1):
+//   tl >= 0: dz_tl = dv * GELU'(z_tl), stored; dW_tl += dz_tl^T v_tl and
+//       the row partials Gb[j][c] += sum_y T[y][j] dz_tl[y][c] (both products
+//       contract over the tile's points, read from the accumulator layout);
+//       db_tl += sum dz_tl
+//   tl < 0 (lift): dW_L += dv^T phi, db_L += sum dv, and the feature
+//       gradient dphi0[p] = W_L[:, 0] . dv
+// The four waves' partial weight gradients are added in a fixed order and
+// written once per block.  Contraction order of the channel products: step
+// ks, lane group g takes channel g KC + ks (KC = C / 4), so that each lane's
+// A operand of a tile is one contiguous run of its point's channels; the
+// same for the synthesis index j (KJ = MP / 4).
 // ---------------------------------------------------------------------------
-template <typename acc_t, int C>
-__global__ void k_bwd(BwdArgs a) {
-  constexpr int PB = PtsPerBlock<acc_t>::value;
-  __shared__ acc_t sA[PB][C + 1];     // dz (or dv, or s*g*v_L)
-  __shared__ acc_t sV[PB][C + 1];     // v_tl (or features)
-  __shared__ acc_t sW[C][C + 1];      // W_l (row o, col c)
-  __shared__ acc_t sg[PB];
-  const int N = a.N, n = N * N, MP = a.MP, twoM = 2 * a.M;
-  const int b = blockIdx.x / a.nbs, ub = blockIdx.x - b * a.nbs;
-  const int t = threadIdx.x;
-  int x, y;
-  bool valid;
-  if (N <= PB) {
-    const int RB = PB / N;
-    x = ub * RB + t / N;
-    y = t % N;
-    valid = (t < RB * N) && x < N;
-  } else {
-    x = ub / a.S;
-    y = (ub - x * a.S) * PB + t;
-    valid = y < N;
-  }
-  // tail threads keep in-range indices so that no load can leave the buffers
-  if (!valid) { x = 0; y = 0; }
-  const size_t p = (size_t)x * N + y;
-  const int tl = a.mode == 0 ? a.L - 1 : a.l - 1;
+// SRC: 0 start (dv from the projection), 1 layer l.  TGT: 0 target layer
+// tl >= 1 (input from the saved activations), 1 target layer 0 (input
+// recomputed from the lift), 2 the lift itself (tl < 0).
+template <int PREC, int C, int MP, int SRC, int TGT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == P32 && TGT != 1 ? 3 : 1))) void k_bwd(BwdArgs a) {
+  using M_ = Mf<PREC>;
+  using acc_t = typename M_::acc_t;
+  using accv_t = typename M_::accv_t;
+  constexpr int NOB = C / 16, KC = C / 4, KJ = MP / 4, MB = MP / 16;
+  constexpr int NW = 4;
+  static_assert(M_::KPL == 1, "FP32 / FP64 only");
+  __shared__ acc_t red[NW][C * C];
+  __shared__ acc_t red2[NW][4][2 * C + 1];   // [wave][lane group][per-channel sums, db_P]
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n16 = lane & 15, g = lane >> 4;
+  const int N = a.N, n = N * N;
+  const int tl = SRC == 0 ? a.L - 1 : a.l - 1;
+  const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * NW + w);
+  const bool live = item < a.B * a.nbs;
+  const int b = live ? item / a.nbs : 0;
+  const int rem = item - b * a.nbs;
+  const int x = live ? rem / a.S : 0, seg = live ? rem - (rem / a.S) * a.S : 0;
+  const int nyt = (N + 15) >> 4;
+  const int t0 = seg * TPW, t1 = live ? min(nyt, t0 + TPW) : t0;
   const double* blob = a.blob;
-  acc_t* pdW = (acc_t*)a.pdW;
-  acc_t* pdb = (acc_t*)a.pdb;
-  acc_t* pdWP = (acc_t*)a.pdWP;
-  acc_t* pdbP = (acc_t*)a.pdbP;
-  acc_t* pdWL = (acc_t*)a.pdWL;
-  acc_t* pdbL = (acc_t*)a.pdbL;
-  // --- dv ---
-  acc_t dv[C];
-  if (a.mode == 0) {
-    const double snorm = a.st[b].snorm;
-    const acc_t gws = valid ? (acc_t)(snorm * a.gscale[b] * a.gw[(size_t)b * n + p]) : (acc_t)0;
-    const acc_t* z = (const acc_t*)a.z + (size_t)(a.L - 1) * a.z_layer + (size_t)b * a.z_sys + p * C;
+  const double hstep = 1.0 / (double)(N + 1);
+  const double snorm = a.st[b].snorm;
+  const double inv_s = snorm > 0.0 ? 1.0 / snorm : 0.0;
+  const acc_t* T = (const acc_t*)a.T;
+  const size_t rowp = (size_t)x * N;   // first point of the row
+  const acc_t* zt = (const acc_t*)a.z + (size_t)(TGT == 2 ? 0 : tl) * a.z_layer + (size_t)b * a.z_sys + rowp * C;
+  const acc_t* vt = (const acc_t*)a.act + (size_t)(TGT == 0 ? tl - 1 : 0) * a.act_slot + (size_t)b * a.act_sys + rowp * C;
+  const acc_t* dzl = (const acc_t*)a.dz_in + (size_t)b * n * C + rowp * C;
+  acc_t* dzo = (acc_t*)a.dz_out + (size_t)b * n * C + rowp * C;
+  const acc_t* lk = (const acc_t*)a.logk + (size_t)b * n + rowp;   // log k of the forward's set-up
+  const double* rr = a.r + (size_t)b * n + rowp;
+
+  // B operands of the layer products: W_l[o = g KC + ks][c], Hc_b[x][c][j = g KJ + ks]
+  acc_t BW[SRC == 1 ? KC : 1][NOB], BH[SRC == 1 ? KJ : 1][NOB], wpc[NOB];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      dv[c] = gws * (acc_t)blob[a.off_WP + c];
-      sA[t][c] = valid ? gws * gelu_t<acc_t>(z[c]) : (acc_t)0;   // for dW_P
-    }
-    sg[t] = gws;
-    __syncthreads();
-    if (t < C) {
-      acc_t s = 0;
-      for (int q = 0; q < PB; ++q) s += sA[q][t];
-      pdWP[(size_t)blockIdx.x * C + t] = s;
-    }
-    if (t == 0) {
-      acc_t s = 0;
-      for (int q = 0; q < PB; ++q) s += sg[q];
-      pdbP[blockIdx.x] = s;
-    }
-    __syncthreads();
-  } else {
-    for (int q = t; q < C * C; q += PB) sW[q / C][q % C] = (acc_t)blob[a.off_W + q];
-    __syncthreads();
-    const acc_t* dzl = (const acc_t*)a.dz_in + (size_t)b * n * C + p * C;
-    acc_t dzv[C];
+  for (int ob = 0; ob < NOB; ++ob) {
+    const int c = ob * 16 + n16;
+    if constexpr (SRC == 1) {
 #pragma unroll
-    for (int o = 0; o < C; ++o) dzv[o] = valid ? dzl[o] : (acc_t)0;
+      for (int ks = 0; ks < KC; ++ks) BW[ks][ob] = (acc_t)blob[a.off_W + (size_t)(g * KC + ks) * C + c];
+      const acc_t* Hc = (const acc_t*)a.Hcb + (size_t)b * a.hc_sys + ((size_t)x * C + c) * MP + g * KJ;
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      acc_t s = 0;
-#pragma unroll
-      for (int o = 0; o < C; ++o) s += sW[o][c] * dzv[o];
-      dv[c] = s;
-    }
-    if (valid) {
-      const acc_t* Tr = (const acc_t*)a.T + (size_t)y * MP;
-      const acc_t* Hc = (const acc_t*)a.Hcb + (size_t)b * a.hc_sys + (size_t)x * C * MP;
-      for (int j = 0; j < twoM; ++j) {
-        const acc_t tj = Tr[j];
-#pragma unroll
-        for (int c = 0; c < C; ++c) dv[c] += tj * Hc[c * MP + j];
-      }
+      for (int ks = 0; ks < KJ; ++ks) BH[ks][ob] = Hc[ks];
+    } else {
+      wpc[ob] = (acc_t)blob[a.off_WP + c];
     }
   }
-  // --- target layer ---
-  const double hstep = 1.0 / (double)(N + 1);
-  if (tl >= 0) {
-    const acc_t* z = (const acc_t*)a.z + (size_t)tl * a.z_layer + (size_t)b * a.z_sys + p * C;
-    acc_t* dzo = (acc_t*)a.dz_out + (size_t)b * n * C + p * C;
-    // input v_tl of layer tl
-    if (tl >= 1) {
-      const acc_t* v = (const acc_t*)a.act + (size_t)(tl - 1) * a.act_slot + (size_t)b * a.act_sys + p * C;
+  accv_t dW[NOB][NOB], G2[MB][NOB];
 #pragma unroll
-      for (int c = 0; c < C; ++c) sV[t][c] = valid ? v[c] : (acc_t)0;
+  for (int i = 0; i < NOB; ++i)
+#pragma unroll
+    for (int j = 0; j < NOB; ++j) dW[i][j] = accv_t{0, 0, 0, 0};
+#pragma unroll
+  for (int jb = 0; jb < MB; ++jb)
+#pragma unroll
+    for (int ob = 0; ob < NOB; ++ob) G2[jb][ob] = accv_t{0, 0, 0, 0};
+  acc_t s1[NOB], s2[NOB];   // db (or db_L) and dW_P per channel; dW_L through dW
+  acc_t dbp = 0;
+#pragma unroll
+  for (int ob = 0; ob < NOB; ++ob) s1[ob] = s2[ob] = 0;
+
+  // A operands of GEMM1 for one tile (this lane's point y0 + n, contiguous
+  // channel and twiddle runs), two tiles in flight; rows past N read row
+  // N - 1 (zero in T) and are masked
+  struct TileA {
+    acc_t dz[SRC == 1 ? KC : 1], tw[SRC == 1 ? KJ : 1];
+  };
+  auto load_a = [&](int t, TileA& ta) __attribute__((always_inline)) {
+    if constexpr (SRC == 1) {
+      const int ya = t * 16 + n16;
+      const int yc = ya < N ? ya : N - 1;
+      const acc_t* dzr = dzl + (size_t)yc * C + g * KC;
+      const acc_t* tr = T + (size_t)ya * MP + g * KJ;   // T has NP >= ya + 1 rows
+#pragma unroll
+      for (int ks = 0; ks < KC; ++ks) ta.dz[ks] = dzr[ks];
+#pragma unroll
+      for (int ks = 0; ks < KJ; ++ks) ta.tw[ks] = tr[ks];
+    }
+  };
+  TileA ring[2];
+  if (t0 < t1) {
+    load_a(t0, ring[0]);
+    load_a(min(t0 + 1, t1 - 1), ring[1]);
+  }
+  auto tile = [&](int t, TileA& ta) __attribute__((always_inline)) {
+    const int y0 = t * 16;
+    int yr[4];
+    bool vr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int y = y0 + M_::row(g, i);
+      vr[i] = y < N;
+      yr[i] = vr[i] ? y : N - 1;
+    }
+    // loads of the accumulator-layout operands first: their latency runs
+    // under GEMM1
+    acc_t zv[NOB][4], vv[NOB][4], gws[4], A2[4][MB];
+    double ph0[4], ph1[4];
+    if constexpr (SRC == 0) {
+      const double sc = snorm * a.gscale[b];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        gws[i] = vr[i] ? (acc_t)(sc * a.gw[(size_t)b * n + rowp + yr[i]]) : (acc_t)0;
+    }
+    if constexpr (TGT <= 1) {
+#pragma unroll
+      for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) zv[ob][i] = zt[(size_t)yr[i] * C + ob * 16 + n16];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jb = 0; jb < MB; ++jb) A2[i][jb] = T[(size_t)(y0 + M_::row(g, i)) * MP + jb * 16 + n16];
+    }
+    if constexpr (TGT == 0) {
+#pragma unroll
+      for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vv[ob][i] = vt[(size_t)yr[i] * C + ob * 16 + n16];
     } else {
-      double phi[4] = {0.0, 0.0, 0.0, 0.0};
-      if (valid) {
-        const double snorm = a.st[b].snorm;
-        const double inv_s = snorm > 0.0 ? 1.0 / snorm : 0.0;
-        phi[0] = a.r[(size_t)b * n + p] * inv_s;
-        phi[1] = log(a.k[(size_t)b * (N + 2) * (N + 2) + (size_t)(x + 1) * (N + 2) + y + 1]);
-        phi[2] = (double)(x + 1) * hstep;
-        phi[3] = (double)(y + 1) * hstep;
-      }
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        double v0 = blob[a.off_bL + c];
-        for (int f = 0; f < 4; ++f) v0 += blob[a.off_WL + c * 4 + f] * phi[f];
-        sV[t][c] = valid ? (acc_t)v0 : (acc_t)0;
+      for (int i = 0; i < 4; ++i) {
+        ph0[i] = rr[yr[i]] * inv_s;
+        ph1[i] = (double)lk[yr[i]];
       }
     }
+    // --- dv in the accumulator layout: item i of lane (c, g) is dv[y0 + row(g, i)][c]
+    accv_t dv[NOB];
+    if constexpr (SRC == 0) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const acc_t d = valid ? dv[c] * dgelu_t<acc_t>(z[c]) : (acc_t)0;
-      sA[t][c] = d;
-      if (valid) dzo[c] = d;
-    }
-    __syncthreads();
-    // dW_tl[o][c] = sum dz[o] v[c], db_tl[o] = sum dz[o]
-    for (int q = t; q < C * C; q += PB) {
-      const int o = q / C, c = q - o * C;
-      acc_t s = 0;
-      for (int u = 0; u < PB; ++u) s += sA[u][o] * sV[u][c];
-      pdW[(size_t)blockIdx.x * C * C + q] = s;
-    }
-    for (int o = t; o < C; o += PB) {
-      acc_t s = 0;
-      for (int u = 0; u < PB; ++u) s += sA[u][o];
-      pdb[(size_t)blockIdx.x * C + o] = s;
-    }
-    // row partials of the y-direction DFT of dz: Gb[x][seg][j][o] = sum_y T[y][j] dz[y][o]
-    acc_t* Gb = (acc_t*)a.Gb;
-    if (N <= PB) {
-      const int RB = PB / N;
-      for (int q = t; q < RB * MP * C; q += PB) {
-        const int xr = q / (MP * C), rem = q - xr * (MP * C), j = rem / C, o = rem - j * C;
-        const int xx = ub * RB + xr;
-        if (xx >= N) continue;
-        acc_t s = 0;
-        if (j < twoM)
-          for (int yy = 0; yy < N; ++yy) s += ((const acc_t*)a.T)[(size_t)yy * MP + j] * sA[xr * N + yy][o];
-        Gb[(size_t)b * a.gb_sys + (size_t)xx * MP * C + rem] = s;
-      }
+      for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dv[ob][i] = gws[i] * wpc[ob];
     } else {
-      const int xb = ub / a.S, seg = ub - xb * a.S;   // block-uniform row and segment
-      const int y0 = seg * PB;
-      for (int q = t; q < MP * C; q += PB) {
-        const int j = q / C, o = q - j * C;
-        acc_t s = 0;
-        if (j < twoM)
-          for (int u = 0; u < PB && y0 + u < N; ++u) s += ((const acc_t*)a.T)[(size_t)(y0 + u) * MP + j] * sA[u][o];
-        Gb[(size_t)b * a.gb_sys + ((size_t)xb * a.S + seg) * MP * C + q] = s;
+      const bool va = y0 + n16 < N;
+#pragma unroll
+      for (int ob = 0; ob < NOB; ++ob) {
+        accv_t acc = accv_t{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < KC; ++ks) acc = M_::mma(va ? ta.dz[ks] : (acc_t)0, BW[ks][ob], acc);
+#pragma unroll
+        for (int ks = 0; ks < KJ; ++ks) acc = M_::mma(ta.tw[ks], BH[ks][ob], acc);
+        dv[ob] = acc;
       }
+    }
+    if constexpr (TGT <= 1) {
+      // --- dz_tl = dv GELU'(z_tl), its store, db, dW_P
+      accv_t dz[NOB];
+#pragma unroll
+      for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const acc_t d = vr[i] ? dv[ob][i] * dgelu_t<acc_t>(zv[ob][i]) : (acc_t)0;
+          dz[ob][i] = d;
+          if (vr[i]) dzo[(size_t)yr[i] * C + ob * 16 + n16] = d;
+          s1[ob] += d;
+          if constexpr (SRC == 0) s2[ob] += vr[i] ? gws[i] * gelu_t<acc_t>(zv[ob][i]) : (acc_t)0;
+        }
+      if constexpr (SRC == 0) {
+        if (n16 == 0) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) dbp += gws[i];
+        }
+      }
+      // --- input v_tl of layer tl in the accumulator layout
+      accv_t v[NOB];
+      if constexpr (TGT == 0) {
+#pragma unroll
+        for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v[ob][i] = vr[i] ? vv[ob][i] : (acc_t)0;
+      } else {
+        // v_0 = W_L phi + b_L
+#pragma unroll
+        for (int ob = 0; ob < NOB; ++ob) {
+          const int c = ob * 16 + n16;
+          const double bl = blob[a.off_bL + c], w0 = blob[a.off_WL + c * 4], w1 = blob[a.off_WL + c * 4 + 1],
+                       w2 = blob[a.off_WL + c * 4 + 2], w3 = blob[a.off_WL + c * 4 + 3];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double v0 = bl + w0 * ph0[i] + w1 * ph1[i] + w2 * ((double)(x + 1) * hstep) +
+                              w3 * ((double)(yr[i] + 1) * hstep);
+            v[ob][i] = vr[i] ? (acc_t)v0 : (acc_t)0;
+          }
+        }
+      }
+      // --- dW_tl[o][c] += sum_y dz[y][o] v[y][c]: K-step i takes the rows
+      // row(g, i) of both accumulator layouts
+#pragma unroll
+      for (int oo = 0; oo < NOB; ++oo)
+#pragma unroll
+        for (int oc = 0; oc < NOB; ++oc)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) dW[oo][oc] = M_::mma(dz[oo][i], v[oc][i], dW[oo][oc]);
+      // --- row partials Gb[j][c] += sum_y T[y][j] dz[y][c]
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jb = 0; jb < MB; ++jb)
+#pragma unroll
+          for (int ob = 0; ob < NOB; ++ob) G2[jb][ob] = M_::mma(A2[i][jb], dz[ob][i], G2[jb][ob]);
+    } else {
+      // --- lift: dW_L[c][f] += dv[y][c] phi[y][f] (in dW[0][0] .. as
+      // [c][f] sums per lane), db_L, dphi0
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double phi[4] = {ph0[i], ph1[i], (double)(x + 1) * hstep, (double)(yr[i] + 1) * hstep};
+        double d0 = 0.0;
+#pragma unroll
+        for (int ob = 0; ob < NOB; ++ob) {
+          const acc_t d = vr[i] ? dv[ob][i] : (acc_t)0;
+          s1[ob] += d;
+#pragma unroll
+          for (int f = 0; f < 4; ++f) dW[ob][0][f] += d * (acc_t)phi[f];
+          d0 += blob[a.off_WL + (ob * 16 + n16) * 4] * (double)d;
+        }
+        if (a.dphi0) {
+          // W_L[:, 0] . dv over the C channels: lanes n of this group, then blocks ob
+          d0 += __shfl_xor(d0, 1, 64);
+          d0 += __shfl_xor(d0, 2, 64);
+          d0 += __shfl_xor(d0, 4, 64);
+          d0 += __shfl_xor(d0, 8, 64);
+          if (n16 == 0 && vr[i]) a.dphi0[(size_t)b * n + rowp + yr[i]] = d0;
+        }
+      }
+    }
+  };
+  for (int t = t0; t < t1; t += 2) {
+    tile(t, ring[0]);
+    load_a(min(t + 2, t1 - 1), ring[0]);
+    if (t + 1 < t1) {
+      tile(t + 1, ring[1]);
+      load_a(min(t + 3, t1 - 1), ring[1]);
+    }
+  }
+  // --- the segment's row partial spectrum
+  if constexpr (TGT <= 1) {
+    if (live) {
+      acc_t* Gb = (acc_t*)a.Gb + (size_t)b * a.gb_sys + ((size_t)x * a.S + seg) * MP * C;
+#pragma unroll
+      for (int jb = 0; jb < MB; ++jb)
+#pragma unroll
+        for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) Gb[(jb * 16 + M_::row(g, i)) * C + ob * 16 + n16] = G2[jb][ob][i];
+    }
+  }
+
+  // --- the block's partial gradients: four waves in a fixed order
+  if constexpr (TGT <= 1) {
+    // accumulator item i of lane (c, g) in tile (oo, oc) holds dW[oo 16 + row(g, i)][oc 16 + c]
+#pragma unroll
+    for (int oo = 0; oo < NOB; ++oo)
+#pragma unroll
+      for (int oc = 0; oc < NOB; ++oc)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[w][(oo * 16 + M_::row(g, i)) * C + oc * 16 + n16] = dW[oo][oc][i];
+  } else {
+    // dW_L[c][f] per lane (group g) in dW[ob][0][f]
+#pragma unroll
+    for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) red[w][(g * C + ob * 16 + n16) * 4 + f] = dW[ob][0][f];
+  }
+#pragma unroll
+  for (int ob = 0; ob < NOB; ++ob) {
+    red2[w][g][ob * 16 + n16] = s1[ob];
+    red2[w][g][C + ob * 16 + n16] = s2[ob];
+  }
+  if (n16 == 0) red2[w][g][2 * C] = dbp;
+  __syncthreads();
+  const size_t blk = blockIdx.x;
+  if constexpr (TGT <= 1) {
+    for (int q = threadIdx.x; q < C * C; q += 256) {
+      acc_t sum = 0;
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) sum += red[ww][q];
+      ((acc_t*)a.pdW)[blk * C * C + q] = sum;
     }
   } else {
-    // lift: v_0 = W_L phi + b_L
-    if (valid) {
-      const double snorm = a.st[b].snorm;
-      const double inv_s = snorm > 0.0 ? 1.0 / snorm : 0.0;
-      sV[t][0] = (acc_t)(a.r[(size_t)b * n + p] * inv_s);
-      sV[t][1] = (acc_t)log(a.k[(size_t)b * (N + 2) * (N + 2) + (size_t)(x + 1) * (N + 2) + y + 1]);
-      sV[t][2] = (acc_t)((double)(x + 1) * hstep);
-      sV[t][3] = (acc_t)((double)(y + 1) * hstep);
-    } else {
-      sV[t][0] = sV[t][1] = sV[t][2] = sV[t][3] = (acc_t)0;
-    }
+    for (int q = threadIdx.x; q < C * 4; q += 256) {
+      acc_t sum = 0;
 #pragma unroll
-    for (int c = 0; c < C; ++c) sA[t][c] = valid ? dv[c] : (acc_t)0;
-    if (a.dphi0 && valid) {
-      // gradient w.r.t. the first feature r/s: W_L[:, 0]^T dv0
-      double d = 0.0;
+      for (int ww = 0; ww < NW; ++ww)
 #pragma unroll
-      for (int c = 0; c < C; ++c) d += blob[a.off_WL + c * 4] * (double)dv[c];
-      a.dphi0[(size_t)b * n + p] = d;
+        for (int gg = 0; gg < 4; ++gg) sum += red[ww][gg * C * 4 + q];
+      ((acc_t*)a.pdWL)[blk * C * 4 + q] = sum;
     }
-    __syncthreads();
-    for (int q = t; q < C * 4; q += PB) {
-      const int c = q / 4, f = q - c * 4;
-      acc_t s = 0;
-      for (int u = 0; u < PB; ++u) s += sA[u][c] * sV[u][f];
-      pdWL[(size_t)blockIdx.x * C * 4 + q] = s;
-    }
-    for (int c = t; c < C; c += PB) {
-      acc_t s = 0;
-      for (int u = 0; u < PB; ++u) s += sA[u][c];
-      pdbL[(size_t)blockIdx.x * C + c] = s;
+  }
+  for (int c = threadIdx.x; c < C; c += 256) {
+    acc_t u0 = 0, u1 = 0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww)
+#pragma unroll
+      for (int gg = 0; gg < 4; ++gg) {
+        u0 += red2[ww][gg][c];
+        u1 += red2[ww][gg][C + c];
+      }
+    ((acc_t*)(TGT <= 1 ? a.pdb : a.pdbL))[blk * C + c] = u0;
+    if constexpr (SRC == 0) ((acc_t*)a.pdWP)[blk * C + c] = u1;
+  }
+  if constexpr (SRC == 0) {
+    if (threadIdx.x == 0) {
+      acc_t u = 0;
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww)
+#pragma unroll
+        for (int gg = 0; gg < 4; ++gg) u += red2[ww][gg][2 * C];
+      ((acc_t*)a.pdbP)[blk] = u;
     }
   }
 }
@@ -548,17 +691,32 @@ void launch_loss(const LossArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_loss_fin, dim3(a.B), dim3(256), 0, s, a);
 }
 
-template <typename acc_t>
+template <int PREC, int C, int MP>
+static void bwd_t(const BwdArgs& a, int nblk, hipStream_t s) {
+  const int tl = a.mode == 0 ? a.L - 1 : a.l - 1;
+  const dim3 gr(nblk), bl(256);
+  if (a.mode == 0) {
+    if (tl >= 1) hipLaunchKernelGGL((k_bwd<PREC, C, MP, 0, 0>), gr, bl, 0, s, a);
+    else hipLaunchKernelGGL((k_bwd<PREC, C, MP, 0, 1>), gr, bl, 0, s, a);
+  } else {
+    if (tl >= 1) hipLaunchKernelGGL((k_bwd<PREC, C, MP, 1, 0>), gr, bl, 0, s, a);
+    else if (tl == 0) hipLaunchKernelGGL((k_bwd<PREC, C, MP, 1, 1>), gr, bl, 0, s, a);
+    else hipLaunchKernelGGL((k_bwd<PREC, C, MP, 1, 2>), gr, bl, 0, s, a);
+  }
+}
+
+template <int PREC>
 static void bwd_c(const BwdArgs& a, int C, int nblk, hipStream_t s) {
-  constexpr int PB = PtsPerBlock<acc_t>::value;
-  if (C == 16) hipLaunchKernelGGL((k_bwd<acc_t, 16>), dim3(nblk), dim3(PB), 0, s, a);
-  else hipLaunchKernelGGL((k_bwd<acc_t, 32>), dim3(nblk), dim3(PB), 0, s, a);
+  if (C == 16 && a.MP == 16) bwd_t<PREC, 16, 16>(a, nblk, s);
+  else if (C == 16) bwd_t<PREC, 16, 32>(a, nblk, s);
+  else if (a.MP == 16) bwd_t<PREC, 32, 16>(a, nblk, s);
+  else bwd_t<PREC, 32, 32>(a, nblk, s);
 }
 
 void launch_bwd(const BwdArgs& a, int prec, int C, int nblk, hipStream_t s) {
   ProfScope ps(PK_TRAIN_BWD, s);
-  if (prec == P64) bwd_c<double>(a, C, nblk, s);
-  else bwd_c<float>(a, C, nblk, s);
+  if (prec == P64) bwd_c<P64>(a, C, nblk, s);
+  else bwd_c<P32>(a, C, nblk, s);
 }
 
 void launch_bspec_mix(const BSpecArgs& a, int prec, int C, hipStream_t s) {

@@ -42,13 +42,14 @@ fcgno_status operator_backward(const fcgno_model* m, const Plan& p, char* base, 
   NL.S = p.Sb;
   const int asz = acc_esize(op);
   BwdArgs a{};
-  a.N = N; a.M = M; a.MP = MP; a.L = L; a.nbs = p.nbs; a.S = p.Sb;
+  a.N = N; a.M = M; a.MP = MP; a.L = L; a.nbs = p.nbs; a.S = p.Sb; a.B = B;
   a.st = (const SysState*)(base + p.state);
   a.gscale = gscale;
   a.dphi0 = grad_r ? (double*)(base + p.dvec) : nullptr;
   a.gw = gw;
   a.r = r;
   a.k = k;
+  a.logk = base + p.logk;
   a.z = base + p.z;
   a.z_sys = n * C;
   a.z_layer = (size_t)B * n * C;
