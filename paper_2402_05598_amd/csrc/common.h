@@ -267,7 +267,7 @@ struct SpecArgs {
   const double* E64;
   const void* R;     // [M][2M][C][C] complex, accumulate precision
   const void* WL0;   // [C] accumulate precision
-  void* Vsave;       // training: V^ of this layer, [sys][M][C][2M] complex (nullable)
+  void* Vsave;       // training: V^ of this layer, [M][2M][nsys][C] complex (nullable)
   size_t vs_sys;     // elements per system in Vsave
   int unit_scale;    // synthesis without the normalisation factor (backward pass)
   int basis;         // B_FOURIER or B_SINE (set from NOLaunch::basis)

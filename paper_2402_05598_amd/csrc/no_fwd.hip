@@ -468,9 +468,10 @@ __global__ __launch_bounds__(256) void k_spec_mix(SpecArgs a) {
     Vr[ch][kl] = vr;
     Vi[ch][kl] = vi;
     if (a.Vsave) {
-      acc_t* vs = (acc_t*)a.Vsave + a.vs_sys * blockIdx.z + (size_t)ky * C * twoM * 2;
-      vs[2 * (ch * twoM + kx)] = vr;
-      vs[2 * (ch * twoM + kx) + 1] = vi;
+      // mode-major, [ky][kx][system][c] complex (the weight gradient's operand)
+      acc_t* vs = (acc_t*)a.Vsave + ((((size_t)ky * twoM + kx) * a.nsys + blockIdx.z) * C + ch) * 2;
+      vs[0] = vr;
+      vs[1] = vi;
     }
   }
   __syncthreads();

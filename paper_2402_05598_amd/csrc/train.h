@@ -52,11 +52,11 @@ struct BSpecArgs {
   const void* Vp;      // [B] per-system chunk spectra (forward kernel output)
   size_t vp_sys;
   const void* R;       // [M][2M][C][C] complex, this layer
-  void* Gh;            // [B][M][C][2M] complex: G^ per system
+  void* Gh;            // [M][2M][B][C] complex: G^ of every system, mode-major
   size_t gh_sys;
   void* Wh;            // [B][M][C][MP] complex: G^_V for the synthesis
   size_t wh_sys;
-  const void* Vsave;   // [B][M][C][2M] complex: V^ of this layer
+  const void* Vsave;   // [M][2M][B][C] complex: V^ of this layer, mode-major
   size_t vs_sys;
   int basis;           // B_FOURIER or B_SINE
 };

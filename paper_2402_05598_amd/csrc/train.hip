@@ -476,7 +476,8 @@ __global__ __launch_bounds__(256) void k_bspec_mix(BSpecArgs a) {
   // adjoint of the synthesis normalisation: Fourier N^-2 g_ky, sine (2/(N+1))^2
   const acc_t sc = a.basis == B_SINE ? (acc_t)(4.0 / ((double)(a.N + 1) * (double)(a.N + 1)))
                                      : (acc_t)((ky == 0 ? 1.0 : 2.0) / ((double)a.N * (double)a.N));
-  acc_t* Gh = (acc_t*)a.Gh + (size_t)b * a.gh_sys + (size_t)ky * C * twoM * 2;
+  // G^ mode-major, [ky][a][system][o] complex, for the weight gradient's products
+  acc_t* Gh = (acc_t*)a.Gh + (size_t)ky * twoM * a.B * C * 2;
   for (int q = t; q < C * twoM; q += 256) {
     const int o = q / twoM, kx = q - o * twoM;
     acc_t gr = 0, gi = 0;
@@ -488,8 +489,9 @@ __global__ __launch_bounds__(256) void k_bspec_mix(BSpecArgs a) {
     gi *= sc;
     Gr_[o][kx] = gr;
     Gi_[o][kx] = gi;
-    Gh[2 * q] = gr;
-    Gh[2 * q + 1] = gi;
+    const size_t e = (((size_t)kx * a.B + b) * C + o) * 2;
+    Gh[e] = gr;
+    Gh[e + 1] = gi;
   }
   __syncthreads();
   // R layout [ky][a][c][o] complex
@@ -511,27 +513,84 @@ __global__ __launch_bounds__(256) void k_bspec_mix(BSpecArgs a) {
 }
 
 // dR[c][o][a][ky] = sum_b G^_b[o][a][ky] conj(V^_b[c][a][ky]), into the float64
-// gradient blob (Re block, then Im block).  Grid: (ky, a).
-template <typename acc_t, int C>
+// gradient blob (Re block, then Im block).  One block per mode (ky, a); per
+// mode a [C x B] by [B x C] complex product on the matrix cores (16x16x4,
+// accumulate precision) over the systems b, from the mode-major spectra
+// V^ and G^ ([ky][a][b][c] complex):
+//   Re = Vr^T Gr + Vi^T Gi,  Im = Vr^T Gi - Vi^T Gr.
+// The four waves split the (c, o) tiles and, at C = 16, the systems; the
+// split sums are added in a fixed order.
+template <int PREC, int C>
 __global__ __launch_bounds__(256) void k_dR(BSpecArgs a, double* grad_re, double* grad_im) {
+  using M_ = Mf<PREC>;
+  using acc_t = typename M_::acc_t;
+  using accv_t = typename M_::accv_t;
+  constexpr int NOB = C / 16, NT = NOB * NOB, NKS = 4 / NT, KB = 8;
+  __shared__ acc_t red[4][2][256];
   const int ky = blockIdx.x, kx = blockIdx.y;
-  const int M = a.M, twoM = 2 * M;
-  const int t = threadIdx.x;
-  for (int q = t; q < C * C; q += 256) {
-    const int c = q / C, o = q - c * C;
-    double sr = 0.0, si = 0.0;
-#pragma unroll 8
-    for (int b = 0; b < a.B; ++b) {
-      const acc_t* G = (const acc_t*)a.Gh + (size_t)b * a.gh_sys + (size_t)ky * C * twoM * 2;
-      const acc_t* V = (const acc_t*)a.Vsave + (size_t)b * a.vs_sys + (size_t)ky * C * twoM * 2;
-      const acc_t gr = G[2 * (o * twoM + kx)], gi = G[2 * (o * twoM + kx) + 1];
-      const acc_t vr = V[2 * (c * twoM + kx)], vi = V[2 * (c * twoM + kx) + 1];
-      sr += (double)(gr * vr + gi * vi);
-      si += (double)(gi * vr - gr * vi);
+  const int M = a.M, twoM = 2 * M, B = a.B;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, n16 = lane & 15, g = lane >> 4;
+  const int tile = w % NT, part = w / NT, cb = tile / NOB, ob = tile % NOB;
+  const size_t mode = ((size_t)ky * twoM + kx) * B * C * 2;
+  const acc_t* V = (const acc_t*)a.Vsave + mode + (size_t)(cb * 16 + n16) * 2;
+  const acc_t* G = (const acc_t*)a.Gh + mode + (size_t)(ob * 16 + n16) * 2;
+  // this wave's systems: [b0, b1) in K-steps of four (lane group g takes b + g)
+  const int per = (B + NKS - 1) / NKS;
+  const int b0 = part * per, b1 = min(B, b0 + per);
+  accv_t re = accv_t{0, 0, 0, 0}, im = accv_t{0, 0, 0, 0};
+  for (int bs = b0; bs < b1; bs += 4 * KB) {
+    // loads of KB K-steps before their products; systems past b1 read b0
+    // and are zeroed
+    acc_t vr[KB], vi[KB], gr[KB], gi[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const int b = bs + 4 * u + g;
+      const size_t o = (size_t)(b < b1 ? b : b0) * C * 2;
+      vr[u] = V[o];
+      vi[u] = V[o + 1];
+      gr[u] = G[o];
+      gi[u] = G[o + 1];
     }
+    // every load above is issued before the first product (the compiler
+    // would otherwise wait for each step's loads in turn)
+#pragma unroll
+    for (int u = 0; u < KB; ++u) asm volatile("" : "+v"(vr[u]), "+v"(vi[u]), "+v"(gr[u]), "+v"(gi[u]));
+#pragma unroll
+    for (int u = 0; u < KB; ++u) {
+      const bool ok = bs + 4 * u + g < b1;
+      const acc_t xr = ok ? vr[u] : (acc_t)0, xi = ok ? vi[u] : (acc_t)0;
+      re = M_::mma(xr, gr[u], re);
+      re = M_::mma(xi, gi[u], re);
+      im = M_::mma(xr, gi[u], im);
+      im = M_::mma(-xi, gr[u], im);
+    }
+  }
+  if constexpr (NKS > 1) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      red[w][0][i * 64 + lane] = re[i];
+      red[w][1][i * 64 + lane] = im[i];
+    }
+    __syncthreads();
+    if (part != 0) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      acc_t sr = 0, si = 0;
+      for (int pp = 0; pp < NKS; ++pp) {
+        sr += red[pp * NT + tile][0][i * 64 + lane];
+        si += red[pp * NT + tile][1][i * 64 + lane];
+      }
+      re[i] = sr;
+      im[i] = si;
+    }
+  }
+  // item i of lane (o, g): c = 16 cb + row(g, i), o = 16 ob + n
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = cb * 16 + M_::row(g, i), o = ob * 16 + n16;
     const size_t idx = (((size_t)c * C + o) * twoM + kx) * M + ky;
-    grad_re[idx] = sr;
-    grad_im[idx] = si;
+    grad_re[idx] = (double)re[i];
+    grad_im[idx] = (double)im[i];
   }
 }
 
@@ -733,11 +792,11 @@ void launch_bspec_mix(const BSpecArgs& a, int prec, int C, hipStream_t s) {
 void launch_dR(const BSpecArgs& a, int prec, int C, double* gre, double* gim, hipStream_t s) {
   const dim3 g(a.M, 2 * a.M);
   if (prec == P64) {
-    if (C == 16) hipLaunchKernelGGL((k_dR<double, 16>), g, dim3(256), 0, s, a, gre, gim);
-    else hipLaunchKernelGGL((k_dR<double, 32>), g, dim3(256), 0, s, a, gre, gim);
+    if (C == 16) hipLaunchKernelGGL((k_dR<P64, 16>), g, dim3(256), 0, s, a, gre, gim);
+    else hipLaunchKernelGGL((k_dR<P64, 32>), g, dim3(256), 0, s, a, gre, gim);
   } else {
-    if (C == 16) hipLaunchKernelGGL((k_dR<float, 16>), g, dim3(256), 0, s, a, gre, gim);
-    else hipLaunchKernelGGL((k_dR<float, 32>), g, dim3(256), 0, s, a, gre, gim);
+    if (C == 16) hipLaunchKernelGGL((k_dR<P32, 16>), g, dim3(256), 0, s, a, gre, gim);
+    else hipLaunchKernelGGL((k_dR<P32, 32>), g, dim3(256), 0, s, a, gre, gim);
   }
 }
 
