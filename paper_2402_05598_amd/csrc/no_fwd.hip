@@ -24,6 +24,8 @@
 
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "mfma.h"
 #include "prof.h"
@@ -1433,13 +1435,27 @@ void launch_no_setup(const NOLaunch& L, double* scratch) {
   else setup_p<PBF>(L, scratch);
 }
 
+// With the layer family's timing on, the launch carries its own event pair
+// (hipExtLaunchKernelGGL) rather than events recorded around it.
+template <int PREC, int C, int MP, bool FEAT, bool PROJ>
+static void layer_launch(const NOLaunch& L, const LayerArgs& la, int pk) {
+  const dim3 grid((L.N * ((L.S + L.spw - 1) / L.spw) + 3) / 4, L.nsys);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (prof_kernel_events(pk, &e0, &e1)) {
+    hipExtLaunchKernelGGL((k_layer<PREC, C, MP, FEAT, PROJ>), grid, dim3(256), 0, L.stream, e0, e1, 0, la);
+    prof_kernel_done(pk, e0, e1);
+  } else {
+    hipLaunchKernelGGL((k_layer<PREC, C, MP, FEAT, PROJ>), grid, dim3(256), 0, L.stream, la);
+  }
+}
+
 template <int PREC, int C, int MP>
 static void layer_dispatch(const NOLaunch& L, const LayerArgs& la, bool feat, bool proj) {
-  const dim3 grid((L.N * ((L.S + L.spw - 1) / L.spw) + 3) / 4, L.nsys);
-  if (feat && proj) hipLaunchKernelGGL((k_layer<PREC, C, MP, true, true>), grid, dim3(256), 0, L.stream, la);
-  else if (feat) hipLaunchKernelGGL((k_layer<PREC, C, MP, true, false>), grid, dim3(256), 0, L.stream, la);
-  else if (proj) hipLaunchKernelGGL((k_layer<PREC, C, MP, false, true>), grid, dim3(256), 0, L.stream, la);
-  else hipLaunchKernelGGL((k_layer<PREC, C, MP, false, false>), grid, dim3(256), 0, L.stream, la);
+  const int pk = feat ? PK_LAYER_FEAT : (proj ? PK_LAYER_PROJ : PK_LAYER);
+  if (feat && proj) layer_launch<PREC, C, MP, true, true>(L, la, pk);
+  else if (feat) layer_launch<PREC, C, MP, true, false>(L, la, pk);
+  else if (proj) layer_launch<PREC, C, MP, false, true>(L, la, pk);
+  else layer_launch<PREC, C, MP, false, false>(L, la, pk);
 }
 
 template <int PREC, int C>
@@ -1526,7 +1542,6 @@ static void apply_pc(const NOLaunch& L) {
     LayerArgs la{L.sys, L.N, L.S, 2 * L.M, sin, sout, L.tab.T, L.tab.TT, L.Wfrag[l], L.bias[l], L.WP, L.bP,
                  L.zsave ? (char*)L.zsave + L.z_layer * l * L.op_bytes : nullptr, L.z_sys, L.spw};
     const bool feat = l == 0, proj = l == L.L - 1;
-    ProfScope ps(feat ? PK_LAYER_FEAT : (proj ? PK_LAYER_PROJ : PK_LAYER), L.stream);
     if (L.MP == 16) layer_dispatch<PREC, C, 16>(L, la, feat, proj);
     else layer_dispatch<PREC, C, 32>(L, la, feat, proj);
   }

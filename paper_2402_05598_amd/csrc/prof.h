@@ -15,6 +15,10 @@ void prof_begin(int kernel, hipStream_t s);
 void prof_end(int kernel, hipStream_t s);
 // Accumulate the durations of completed event pairs (call after a stream sync).
 void prof_collect();
+// Event pair for a launch that carries its own events
+// (hipExtLaunchKernelGGL).  False (no events) when the family is off.
+bool prof_kernel_events(int kernel, hipEvent_t* start, hipEvent_t* stop);
+void prof_kernel_done(int kernel, hipEvent_t start, hipEvent_t stop);
 
 struct ProfScope {
   int k;

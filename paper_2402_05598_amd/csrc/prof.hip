@@ -47,6 +47,22 @@ void prof_end(int k, hipStream_t s) {
   g_open[k] = nullptr;
 }
 
+bool prof_kernel_events(int k, hipEvent_t* a, hipEvent_t* b) {
+  if (!prof_on(k)) return false;
+  std::lock_guard<std::mutex> lk(g_mu);
+  *a = take_event();
+  *b = take_event();
+  if (*a && *b) return true;
+  if (*a) g_pool.push_back(*a);
+  if (*b) g_pool.push_back(*b);
+  return false;
+}
+
+void prof_kernel_done(int k, hipEvent_t a, hipEvent_t b) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_pending.push_back({k, a, b});
+}
+
 void prof_collect() {
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto& p : g_pending) {
