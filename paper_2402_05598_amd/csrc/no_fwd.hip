@@ -1063,7 +1063,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
   frag_t Bf[KT + KIN][NOB];
   const in_t* Hc = (const in_t*)sd.Hc + (size_t)x * C * MP;
   const in_t* Wf = (const in_t*)a.Wf;
-  acc_t bias[NOB], wp[NOB];
+  // bias and projection weights by accumulator item: the projection layer
+  // computes its product transposed (item i of lane (n, g) holds channel
+  // 16 ob + row(g, i) of point y0 + n), the others item-independent
+  acc_t bias[NOB][4], wp[NOB][4];
 #pragma unroll
   for (int ob = 0; ob < NOB; ++ob) {
     const int o = ob * 16 + n16;
@@ -1071,8 +1074,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
     for (int ks = 0; ks < KT; ++ks) Bf[ks][ob] = M_::ld(Hc + o * MP + ks * KSTEP + g * KPL);
 #pragma unroll
     for (int ks = 0; ks < KIN; ++ks) Bf[KT + ks][ob] = M_::ld(Wf + o * KWP + ks * KSTEP + g * KPL);
-    bias[ob] = ((const acc_t*)a.bias)[o];
-    wp[ob] = PROJ ? ((const acc_t*)a.WP)[o] : (acc_t)0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int oi = PROJ ? ob * 16 + M_::row(g, i) : o;
+      bias[ob][i] = ((const acc_t*)a.bias)[oi];
+      wp[ob][i] = PROJ ? ((const acc_t*)a.WP)[oi] : (acc_t)0;
+    }
   }
   accv_t G2[MB][NOB];
 #pragma unroll
@@ -1211,15 +1218,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
     accv_t acc[NOB];
 #pragma unroll
     for (int ob = 0; ob < NOB; ++ob) {
-      acc[ob] = accv_t{bias[ob], bias[ob], bias[ob], bias[ob]};
-      // twiddle columns past 2M are zero in T and Hc, so every K-step runs
+      acc[ob] = accv_t{bias[ob][0], bias[ob][1], bias[ob][2], bias[ob][3]};
+      // twiddle columns past 2M are zero in T and Hc, so every K-step runs.
+      // The projection layer swaps the operands: the A-operand layout of
+      // [T | v] is the B-operand layout of its transpose, so z^T comes out
+      // with the point along the lane and its channels along the items.
 #pragma unroll
-      for (int ks = 0; ks < KT; ++ks) acc[ob] = M_::mma(Af[ks], Bf[ks][ob], acc[ob]);
-#pragma unroll
-      for (int ks = 0; ks < KIN; ++ks) acc[ob] = M_::mma(Af[KT + ks], Bf[KT + ks][ob], acc[ob]);
+      for (int ks = 0; ks < KT + KIN; ++ks)
+        acc[ob] = PROJ ? M_::mma(Bf[ks][ob], Af[ks], acc[ob]) : M_::mma(Af[ks], Bf[ks][ob], acc[ob]);
     }
     if constexpr (RELOAD) load_a(tn, cur, full_t{});
-    // lane holds z[y0 + row(g, i)][ob*16 + n16]
+    // lane holds z[y0 + row(g, i)][ob*16 + n16] (projection: z[y0 + n16][ob*16 + row(g, i)])
     if (a.zout) {
       // training: keep the pre-activation (same LDS transpose as the activations)
       in_t* ot = otile[threadIdx.x >> 6];
@@ -1227,7 +1236,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
       for (int ob = 0; ob < NOB; ++ob)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          ot[M_::row(g, i) * (C + PADE) + ob * 16 + n16] = M_::cvt(acc[ob][i]);
+          if constexpr (PROJ) ot[n16 * (C + PADE) + ob * 16 + M_::row(g, i)] = M_::cvt(acc[ob][i]);
+          else ot[M_::row(g, i) * (C + PADE) + ob * 16 + n16] = M_::cvt(acc[ob][i]);
           // float32, width 16: the compiler merges these four stores into a
           // paired LDS store with a wrong offset for the second row (seen in
           // the generated assembly); a compiler barrier keeps them apart
@@ -1247,18 +1257,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
       asm volatile("" ::: "memory");
     }
     if constexpr (PROJ) {
+      // w[y] = sum_o W_P[o] GELU(z[y][o]): this lane's channels, then the
+      // four lane groups of point y0 + n16
+      acc_t part = 0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int yv = y0 + M_::row(g, i);
-        acc_t part = 0;
+      for (int ob = 0; ob < NOB; ++ob)
 #pragma unroll
-        for (int ob = 0; ob < NOB; ++ob) part += wp[ob] * act<PREC>(acc[ob][i]);
-        part += __shfl_xor(part, 1, 64);
-        part += __shfl_xor(part, 2, 64);
-        part += __shfl_xor(part, 4, 64);
-        part += __shfl_xor(part, 8, 64);
-        if (n16 == i && (FULL || yv < N)) sd.w[(size_t)x * N + yv] = snorm * ((double)part + bP);
-      }
+        for (int i = 0; i < 4; ++i) part += wp[ob][i] * act<PREC>(acc[ob][i]);
+      part += __shfl_xor(part, 16, 64);
+      part += __shfl_xor(part, 32, 64);
+      if (g == 0 && va) sd.w[(size_t)x * N + ya] = snorm * ((double)part + bP);
     } else {
       // v' = GELU(z) rounded once to the op precision; rows past N are zero
       in_t hv[NOB][4];
