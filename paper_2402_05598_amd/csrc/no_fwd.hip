@@ -1086,6 +1086,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
   for (int jb = 0; jb < MB; ++jb)
 #pragma unroll
     for (int ob = 0; ob < NOB; ++ob) G2[jb][ob] = accv_t{0, 0, 0, 0};
+  // bfloat16: a wave that holds every segment of its row (spw >= S) adds the
+  // segment partials itself, from zero and in segment order as the x
+  // transform would, and writes the one sum (the x transform then reads a
+  // single segment): half the partial-spectrum traffic, the same bits
+  const bool whole = PREC == PBF && ngrp == 1 && a.S > 1;
+  accv_t Gs[PREC == PBF ? MB : 1][NOB];
 
   const in_t* T = (const in_t*)a.T;
   const in_t* TT = (const in_t*)a.TT;
@@ -1336,18 +1342,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
     if constexpr (!PROJ) {
       if ((t + 1) % TPW == 0 || t + 1 == T1) {
         if constexpr (PREC == PBF) {
+          const int seg = t / TPW;
+          if (whole) {
+#pragma unroll
+            for (int jb = 0; jb < MB; ++jb)
+#pragma unroll
+              for (int ob = 0; ob < NOB; ++ob) {
+                Gs[jb][ob] = (seg == 0 ? accv_t{0, 0, 0, 0} : Gs[jb][ob]) + G2[jb][ob];
+                G2[jb][ob] = accv_t{0, 0, 0, 0};
+              }
+            if (t + 1 != T1) return;
+          }
           // lane holds j = 16 jb + 4 g + i, i.e. mode 8 jb + 2 g + i / 2, part i % 2
           float* Gp = (float*)sd.Gp;
 #pragma unroll
           for (int jb = 0; jb < MB; ++jb)
 #pragma unroll
             for (int ob = 0; ob < NOB; ++ob) {
+              const accv_t v = whole ? Gs[jb][ob] : G2[jb][ob];
 #pragma unroll
               for (int ip = 0; ip < 2; ++ip) {
                 const int ky = 8 * jb + 2 * g + ip;
                 if (2 * ky < twoM)
-                  *(float2*)(Gp + gp_index(N, a.S, C, ky, x, t / TPW, ob * 16 + n16)) =
-                      float2{G2[jb][ob][2 * ip], G2[jb][ob][2 * ip + 1]};
+                  *(float2*)(Gp + gp_index(N, whole ? 1 : a.S, C, ky, x, whole ? 0 : seg, ob * 16 + n16)) =
+                      float2{v[2 * ip], v[2 * ip + 1]};
               }
               G2[jb][ob] = accv_t{0, 0, 0, 0};
             }
@@ -1504,15 +1522,19 @@ static void apply_pc(const NOLaunch& L) {
     SpecArgs sa{L.sys, L.N, L.S, L.M, l == 0 ? 1 : 0, XS, L.nsys, L.tab.Eacc, L.tab.E64, L.Rmix[l], L.WL0,
                 L.vsave ? (char*)L.vsave + L.vs_layer * l * L.acc_bytes : nullptr, L.vs_sys, 0, L.basis};
     if constexpr (PREC == PBF) {
-      // matrix-core x transforms (inference only: training runs FP32/FP64)
+      // matrix-core x transforms (inference only: training runs FP32/FP64).
+      // With spw >= S the layer kernel wrote each row's segment partials
+      // already summed, as one segment.
       ProfScope ps(PK_SPECTRAL, L.stream);
-      if (L.S == 1)
+      const int Sx = L.spw >= L.S ? 1 : L.S;
+      sa.S = Sx;
+      if (Sx == 1)
         hipLaunchKernelGGL((k_xfm_bf<C, 1>), dim3(L.M, (2 * L.M + 15) / 16, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
                            (const __bf16*)L.tab.FA);
-      else if (L.S == 2)
+      else if (Sx == 2)
         hipLaunchKernelGGL((k_xfm_bf<C, 2>), dim3(L.M, (2 * L.M + 15) / 16, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
                            (const __bf16*)L.tab.FA);
-      else if (L.S == 4)
+      else if (Sx == 4)
         hipLaunchKernelGGL((k_xfm_bf<C, 4>), dim3(L.M, (2 * L.M + 15) / 16, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
                            (const __bf16*)L.tab.FA);
       else

@@ -41,6 +41,7 @@ def weights():
 @pytest.mark.parametrize("N,B,ops,sample", [(512, 16, ("fp64", "fp32", "bf16"), (0, 15)),
                                             (128, 64, ("fp32",), (0, 37, 63)),
                                             (256, 64, ("fp32",), (5, 63)),
+                                            (300, 5, ("bf16",), (0, 4)),
                                             (520, 2, ("fp64", "fp32", "bf16"), (0, 1)),
                                             (1024, 2, ("fp64", "fp32", "bf16"), (0, 1))])
 def test_operator_full_size_sampled(dev, weights, N, B, ops, sample):
@@ -120,4 +121,28 @@ def test_fcg_1024_first_iterations(dev, weights):
     print(f"  1024 fcg fp64: rel hist diff {rel:.2e}, max increment diff {mx:.2e}", flush=True)
     assert rel < 1e-10
     assert mx < 1e-9
+    model.close()
+
+
+def test_bf16_whole_row_partials_ragged(dev, weights):
+    """300x300 (two row segments, the second ragged): with more than four
+    active systems a wave takes both segments of its row and writes their
+    partial spectra already summed; alone, each segment is written apart and
+    the x transform sums them.  The same sums in the same order, so a system
+    solved alone equals the same system inside the batch, bit for bit."""
+    N, B, its = 300, 5, 6
+    wb, w = weights
+    k, f, u0, _ = synth.batch(3, B, N, (10.0, 1000.0))
+    model = fc.Model(wb, C, M, L)
+    kd, fd = torch.from_numpy(k).to(dev), torch.from_numpy(f).to(dev)
+    u = torch.from_numpy(u0).to(dev)
+    out = fc.solve(model, kd, fd, u, op="bf16", m_max=5, max_iter=its, rtol=1e-300, check_every=4)
+    assert np.all(out["iters"] == its)
+    for b in (1, 4):
+        u1 = torch.from_numpy(u0[b:b + 1]).to(dev)
+        one = fc.solve(model, kd[b:b + 1].contiguous(), fd[b:b + 1].contiguous(), u1, op="bf16", m_max=5,
+                       max_iter=its, rtol=1e-300, check_every=4)
+        print(f"  N={N} b={b} alone vs batch: hist {one['hist'][0][its]:.6e} / {out['hist'][b][its]:.6e}", flush=True)
+        assert np.array_equal(one["hist"][0], out["hist"][b])
+        assert torch.equal(u1[0], u[b])
     model.close()
