@@ -777,7 +777,10 @@ def main():
     # (L - 2) * sum(iters) active system-launches over the timed solves.
     esize = {"bf16": 2, "fp32": 4, "fp64": 8}[main_op]
     asize = 8 if main_op == "fp64" else 4
-    S = ((N + 15) // 16 + 15) // 16   # row segments of 16 tiles (seg_count)
+    # one partial spectrum per row: the bytes the layer's job needs (a wave
+    # that holds a whole row writes just that; the tail's one-segment-per-wave
+    # launches write a partial per segment, which counts as overhead here)
+    S = 1
     per_sys = layer_bytes_per_launch(N, 1, C, M, esize, asize, S)
     n_l, ms_l = prof["layer"]
     sys_launches = (L - 2) * int(R["iters"].sum())

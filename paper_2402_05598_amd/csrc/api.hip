@@ -211,11 +211,13 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
     p.Eacc = cv.take((size_t)tw_period(m->arch.basis, N) * 2 * asz);
     p.T = cv.take((size_t)NP * MP * esz);
     p.TT = cv.take((size_t)MP * NP * esz);
+    p.RD = cv.take((size_t)NP * 32 * 8);
     if (op == PBF) {
       // matrix-core x transforms: split-bfloat16 twiddle operands and the
       // synthesis operand of each system (see the bfloat16 spectral kernels)
       p.FA = cv.take((size_t)2 * 32 * 2 * NP * 2);
       p.SA = cv.take((size_t)2 * NP * 64 * 2);
+      p.EX = cv.take((size_t)NP * 32 * 8);
       p.wt_bytes_per_sys = (size_t)2 * C * M * 64 * 2;
       p.WT = cv.take((size_t)B * p.wt_bytes_per_sys);
     }
@@ -288,6 +290,8 @@ NOLaunch make_no(const fcgno_model* m, const Plan& p, char* base, const SysDev* 
   L.tab.TT = base + p.TT;
   L.tab.FA = op == PBF ? base + p.FA : nullptr;
   L.tab.SA = op == PBF ? base + p.SA : nullptr;
+  L.tab.RD = (const double*)(base + p.RD);
+  L.tab.EX = op == PBF ? base + p.EX : nullptr;
   L.Wfrag = m->Wfrag[op].data();
   L.bias = m->bias[op].data();
   L.Rmix = m->Rmix[op].data();
@@ -307,8 +311,9 @@ fcgno_status operator_setup(const fcgno_model* m, const Plan& p, char* base, con
                             int op, hipStream_t s) {
   launch_zero(base + p.Hc, (size_t)B * N * m->arch.width * p.MP * op_esize(op), s);
   launch_zero(base + p.Wh, (size_t)B * p.wh_bytes_per_sys, s);
-  launch_tables(NL, (double*)(base + p.E64), base + p.Eacc, base + p.T, base + p.TT,
-                op == PBF ? base + p.FA : nullptr, op == PBF ? base + p.SA : nullptr);
+  launch_tables(NL, (double*)(base + p.E64), base + p.Eacc, base + p.T, base + p.TT, (double*)(base + p.RD),
+                op == PBF ? base + p.FA : nullptr, op == PBF ? base + p.SA : nullptr,
+                op == PBF ? base + p.EX : nullptr);
   launch_no_setup(NL, (double*)(base + p.Gp));
   return FCGNO_OK;
 }

@@ -119,6 +119,13 @@ struct Tables {
   // operands, each value split into a bfloat16 pair hi + lo
   const void* FA;     // [2][32][2 NP] forward: FA[h][a][2x] = cos, FA[h][a][2x+1] = -sin
   const void* SA;     // [2][NP][64]   synthesis: SA[h][x][2a] = cos, SA[h][x][2a+1] = -sin
+  // float64 twiddles of the row transform of r, as the B operand of its
+  // 16x16x4 products: RD[(s * 2 + cb) * 64 + 16 g + n] = T(4 s + g, 16 cb + n)
+  // (T as above, zero for y >= N and columns >= 2M); NP / 4 steps of 4 rows
+  const double* RD;
+  // bfloat16 operator: the first layer's x transform, EX[x][a] = (cos, -sin)
+  // of kept x-mode a at row x in float32 (zero for a >= 2M or x >= N), [NP][32]
+  const void* EX;
 };
 
 __device__ __forceinline__ int window_size(int i, int m_max) {
@@ -271,11 +278,12 @@ struct SpecArgs {
   size_t vs_sys;     // elements per system in Vsave
   int unit_scale;    // synthesis without the normalisation factor (backward pass)
   int basis;         // B_FOURIER or B_SINE (set from NOLaunch::basis)
+  const void* EX = nullptr;   // bfloat16 first layer: Tables::EX
 };
 
-// FA, SA: bfloat16 operator only (nullptr otherwise)
-void launch_tables(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT, void* FA = nullptr,
-                   void* SA = nullptr);
+// FA, SA, EX: bfloat16 operator only (nullptr otherwise); RD: every operator
+void launch_tables(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT, double* RD, void* FA = nullptr,
+                   void* SA = nullptr, void* EX = nullptr);
 // single stages of the spectral part (used by the backward pass)
 void launch_spec_fwd(const NOLaunch& L, const SpecArgs& a);
 void launch_spec_inv(const NOLaunch& L, const SpecArgs& a);

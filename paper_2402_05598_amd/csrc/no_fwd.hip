@@ -182,13 +182,12 @@ __global__ __launch_bounds__(256) void k_rowdft(const SysDev* sys, int N, int M,
 // in 16x16x4 steps) and the eight partial tiles are added through LDS in a
 // fixed order, so a system's result does not depend on the batch.  A wave
 // issues all loads of a 64-point chunk of y before its products, since the
-// launch is too small to hide memory latency by occupancy.  T is not read from
-// a table: each lane walks its two columns' twiddle index along y (index of
-// harmonic q at y: q y mod N, sine (q+1)(y+1) mod (2N+2)) and gathers from
-// E64, which stays in L1.
+// launch is too small to hide memory latency by occupancy.  The B operands
+// come from RD, stored in the products' fragment order: one contiguous 512-byte
+// read per step and column tile (a gather from E64 would cost a cache access
+// per lane).
 constexpr int RD_WAVES = 8;   // the combine below adds eight partials; 512 threads = 16 rows x 32 columns
-__global__ __launch_bounds__(64 * RD_WAVES) void k_rowdft_r(const SysDev* sys, int N, int M, int basis,
-                                                            const double* E64) {
+__global__ __launch_bounds__(64 * RD_WAVES) void k_rowdft_r(const SysDev* sys, int N, int M, const double* RD) {
   __shared__ double part[RD_WAVES][16][33];
   const SysDev sd = sys[blockIdx.y];
   if (!sd.st->active) return;
@@ -201,22 +200,8 @@ __global__ __launch_bounds__(64 * RD_WAVES) void k_rowdft_r(const SysDev* sys, i
   const int xr = x0 + n16;
   const bool rowok = xr < N;
   const double* rrow = sd.r + (size_t)(rowok ? xr : 0) * N;
-  const bool sine = basis == B_SINE;
-  const unsigned P = (unsigned)tw_period(basis, N);
-  // this lane's two B columns k = cb*16 + n16: harmonic q = k/2, cosine or sine
-  unsigned idx[2], step[2];
-  int off[2];
-  bool keep[2];
-#pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
-    const int k = cb * 16 + n16, q = k >> 1;
-    const unsigned qq = (unsigned)(sine ? q + 1 : q);
-    const unsigned y0 = (unsigned)(sine ? ybeg + g + 1 : ybeg + g);
-    idx[cb] = (qq * y0) % P;
-    step[cb] = (4u * qq) % P;
-    off[cb] = sine ? 0 : (k & 1);
-    keep[cb] = k < 2 * M && !(sine && (k & 1));
-  }
+  const int last = (round16(N) >> 2) - 1;   // last step of RD
+  const double* RDl = RD + lane;
   double4_t acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
   constexpr int CH = 16;   // steps of 4 points per chunk
   for (int yc = ybeg; yc < yend; yc += 4 * CH) {
@@ -225,12 +210,10 @@ __global__ __launch_bounds__(64 * RD_WAVES) void k_rowdft_r(const SysDev* sys, i
     for (int s = 0; s < CH; ++s) {
       const int y = yc + 4 * s + g;
       av[s] = (rowok && y < yend) ? rrow[y] : 0.0;
+      // steps past the table (points past N, whose r is zero above) read its last step
+      const int st = min((yc >> 2) + s, last);
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        bv[s][cb] = keep[cb] ? E64[2 * idx[cb] + off[cb]] : 0.0;
-        idx[cb] += step[cb];
-        if (idx[cb] >= P) idx[cb] -= P;
-      }
+      for (int cb = 0; cb < 2; ++cb) bv[s][cb] = RDl[(size_t)(st * 2 + cb) * 64];
     }
 #pragma unroll
     for (int s = 0; s < CH; ++s)
@@ -659,6 +642,40 @@ __global__ __launch_bounds__(256) void k_tables_bfx(int N, int M, int basis, con
   SA[(size_t)ns * 1024 + sa] = lo;
 }
 
+// Gather-free twiddles, copied from E64 / Eacc (the same values the index
+// walks over those tables would fetch):
+//   RD (every operator): the row transform of r, entry (s, cb, 16 g + n) =
+//       T(4 s + g, 16 cb + n), the B operand of step s, column tile cb
+//   EX (bfloat16 operator): the first layer's x transform, EX[x][a] =
+//       (Eacc cos, -Eacc sin) at tw_index(a, x)
+__global__ __launch_bounds__(256) void k_tables_rx(int N, int M, int basis, const double* E64, const float* Eacc,
+                                                  double* RD, float2* EX) {
+  const int NP = round16(N);
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= NP * 32) return;
+  {
+    const int st = q >> 7, cb = (q >> 6) & 1, n = q & 15, g = (q >> 4) & 3;
+    const int y = 4 * st + g, k = cb * 16 + n, h = k >> 1;
+    const bool sine = basis == B_SINE;
+    double v = 0.0;
+    if (y < N && k < 2 * M && !(sine && (k & 1))) {
+      const unsigned P = (unsigned)tw_period(basis, N);
+      const unsigned idx = sine ? ((unsigned)(h + 1) * (unsigned)(y + 1)) % P : ((unsigned)h * (unsigned)y) % P;
+      v = E64[2 * idx + (sine ? 0 : (k & 1))];
+    }
+    RD[q] = v;
+  }
+  if (EX) {
+    const int x = q >> 5, a = q & 31;
+    float2 e = {0.f, 0.f};
+    if (x < N && a < 2 * M) {
+      const unsigned idx = tw_index(basis, N, M, a, x);
+      e = float2{Eacc[2 * idx], -Eacc[2 * idx + 1]};
+    }
+    EX[q] = e;
+  }
+}
+
 // Synthesis operand WT[h] of the mixed spectrum, value (j = o M + ky,
 // column 2a + t) in the fragment order of the synthesis product: lane
 // (n, g) of column tile jt and step ks holds j = 16 jt + n, column 32 ks +
@@ -686,24 +703,28 @@ __device__ __forceinline__ size_t gp_index(int N, int S, int C, int ky, int x, i
 // r's row partials instead and adds the per-solve constant part.
 // SEG: the row-segment count a.S as a compile-time constant (1, 2 or 4, so
 // that the loads of every segment issue together), or 0 for any count.
+// KGN: groups of 16 modes per block, 1 or 2 (two: the block reads its rows
+// once for both groups; used while many systems fill the chip, the same
+// sums either way).
 constexpr int XFM_THREADS = 512;
-template <int C, int SEG>
+template <int C, int SEG, int KGN>
 __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16* FA) {
   constexpr int NW = XFM_THREADS / 64, NCT = C / 16, SPW = SEG == 4 ? 2 : 4;
   constexpr int SEG0 = SEG > 0 ? SEG : 1;   // segments summed in the first pass
-  __shared__ float red[NW][4][256];   // [wave][(re/im, ct)][element]
-  __shared__ float Vr_[C][17], Vi_[C][17];
-  const int ky = blockIdx.x, kg = blockIdx.y;   // modes a = 16 kg .. 16 kg + 15
+  constexpr int NK = 16 * KGN;              // modes of the block
+  __shared__ float red[NW][KGN * 2 * NCT][256];   // [wave][(group, re/im, ct)][element]
+  __shared__ float Vr_[C][NK + 1], Vi_[C][NK + 1];
+  const int ky = blockIdx.x, kg = blockIdx.y * KGN;   // modes a = 16 kg .. 16 kg + NK - 1
   const SysDev sd = a.sys[blockIdx.z];
   if (!sd.st->active) return;
   const int N = a.N, M = a.M, twoM = 2 * M, MP = round16(twoM), NP = round16(N);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, n16 = lane & 15, g = lane >> 4;
   const int nkt = (twoM + 15) >> 4;
-  if (a.layer0) {
+  if (KGN == 1 && a.layer0) {
     // S[a] = sum_x (Gr - i Gi)[x] e^{-i theta}, float32, 32 row parts per mode
     constexpr int XR = XFM_THREADS / 16, CHR = 8;
     __shared__ float pr_[XR][17], pi_[XR][17];
-    const float* E = (const float*)a.Eacc;
+    const float2* EX = (const float2*)a.EX;   // [NP][32]: 16 modes of a row in 128 contiguous bytes
     const int kl = t & 15, ka = kg * 16 + kl, part = t >> 4;
     float sr = 0.f, si = 0.f;
     if (ka < twoM) {
@@ -720,9 +741,9 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
           const int xc = x < N ? x : 0;
           g0[e] = sd.Gr[(size_t)xc * MP + 2 * ky];
           g1[e] = sd.Gr[(size_t)xc * MP + 2 * ky + 1];
-          const unsigned idx = tw_index(a.basis, N, M, ka, xc);
-          er[e] = E[2 * idx];
-          ei[e] = -E[2 * idx + 1];
+          const float2 ex = EX[(size_t)xc * 32 + ka];
+          er[e] = ex.x;
+          ei[e] = ex.y;
         }
 #pragma unroll
         for (int e = 0; e < CHR; ++e) {
@@ -757,18 +778,20 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
     const int ns = NP >> 4;
     const __bf16* FAh = FA + ((size_t)kg * ns * 64 + lane) * 8;
     const __bf16* FAl = FAh + (size_t)2 * ns * 512;
-    float4_t acc[2][NCT];
+    float4_t acc[KGN][2][NCT];
 #pragma unroll
-    for (int ri = 0; ri < 2; ++ri)
+    for (int kq = 0; kq < KGN; ++kq)
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) acc[ri][ct] = float4_t{0.f, 0.f, 0.f, 0.f};
+      for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[kq][ri][ct] = float4_t{0.f, 0.f, 0.f, 0.f};
     const int nsteps = NP >> 4;
     for (int s0 = w; s0 < nsteps; s0 += NW * SPW) {
       // loads of up to SPW steps (s0, s0 + NW, ...) before any product: the
       // first SEG0 segments of every (step, channel, row, Gc/Gs); rows past
       // N and dead steps read row 0 and are zeroed after
       float raw[SPW][NCT][8][SEG0];
-      bf16x8_t ah[SPW], al[SPW];
+      bf16x8_t ah[SPW][KGN], al[SPW][KGN];
 #pragma unroll
       for (int u = 0; u < SPW; ++u) {
         const int st = s0 + u * NW;
@@ -788,15 +811,19 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
             }
           }
         }
-        ah[u] = *(const bf16x8_t*)(FAh + (size_t)stc * 512);
-        al[u] = *(const bf16x8_t*)(FAl + (size_t)stc * 512);
+#pragma unroll
+        for (int kq = 0; kq < KGN; ++kq) {
+          ah[u][kq] = *(const bf16x8_t*)(FAh + ((size_t)kq * ns + stc) * 512);
+          al[u][kq] = *(const bf16x8_t*)(FAl + ((size_t)kq * ns + stc) * 512);
+        }
       }
       // every load above completes here, before any sum or product (the
       // compiler would otherwise issue each step's loads after the previous
       // step's products, one round trip per step)
 #pragma unroll
       for (int u = 0; u < SPW; ++u) {
-        asm volatile("" : "+v"(ah[u]), "+v"(al[u]));
+#pragma unroll
+        for (int kq = 0; kq < KGN; ++kq) asm volatile("" : "+v"(ah[u][kq]), "+v"(al[u][kq]));
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
@@ -850,31 +877,36 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
             bh[ct][e] = h;
             bl[ct][e] = l;
           }
-        const bf16x8_t aih = pairs_fwd(ah[u]), ail = pairs_fwd(al[u]);
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-          acc[0][ct] = mfma_bf3(ah[u], al[u], bh[ct], bl[ct], acc[0][ct]);
-          acc[1][ct] = mfma_bf3(aih, ail, bh[ct], bl[ct], acc[1][ct]);
+        for (int kq = 0; kq < KGN; ++kq) {
+          const bf16x8_t aih = pairs_fwd(ah[u][kq]), ail = pairs_fwd(al[u][kq]);
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) {
+            acc[kq][0][ct] = mfma_bf3(ah[u][kq], al[u][kq], bh[ct], bl[ct], acc[kq][0][ct]);
+            acc[kq][1][ct] = mfma_bf3(aih, ail, bh[ct], bl[ct], acc[kq][1][ct]);
+          }
         }
       }
     }
     // partial tiles -> LDS; element index i * 64 + lane (row 4 g + i, column n16)
 #pragma unroll
-    for (int ri = 0; ri < 2; ++ri)
+    for (int kq = 0; kq < KGN; ++kq)
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct)
+      for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) red[w][ri * NCT + ct][i * 64 + lane] = acc[ri][ct][i];
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) red[w][(kq * 2 + ri) * NCT + ct][i * 64 + lane] = acc[kq][ri][ct][i];
     __syncthreads();
     // fixed-order sum over the waves, then V^[c][a] of this block's modes
-    for (int q = t; q < 2 * NCT * 256; q += XFM_THREADS) {
+    for (int q = t; q < KGN * 2 * NCT * 256; q += XFM_THREADS) {
       const int tile = q >> 8, el = q & 255;
       float v = 0.f;
 #pragma unroll
       for (int ww = 0; ww < NW; ++ww) v += red[ww][tile][el];
-      const int ct = tile % NCT, ri = tile / NCT;
+      const int ct = tile % NCT, ri = (tile / NCT) & 1, kq = tile / (2 * NCT);
       const int i = el >> 6, ln = el & 63;
-      const int k2 = 4 * (ln >> 4) + i, c = ct * 16 + (ln & 15);
+      const int k2 = kq * 16 + 4 * (ln >> 4) + i, c = ct * 16 + (ln & 15);
       if (ri == 0) Vr_[c][k2] = v;
       else Vi_[c][k2] = v;
     }
@@ -884,8 +916,8 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
   const float* Rk0 = (const float*)a.R + (size_t)ky * twoM * C * C * 2;
   __bf16* WTh = (__bf16*)sd.WT;
   __bf16* WTl = WTh + (size_t)C * M * 64;
-  // this block's 16 modes; the last group also clears the slots 16 nkt .. 31
-  const int kend = kg == nkt - 1 ? 32 : kg * 16 + 16;
+  // this block's modes; the last group also clears the slots 16 nkt .. 31
+  const int kend = kg + KGN - 1 == nkt - 1 ? 32 : kg * 16 + NK;
   for (int q = t; q < (kend - kg * 16) * C; q += XFM_THREADS) {
     const int kx = kg * 16 + q / C, o = q % C, k2 = kx - kg * 16;
     float sr = 0.f, si = 0.f;
@@ -1428,7 +1460,8 @@ static void tables_p(const NOLaunch& L, double* E64, void* Eacc, void* T, void* 
                      T, TT);
 }
 
-void launch_tables(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT, void* FA, void* SA) {
+void launch_tables(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT, double* RD, void* FA, void* SA,
+                   void* EX) {
   if (L.prec == P64) tables_p<P64>(L, E64, Eacc, T, TT);
   else if (L.prec == P32) tables_p<P32>(L, E64, Eacc, T, TT);
   else {
@@ -1438,6 +1471,9 @@ void launch_tables(const NOLaunch& L, double* E64, void* Eacc, void* T, void* TT
     hipLaunchKernelGGL(k_tables_bfx, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.N, L.M, L.basis, E64,
                        (__bf16*)FA, (__bf16*)SA);
   }
+  const int n = round16(L.N) * 32;
+  hipLaunchKernelGGL(k_tables_rx, dim3((n + 255) / 256), dim3(256), 0, L.stream, L.N, L.M, L.basis, E64,
+                     L.prec == PBF ? (const float*)Eacc : nullptr, RD, L.prec == PBF ? (float2*)EX : nullptr);
 }
 
 template <int PREC>
@@ -1515,12 +1551,13 @@ static void apply_pc(const NOLaunch& L) {
   {
     ProfScope ps(PK_ROWDFT, L.stream);
     hipLaunchKernelGGL(k_rowdft_r, dim3((L.N + 15) / 16, L.nsys), dim3(64 * RD_WAVES), 0, L.stream, L.sys, L.N, L.M,
-                       L.basis, L.tab.E64);
+                       L.tab.RD);
   }
   for (int l = 0; l < L.L; ++l) {
     const int XS = (L.N + SX - 1) / SX;
     SpecArgs sa{L.sys, L.N, L.S, L.M, l == 0 ? 1 : 0, XS, L.nsys, L.tab.Eacc, L.tab.E64, L.Rmix[l], L.WL0,
-                L.vsave ? (char*)L.vsave + L.vs_layer * l * L.acc_bytes : nullptr, L.vs_sys, 0, L.basis};
+                L.vsave ? (char*)L.vsave + L.vs_layer * l * L.acc_bytes : nullptr, L.vs_sys, 0, L.basis,
+                L.tab.EX};
     if constexpr (PREC == PBF) {
       // matrix-core x transforms (inference only: training runs FP32/FP64).
       // With spw >= S the layer kernel wrote each row's segment partials
@@ -1528,18 +1565,22 @@ static void apply_pc(const NOLaunch& L) {
       ProfScope ps(PK_SPECTRAL, L.stream);
       const int Sx = L.spw >= L.S ? 1 : L.S;
       sa.S = Sx;
-      if (Sx == 1)
-        hipLaunchKernelGGL((k_xfm_bf<C, 1>), dim3(L.M, (2 * L.M + 15) / 16, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
-                           (const __bf16*)L.tab.FA);
-      else if (Sx == 2)
-        hipLaunchKernelGGL((k_xfm_bf<C, 2>), dim3(L.M, (2 * L.M + 15) / 16, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
-                           (const __bf16*)L.tab.FA);
-      else if (Sx == 4)
-        hipLaunchKernelGGL((k_xfm_bf<C, 4>), dim3(L.M, (2 * L.M + 15) / 16, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
-                           (const __bf16*)L.tab.FA);
-      else
-        hipLaunchKernelGGL((k_xfm_bf<C, 0>), dim3(L.M, (2 * L.M + 15) / 16, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
-                           (const __bf16*)L.tab.FA);
+      const int nkt = (2 * L.M + 15) / 16;
+      const __bf16* FA = (const __bf16*)L.tab.FA;
+      auto xfm = [&](auto segc, auto kgnc) {
+        constexpr int SEG = decltype(segc)::value, KGN = decltype(kgnc)::value;
+        hipLaunchKernelGGL((k_xfm_bf<C, SEG, KGN>), dim3(L.M, nkt / KGN, L.nsys), dim3(XFM_THREADS), 0, L.stream, sa,
+                           FA);
+      };
+      using I1 = std::integral_constant<int, 1>;
+      using I2 = std::integral_constant<int, 2>;
+      // both mode groups per block while many systems are active (the first
+      // layer transforms r's row spectrum and always takes one group)
+      if (Sx == 1 && nkt == 2 && l > 0 && L.spw > 1) xfm(I1{}, I2{});
+      else if (Sx == 1) xfm(I1{}, I1{});
+      else if (Sx == 2) xfm(I2{}, I1{});
+      else if (Sx == 4) xfm(std::integral_constant<int, 4>{}, I1{});
+      else xfm(std::integral_constant<int, 0>{}, I1{});
       const int halves = (C * L.M / 16) % 2 == 0 ? 2 : 1;   // output-channel halves per 16 rows
       // column tiles per wave (four waves), rounded up to a power of two
       const int tpw = (C * L.M / 16 / halves + 3) / 4;

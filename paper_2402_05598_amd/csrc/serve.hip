@@ -35,7 +35,7 @@ struct EngReq {
 struct EngGroup {
   int N = 0;
   size_t off = 0, bytes = 0;
-  size_t E64 = 0, Eacc = 0, T = 0, TT = 0, FA = 0, SA = 0, table = 0, ftable = 0, flags = 0, tres = 0;
+  size_t E64 = 0, Eacc = 0, T = 0, TT = 0, FA = 0, SA = 0, RD = 0, EX = 0, table = 0, ftable = 0, flags = 0, tres = 0;
   std::vector<int64_t> members;
   bool dirty = true;
   size_t hoff = 0;           // this step's range in the engine's pinned export buffers
@@ -112,16 +112,18 @@ size_t group_bytes(const fcgno_model* m, int op, int N, int slots, EngGroup* g) 
   t.Eacc = cv.take((size_t)tw_period(m ? m->arch.basis : B_FOURIER, N) * 2 * asz);
   t.T = cv.take((size_t)NP * MP * esz);
   t.TT = cv.take((size_t)MP * NP * esz);
+  t.RD = cv.take((size_t)NP * 32 * 8);
   if (op == PBF) {   // split-bfloat16 twiddle operands of the matrix-core x transforms
     t.FA = cv.take((size_t)2 * 32 * 2 * NP * 2);
     t.SA = cv.take((size_t)2 * NP * 64 * 2);
+    t.EX = cv.take((size_t)NP * 32 * 8);
   }
   t.table = cv.take((size_t)slots * sizeof(SysDev));
   t.ftable = cv.take((size_t)slots * sizeof(SysDev));
   t.flags = cv.take((size_t)slots * 3 * sizeof(int));
   t.tres = cv.take((size_t)slots * 2 * sizeof(double));
   if (g) {
-    g->E64 = t.E64; g->Eacc = t.Eacc; g->T = t.T; g->TT = t.TT; g->FA = t.FA; g->SA = t.SA;
+    g->E64 = t.E64; g->Eacc = t.Eacc; g->T = t.T; g->TT = t.TT; g->FA = t.FA; g->SA = t.SA; g->RD = t.RD; g->EX = t.EX;
     g->table = t.table; g->ftable = t.ftable; g->flags = t.flags; g->tres = t.tres;
   }
   return cv.n;
@@ -150,6 +152,8 @@ NOLaunch group_no(const fcgno_engine* e, const EngGroup& g, const SysDev* table,
   L.tab.TT = base + g.TT;
   L.tab.FA = op == PBF ? base + g.FA : nullptr;
   L.tab.SA = op == PBF ? base + g.SA : nullptr;
+  L.tab.RD = (const double*)(base + g.RD);
+  L.tab.EX = op == PBF ? base + g.EX : nullptr;
   L.Wfrag = m->Wfrag[op].data();
   L.bias = m->bias[op].data();
   L.Rmix = m->Rmix[op].data();
@@ -179,8 +183,9 @@ EngGroup* group_commit(fcgno_engine* e, EngGroup g) {
   if (e->d.op != PID) {
     const NOLaunch NL = group_no(e, g, nullptr, 0);
     char* base = e->pool + g.off;
-    launch_tables(NL, (double*)(base + g.E64), base + g.Eacc, base + g.T, base + g.TT,
-                  e->d.op == PBF ? base + g.FA : nullptr, e->d.op == PBF ? base + g.SA : nullptr);
+    const bool bf = e->d.op == PBF;
+    launch_tables(NL, (double*)(base + g.E64), base + g.Eacc, base + g.T, base + g.TT, (double*)(base + g.RD),
+                  bf ? base + g.FA : nullptr, bf ? base + g.SA : nullptr, bf ? base + g.EX : nullptr);
   }
   return &e->groups.emplace(g.N, g).first->second;
 }
