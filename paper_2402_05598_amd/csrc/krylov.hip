@@ -162,6 +162,38 @@ __device__ __forceinline__ double slot_sum(const GLOBAL double* part, int N, int
   return block_sum(v, lds);
 }
 
+// slot_sum of the nq <= QN consecutive slots q0 .. q0 + nq - 1 at once: the
+// same per-thread partials, wave sums and four-wave combine (the same bits),
+// with every slot's loads in flight together (one memory round trip instead
+// of nq).  out[q] is valid in every thread; lds holds >= 4 QN values.
+template <int QN>
+__device__ __forceinline__ void slot_sums(const GLOBAL double* part, int N, int nb, int q0, int nq, double (&out)[QN],
+                                          double* lds) {
+  double v[QN];
+#pragma unroll
+  for (int q = 0; q < QN; ++q) v[q] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    double t[QN];
+    // slots past nq read the last one (unconditional loads) and are not added
+#pragma unroll
+    for (int q = 0; q < QN; ++q) t[q] = part[pslot(N, q0 + min(q, nq - 1), b)];
+#pragma unroll
+    for (int q = 0; q < QN; ++q)
+      if (q < nq) v[q] += t[q];
+  }
+#pragma unroll
+  for (int q = 0; q < QN; ++q) v[q] = wave_sum(v[q]);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < QN; ++q) lds[4 * q + w] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < QN; ++q) out[q] = (lds[4 * q] + lds[4 * q + 1]) + (lds[4 * q + 2] + lds[4 * q + 3]);
+}
+
 // Window sums over NV (a compile-time count) window vectors for this
 // thread's points.
 template <int NV>
@@ -275,10 +307,9 @@ __device__ __forceinline__ void dir_pass(const double* __restrict__ P, size_t n,
 // fixed-order sums) instead of a one-block pass between the two kernels.
 __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
   constexpr int HW = DIR_HW, HN = DIR_HN, HR = DIR_HR;
-  constexpr int IR = TILE_I * TILE_J / 256;
   __shared__ double pl[HN];
   __shared__ double cf[MAXW];
-  __shared__ double lds[4];
+  __shared__ double lds[4 * 8];
   const SysDev sd = sys[blockIdx.y];
   GLOBAL SysState* st = sd.st;
   if (!st->active) return;
@@ -304,13 +335,32 @@ __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
     const double t = sd.w[hc[e]];
     hv[e] = hok[e] ? t : 0.0;
   }
-  // coefficients, then passes of at most DIR_PV window vectors
-  const int nbw = flat_blocks(n);
-  for (int q = 0; q < m; ++q) {
-    const double d = slot_sum(sd.part, N, nbw, q, lds);
-    if (threadIdx.x == 0) cf[q] = d / st->ps_ring[(i - m + q) % ring];
+  // the residual at the interior points and (p_k, s_k) of the window, loaded
+  // before the coefficient sums so that their latencies overlap
+  constexpr int IR = TILE_I * TILE_J / 256;
+  bool ok[IR];
+  int gic[IR], gjc[IR];
+  double rv[IR];
+#pragma unroll
+  for (int e = 0; e < IR; ++e) {
+    const int t = threadIdx.x + 256 * e;
+    const int a = t / TILE_J, c = t - a * TILE_J;
+    ok[e] = i0 + a < N && j0 + c < N;
+    gic[e] = ok[e] ? i0 + a : 0;
+    gjc[e] = ok[e] ? j0 + c : 0;
+    rv[e] = sd.r[gic[e] * N + gjc[e]];
   }
-  __syncthreads();
+  const double psq = (int)threadIdx.x < m ? st->ps_ring[(i - m + (int)threadIdx.x) % ring] : 1.0;
+  // coefficients (thread q forms c_q), then passes of at most DIR_PV window vectors
+  const int nbw = flat_blocks(n);
+  for (int q0 = 0; q0 < m; q0 += 8) {
+    double d[8];
+    slot_sums<8>(sd.part, N, nbw, q0, min(8, m - q0), d, lds);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if ((int)threadIdx.x == q0 + q && q0 + q < m) cf[q0 + q] = d[q] / psq;
+    __syncthreads();   // lds is reused by the next group
+  }
   if (blockIdx.x == 0 && threadIdx.x < m) st->coef[threadIdx.x] = cf[threadIdx.x];
   if (blockIdx.x == 0 && threadIdx.x == 0) st->m = m;
   for (int q0 = 0; q0 < m; q0 += DIR_PV) {
@@ -331,20 +381,7 @@ __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
   __syncthreads();
   double* __restrict__ Pi = sd.P + (size_t)(i % ring) * n;
   double* __restrict__ Si = sd.S + (size_t)(i % ring) * n;
-  // interior points: all coefficient and residual loads first (clamped
-  // indices), then the stencil, the stores and the two sums
-  bool ok[IR];
-  int gic[IR], gjc[IR];
-  double rv[IR];
-#pragma unroll
-  for (int e = 0; e < IR; ++e) {
-    const int t = threadIdx.x + 256 * e;
-    const int a = t / TILE_J, c = t - a * TILE_J;
-    ok[e] = i0 + a < N && j0 + c < N;
-    gic[e] = ok[e] ? i0 + a : 0;
-    gjc[e] = ok[e] ? j0 + c : 0;
-    rv[e] = sd.r[gic[e] * N + gjc[e]];
-  }
+  // interior points: the stencil, the stores and the two sums
   double pr = 0.0, ps = 0.0;
 #pragma unroll
   for (int e = 0; e < IR; ++e) {
@@ -386,7 +423,7 @@ __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
 // it.  On breakdown no block updates and block 0 stops the system.
 __global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
   constexpr int UPT = UPD_PTS / 256;
-  __shared__ double lds[4];
+  __shared__ double lds[4], lds8[8];
   const SysDev sd = sys[blockIdx.y];
   GLOBAL SysState* st = sd.st;
   if (!st->active) return;
@@ -408,7 +445,9 @@ __global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
     }
   }
   const int nbd = tile_blocks(N);
-  const double PR = slot_sum(sd.part, N, nbd, SL_PR, lds), PS = slot_sum(sd.part, N, nbd, SL_PS, lds);
+  double prs[2];
+  slot_sums<2>(sd.part, N, nbd, SL_PR, 2, prs, lds8);
+  const double PR = prs[0], PS = prs[1];
   if (!(isfinite(PS) && isfinite(PR)) || !(PS > 0.0)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       st->alpha = 0.0;
