@@ -471,7 +471,9 @@ def all_active_kernels(fc, torch, model, kd, fd, u0d, op, C, M, L, S, logf, iter
         avg = ms_ / max(n_, 1) * 1e3
         it_us += ms_ * 1e3 / iters
         d = {"launches": n_, "avg_us": round(avg, 2)}
-        if name in tot:
+        if name in tot and n_ == 0:
+            d["note"] = "no launches: formed in the projection layer's epilogue"
+        elif name in tot:
             gbs = tot[name] / max(ms_ * 1e-3, 1e-30) / 1e9
             d.update({"GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
                       "bytes_per_launch": round(tot[name] / max(n_, 1))})
@@ -827,6 +829,9 @@ def main():
     krylov = {}
     for name, bpp in kry_bytes.items():
         n_, avg = per_kernel[name]["launches"], per_kernel[name]["avg_us"]
+        if n_ == 0:
+            krylov[name] = {"note": "no launches: formed in the projection layer's epilogue"}
+            continue
         gbs = bpp * N * N / max(n_ * avg * 1e-6, 1e-30) / 1e9
         krylov[name] = {"GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
     per_kernel["krylov_hbm"] = krylov

@@ -151,11 +151,7 @@ extern "C" void fcgno_model_destroy(fcgno_model* m) {
 // ---------------------------------------------------------------------------
 namespace fcgno_host {
 
-size_t part_blocks(int N) {
-  const size_t flat = ((size_t)N * N + UPD_PTS - 1) / UPD_PTS;   // UPD_PTS <= FLAT_PTS
-  const size_t tile = (size_t)((N + TILE_I - 1) / TILE_I) * ((N + TILE_J - 1) / TILE_J);
-  return std::max(flat, tile);
-}
+size_t part_blocks(int N) { return (size_t)pslot_stride(N); }
 
 // backward kernel geometry: Sb row segments of TPW tiles per row, nbs = N Sb
 // row segments per system (one wave each)
@@ -478,6 +474,9 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
   const SysDev* sysdev = (const SysDev*)(base + p.sysdev);
   HIPCHK(hipMemcpyAsync(base + p.sysdev, h.data(), B * sizeof(SysDev), hipMemcpyHostToDevice, s));
   KrylovLaunch KL{sysdev, B, N, d->m_max, s};
+  // neural-operator solves: the projection layer forms the window sums
+  const bool pwd = is_no(op) && proj_wdots(N, d->m_max);
+  KL.wslots = pwd ? proj_wslots(N) : 0;
   for (int g = 0; g < G; ++g) {
     KrylovLaunch KLg{sysdev + b0[g], b0[g + 1] - b0[g], N, d->m_max, s};
     launch_init_state(KLg, d->max_iter, d->rtol);
@@ -485,6 +484,7 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
   NOLaunch NL{};
   if (is_no(op)) {
     NL = make_no(m, p, base, sysdev, N, B, op, s);
+    NL.wdots = pwd ? 1 : 0;
     fcgno_status os = operator_setup(m, p, base, NL, N, B, op, s);
     if (os != FCGNO_OK) return os;
   }
@@ -508,6 +508,7 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
   std::vector<int> nact(G), hn(G);
   for (int g = 0; g < G; ++g) {
     KLs[g] = KrylovLaunch{sysdev + b0[g], b0[g + 1] - b0[g], N, d->m_max, ss[g]};
+    KLs[g].wslots = pwd ? proj_wslots(N) : 0;
     NLs[g].sys = sysdev + b0[g];
     NLs[g].nsys = b0[g + 1] - b0[g];
     NLs[g].stream = ss[g];
@@ -538,7 +539,7 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
         if (is_no(op)) launch_no_apply(NL1);
         else if (op == PJAC) launch_jacobi(KL, d->precond_steps);
         else if (op == PSGS) launch_rbsgs(KL, d->precond_steps);
-        launch_wdots(KL);
+        if (!pwd) launch_wdots(KL);
         launch_dir(KL);
         launch_update(KL);
         if (rec && i < rec->m) launch_record(KL, i, rec->m, rec->rec_r, rec->rec_e, rec->ustar);
@@ -566,7 +567,7 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
         if (is_no(op)) launch_no_apply(NL1);
         else if (op == PJAC) launch_jacobi(KL, d->precond_steps);
         else if (op == PSGS) launch_rbsgs(KL, d->precond_steps);
-        launch_wdots(KL);
+        if (!pwd) launch_wdots(KL);
         launch_dir(KL);
         launch_update(KL);
         if (rec && i < rec->m) launch_record(KL, i, rec->m, rec->rec_r, rec->rec_e, rec->ustar);
@@ -587,7 +588,7 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
         if (is_no(op)) launch_no_apply(NLs[g]);
         else if (op == PJAC) launch_jacobi(KLs[g], d->precond_steps);
         else if (op == PSGS) launch_rbsgs(KLs[g], d->precond_steps);
-        launch_wdots(KLs[g]);
+        if (!pwd) launch_wdots(KLs[g]);
         launch_dir(KLs[g]);
         launch_update(KLs[g]);
         if (rec && i < rec->m) launch_record(KLs[g], i, rec->m, rec->rec_r, rec->rec_e, rec->ustar);

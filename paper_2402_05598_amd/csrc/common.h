@@ -128,6 +128,23 @@ struct Tables {
   const void* EX;
 };
 
+__host__ __device__ inline int flat_blocks(int n) { return (n + FLAT_PTS - 1) / FLAT_PTS; }
+__host__ __device__ inline int upd_blocks(int n) { return (n + UPD_PTS - 1) / UPD_PTS; }
+__host__ __device__ inline int tile_blocks(int N) {
+  return ((N + TILE_I - 1) / TILE_I) * ((N + TILE_J - 1) / TILE_J);
+}
+// Partial-sum slots of a system: slot-major, [NQ][stride], so that one slot's
+// values from every writer are contiguous (the kernels that sum them in every
+// block read whole lines).  stride = the most partials of any writer: blocks
+// of the flat and tiled Krylov kernels (FLAT_PTS >= UPD_PTS), or the
+// projection layer's window sums (one per 4/S rows).
+__host__ __device__ inline int proj_wslots(int N) { return (N * seg_count(N) + 3) / 4; }
+__host__ __device__ inline int pslot_stride(int N) {
+  const int a = upd_blocks(N * N), b = tile_blocks(N), c = proj_wslots(N);
+  return a > b ? (a > c ? a : c) : (b > c ? b : c);
+}
+__device__ __forceinline__ size_t pslot(int N, int q, int b) { return (size_t)q * pslot_stride(N) + b; }
+
 __device__ __forceinline__ int window_size(int i, int m_max) {
   int r = i % (m_max + 1);
   int a = r > 1 ? r : 1;
@@ -221,12 +238,18 @@ struct KrylovLaunch {
   int N;
   int m_max;
   hipStream_t stream;
+  int wslots = 0;      // partial slots of the window sums (0: the window-sum kernel's)
 };
 
 void launch_init_state(const KrylovLaunch& L, int max_iter, double rtol);
 void launch_residual(const KrylovLaunch& L, int mode);   // 0: r0 setup, 1: final true residual
 void launch_rnorm(const KrylovLaunch& L);                 // snorm from r (operator only)
 void launch_wdots(const KrylovLaunch& L);
+// The projection layer forms the window sums itself (no window-sum launch)
+// when the window holds at most 8 vectors (two per lane group) and a row has
+// at most two segments (N <= 512), proj_wslots(N) partials.
+constexpr int PROJ_WDOTS_MAX_M = 8;
+inline bool proj_wdots(int N, int m_max) { return m_max <= PROJ_WDOTS_MAX_M && seg_count(N) <= 2; }
 void launch_dir(const KrylovLaunch& L);
 void launch_update(const KrylovLaunch& L);
 // classical preconditioners: w = x_steps of Jacobi / red-black symmetric
@@ -264,6 +287,9 @@ struct NOLaunch {
   void* vsave;                // spectra V^, [L][sys][M][C][2M] complex accumulate precision
   size_t vs_sys, vs_layer;    // element strides
   int op_bytes, acc_bytes;
+  // solve: the projection layer also forms the window sums (w_i, s_k) of
+  // Algorithm 1 (one partial per row segment; the window-sum kernel is skipped)
+  int wdots = 0;
 };
 
 struct SpecArgs {

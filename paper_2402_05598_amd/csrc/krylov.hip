@@ -23,19 +23,6 @@ namespace fcgno {
 
 constexpr int PPT = FLAT_PTS / 256;   // points per thread in the flat kernels
 
-__device__ __forceinline__ int flat_blocks(int n) { return (n + FLAT_PTS - 1) / FLAT_PTS; }
-__device__ __forceinline__ int upd_blocks(int n) { return (n + UPD_PTS - 1) / UPD_PTS; }
-__device__ __forceinline__ int tile_blocks(int N) {
-  return ((N + TILE_I - 1) / TILE_I) * ((N + TILE_J - 1) / TILE_J);
-}
-// Partial-sum slots of a system: slot-major, [NQ][stride], so that one slot's
-// values from every block are contiguous (the kernels that sum them in every
-// block read whole lines).  stride = the most blocks of any partial writer
-// (the same count the host plans: max(n / UPD_PTS, tiles); FLAT_PTS >= UPD_PTS).
-__device__ __forceinline__ size_t pslot(int N, int q, int b) {
-  const int stride = max(upd_blocks(N * N), tile_blocks(N));
-  return (size_t)q * stride + b;
-}
 
 // 5-point operator at interior point (i, j) with neighbour values supplied.
 __device__ __forceinline__ double stencil_at(const double* __restrict__ k, int N, int i, int j,
@@ -305,7 +292,9 @@ __device__ __forceinline__ void dir_pass(const double* __restrict__ P, size_t n,
 // partials, then p_i on the tile and a one-point halo, s_i = A p_i, partial
 // (p_i, r_i), (p_i, s_i).  Every block forms the coefficients itself (the same
 // fixed-order sums) instead of a one-block pass between the two kernels.
-__global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
+// wslots: partial slots of the window sums (the window-sum kernel's blocks,
+// or the projection layer's row segments when it formed them).
+__global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N, int wslots) {
   constexpr int HW = DIR_HW, HN = DIR_HN, HR = DIR_HR;
   __shared__ double pl[HN];
   __shared__ double cf[MAXW];
@@ -352,7 +341,7 @@ __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N) {
   }
   const double psq = (int)threadIdx.x < m ? st->ps_ring[(i - m + (int)threadIdx.x) % ring] : 1.0;
   // coefficients (thread q forms c_q), then passes of at most DIR_PV window vectors
-  const int nbw = flat_blocks(n);
+  const int nbw = wslots;
   for (int q0 = 0; q0 < m; q0 += 8) {
     double d[8];
     slot_sums<8>(sd.part, N, nbw, q0, min(8, m - q0), d, lds);
@@ -700,7 +689,8 @@ void launch_dir(const KrylovLaunch& L) {
   const int nb = ((L.N + TILE_I - 1) / TILE_I) * ((L.N + TILE_J - 1) / TILE_J);
   {
     ProfScope ps(PK_DIR, L.stream);
-    hipLaunchKernelGGL(k_dir, dim3(nb, L.nsys), dim3(256), 0, L.stream, L.sys, L.N);
+    hipLaunchKernelGGL(k_dir, dim3(nb, L.nsys), dim3(256), 0, L.stream, L.sys, L.N,
+                       L.wslots > 0 ? L.wslots : (L.N * L.N + FLAT_PTS - 1) / FLAT_PTS);
   }
 }
 void launch_update(const KrylovLaunch& L) {

@@ -1053,6 +1053,7 @@ struct LayerArgs {
   void* zout;       // training: pre-activation z of this layer, [sys][N^2][C] op precision (nullable)
   size_t z_sys;     // elements per system in zout
   int spw;          // row segments (of TPW tiles) per wave
+  int wdots = 0;    // projection layer in a solve: also form the window sums (w_i, s_k)
 };
 
 template <int PREC, int C, int MP, bool FEAT, bool PROJ>
@@ -1091,6 +1092,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
   const int sg0 = grp * a.spw, sg1 = min(a.S, sg0 + a.spw);
   const double snorm = sd.st->snorm;
   const int twoM = a.twoM;
+  // Projection layer in a solve: the window sums (w_i, s_k) of Algorithm 1
+  // over the window k = i - m_i .. i - 1, formed from w_i as it is written
+  // (the separate window-sum pass would read w_i back).  Lane group g takes
+  // the window slots g and g + 4 (m_i <= 8).  One partial per 4/S rows
+  // (S <= 2): each wave adds its segments' sums in segment order, the block
+  // adds its waves' values per row and the rows per partial in order, so the
+  // partials do not depend on spw.
+  constexpr int WJ = 2;
+  int wm = 0;
+  const double* svp[WJ] = {nullptr, nullptr};
+  if (PROJ && a.wdots) {
+    const int it = sd.st->i, mmax = sd.st->m_max, ring = mmax + 1;
+    wm = window_size(it, mmax);
+#pragma unroll
+    for (int j = 0; j < WJ; ++j) {
+      const int q = min(g + 4 * j, max(wm - 1, 0));
+      svp[j] = sd.S + (size_t)((it - wm + q) % ring) * N * N + (size_t)x * N;
+    }
+  }
+  const bool wd = wm > 0;
+  double wacc[WJ] = {0.0, 0.0}, wrow[WJ] = {0.0, 0.0};
 
   frag_t Bf[KT + KIN][NOB];
   const in_t* Hc = (const in_t*)sd.Hc + (size_t)x * C * MP;
@@ -1153,6 +1175,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
     frag_t A2[NA2];
     double rr;
     acc_t lk;
+    double sv[PROJ ? WJ : 1];   // window vectors s_k at this lane's point
   };
   using full_t = std::integral_constant<bool, true>;
   using part_t = std::integral_constant<bool, false>;
@@ -1200,6 +1223,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
   // ... and the twiddle operand of GEMM2
   auto load_b = [&](int t, TileIn& ti) __attribute__((always_inline)) {
     const int y0 = t * 16;
+    // the window vectors at this lane's point (projection layer): refilled
+    // with GEMM2's operand, after the epilogue that reads them
+    if constexpr (PROJ) {
+      if (wd) {
+        const int yc = min(y0 + n16, N - 1);
+#pragma unroll
+        for (int j = 0; j < WJ; ++j) ti.sv[j] = g + 4 * j < wm ? svp[j][yc] : 0.0;
+      }
+    }
     if constexpr (!PROJ) {
       if constexpr (KPL == 4) {
         const in_t* tp = TTl + y0 * MP;
@@ -1304,7 +1336,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
         for (int i = 0; i < 4; ++i) part += wp[ob][i] * act<PREC>(acc[ob][i]);
       part += __shfl_xor(part, 16, 64);
       part += __shfl_xor(part, 32, 64);
-      if (g == 0 && va) sd.w[(size_t)x * N + ya] = snorm * ((double)part + bP);
+      const double wv = snorm * ((double)part + bP);
+      if (g == 0 && va) sd.w[(size_t)x * N + ya] = wv;
+      if (wd && va) {
+#pragma unroll
+        for (int j = 0; j < WJ; ++j)
+          if (g + 4 * j < wm) wacc[j] += wv * cur.sv[j];
+      }
+      if constexpr (RELOAD) load_b(tn, cur);
     } else {
       // v' = GELU(z) rounded once to the op precision; rows past N are zero
       in_t hv[NOB][4];
@@ -1371,7 +1410,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
   const int tf = min(T1, N >> 4);
   static_assert(TPW % DEPTH == 0, "segments must hold whole ring passes");
   auto seg_done = [&](int t) __attribute__((always_inline)) {
-    if constexpr (!PROJ) {
+    if constexpr (PROJ) {
+      if (wd && ((t + 1) % TPW == 0 || t + 1 == T1)) {
+        // this segment's window sums over the 16 points of each lane group
+        // (a fixed order), added to the wave's from zero in segment order
+        const bool first = t / TPW == sg0;
+#pragma unroll
+        for (int j = 0; j < WJ; ++j) {
+          double v = wacc[j];
+          v += __shfl_xor(v, 1, 64);
+          v += __shfl_xor(v, 2, 64);
+          v += __shfl_xor(v, 4, 64);
+          v += __shfl_xor(v, 8, 64);
+          wrow[j] = (first ? 0.0 : wrow[j]) + v;
+          wacc[j] = 0.0;
+        }
+      }
+    } else {
       if ((t + 1) % TPW == 0 || t + 1 == T1) {
         if constexpr (PREC == PBF) {
           const int seg = t / TPW;
@@ -1446,6 +1501,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
     load_b(tf, tl);
     process(tf, tl, 0, part_t{}, std::false_type{});
     seg_done(tf);
+  }
+  if constexpr (PROJ) {
+    // window-sum partials: a block holds 4 / ngrp whole rows (S <= 2, so
+    // ngrp is 1 or 2), i.e. spw partials of 4 / S rows.  Waves past the last
+    // row have left; the barrier waits for the others only.
+    __shared__ double wl[4][WJ][4];
+    if (wd) {
+      const int w = threadIdx.x >> 6;
+      if (n16 == 0) {
+#pragma unroll
+        for (int j = 0; j < WJ; ++j) wl[w][j][g] = wrow[j];
+      }
+      __syncthreads();
+      if (w == 0) {
+        const int sl = lane >> 3, j = (lane >> 2) & 1, gg = lane & 3, q = gg + 4 * j;
+        const int rps = 4 / a.S, xb = (int)(blockIdx.x * 4) / ngrp, rows = 4 / ngrp;
+        if (sl < rows / rps && q < wm) {
+          const int sidx = xb / rps + sl;
+          double val = 0.0;
+          for (int r = 0; r < rps; ++r) {
+            const int row = sidx * rps + r;
+            if (row >= N) break;
+            double rv = 0.0;
+            for (int gp = 0; gp < ngrp; ++gp) rv += wl[(row - xb) * ngrp + gp][j][gg];
+            val += rv;
+          }
+          sd.part[pslot(N, q, sidx)] = val;
+        }
+      }
+    }
   }
 }
 
@@ -1613,6 +1698,7 @@ static void apply_pc(const NOLaunch& L) {
     LayerArgs la{L.sys, L.N, L.S, 2 * L.M, sin, sout, L.tab.T, L.tab.TT, L.Wfrag[l], L.bias[l], L.WP, L.bP,
                  L.zsave ? (char*)L.zsave + L.z_layer * l * L.op_bytes : nullptr, L.z_sys, L.spw};
     const bool feat = l == 0, proj = l == L.L - 1;
+    la.wdots = proj ? L.wdots : 0;
     if (L.MP == 16) layer_dispatch<PREC, C, 16>(L, la, feat, proj);
     else layer_dispatch<PREC, C, 32>(L, la, feat, proj);
   }

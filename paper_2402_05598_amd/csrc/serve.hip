@@ -374,10 +374,14 @@ extern "C" fcgno_status fcgno_engine_step(fcgno_engine* e, int32_t* n_active, in
     const SysDev* table = (const SysDev*)(base + g.table);
     KrylovLaunch KL{table, G, g.N, e->d.m_max, g.s};
     NOLaunch NL{};
+    // the projection layer forms the window sums (no window-sum launch)
+    const bool pwd = e->d.op != PID && proj_wdots(g.N, e->d.m_max);
     if (e->d.op != PID) NL = group_no(e, g, table, G);
+    NL.wdots = pwd ? 1 : 0;
+    KL.wslots = pwd ? proj_wslots(g.N) : 0;
     for (int i = 0; i < K; ++i) {
       if (e->d.op != PID) launch_no_apply(NL);
-      launch_wdots(KL);
+      if (!pwd) launch_wdots(KL);
       launch_dir(KL);
       launch_update(KL);
     }
