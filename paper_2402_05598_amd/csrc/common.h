@@ -88,6 +88,10 @@ struct SysDev {
   GLOBAL double* tmp;       // [N^2] second iterate of the Jacobi sweeps
   GLOBAL void* WT;          // bfloat16 operator: mixed spectrum as the synthesis operand,
                             // [2 (hi, lo)][C*M][64] bfloat16 (see k_xfm_bf)
+  // copies of the state's active flag, iteration index and window size in
+  // the launch table itself, kept by the kernels that change the state:
+  // a kernel reads them with its record instead of behind the state pointer
+  int active, it, mmax;
 };
 
 // Per-N tables shared by the systems of one launch.
@@ -172,10 +176,12 @@ __device__ __forceinline__ T block_sum(T v, T* lds /* >= 4 */) {
   return s;
 }
 
-__device__ __forceinline__ void deactivate(GLOBAL SysState* st, GLOBAL int* n_active, int status, int iters) {
+__device__ __forceinline__ void deactivate(GLOBAL SysState* st, GLOBAL int* n_active, int status, int iters,
+                                           const SysDev* rec) {
   st->status = status;
   st->iters = iters;
   st->active = 0;
+  ((SysDev*)rec)->active = 0;
   atomicSub(n_active, 1);
 }
 
@@ -260,6 +266,9 @@ void launch_record(const KrylovLaunch& L, int it, int m, double* rec_r, double* 
 // flags[3b..3b+2] = {active, status, iters}; tres[2b], tres[2b+1] = true
 // residual relative to ||r_0|| and to ||f||
 void launch_export(const SysDev* sys, int nsys, int* flags, double* tres, hipStream_t s);
+// the launch table's copies of active flag, iteration index and window size
+// from each system's state (after a host upload of the table)
+void launch_sync_records(const SysDev* sys, int nsys, hipStream_t s);
 void launch_zero(void* p, size_t nbytes, hipStream_t s);      // bytes [0, nbytes) = 0
 
 struct NOLaunch {

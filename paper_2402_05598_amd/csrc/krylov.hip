@@ -44,6 +44,10 @@ __global__ __launch_bounds__(64) void k_init_state(const SysDev* sys, int nsys, 
   GLOBAL SysState* st = sys[b].st;
   st->i = 0;
   st->active = 1;
+  SysDev* rec = (SysDev*)(sys + b);
+  rec->active = 1;
+  rec->it = 0;
+  rec->mmax = m_max;
   st->status = S_NOTCONV;
   st->iters = 0;
   for (int q = 0; q < 4; ++q) st->tick[q] = 0u;
@@ -69,7 +73,7 @@ __global__ __launch_bounds__(64) void k_init_state(const SysDev* sys, int nsys, 
 __global__ __launch_bounds__(256) void k_residual(const SysDev* sys, int N, int mode) {
   __shared__ double lds[4];
   const SysDev sd = sys[blockIdx.y];
-  if (mode == 0 && !sd.st->active) return;
+  if (mode == 0 && !sd.active) return;
   const int n = N * N;
   const int K = N + 2;
   double acc = 0.0, bad = 0.0, ff = 0.0;
@@ -204,9 +208,8 @@ __device__ __forceinline__ void wdots_pass(const double* __restrict__ S, size_t 
 // Window dot products (w_i, s_k), in passes of up to 8 window vectors.
 __global__ __launch_bounds__(256) void k_wdots(const SysDev* sys, int N) {
   const SysDev sd = sys[blockIdx.y];
-  const GLOBAL SysState* st = sd.st;
-  if (!st->active) return;
-  const int i = st->i, mm = st->m_max;
+  if (!sd.active) return;
+  const int i = sd.it, mm = sd.mmax;
   const int m = window_size(i, mm);
   if (m == 0) return;
   const int n = N * N;
@@ -301,8 +304,8 @@ __global__ __launch_bounds__(256) void k_dir(const SysDev* sys, int N, int wslot
   __shared__ double lds[4 * 8];
   const SysDev sd = sys[blockIdx.y];
   GLOBAL SysState* st = sd.st;
-  if (!st->active) return;
-  const int i = st->i, mm = st->m_max, ring = mm + 1;
+  if (!sd.active) return;
+  const int i = sd.it, mm = sd.mmax, ring = mm + 1;
   const int m = window_size(i, mm);
   const int n = N * N;
   const int tj = (N + TILE_J - 1) / TILE_J;
@@ -415,8 +418,8 @@ __global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
   __shared__ double lds[4], lds8[8];
   const SysDev sd = sys[blockIdx.y];
   GLOBAL SysState* st = sd.st;
-  if (!st->active) return;
-  const int i = st->i, ring = st->m_max + 1;
+  if (!sd.active) return;
+  const int i = sd.it, ring = sd.mmax + 1;
   const int n = N * N;
   const double* __restrict__ Pi = sd.P + (size_t)(i % ring) * n;
   const double* __restrict__ Si = sd.S + (size_t)(i % ring) * n;
@@ -440,7 +443,7 @@ __global__ __launch_bounds__(256) void k_update(const SysDev* sys, int N) {
   if (!(isfinite(PS) && isfinite(PR)) || !(PS > 0.0)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       st->alpha = 0.0;
-      deactivate(st, sd.n_active, S_BREAK, i);
+      deactivate(st, sd.n_active, S_BREAK, i, sys + blockIdx.y);
     }
     return;
   }
@@ -476,7 +479,7 @@ __global__ __launch_bounds__(256) void k_fin(const SysDev* sys, int N, int mode)
   __shared__ double lds[4];
   const SysDev sd = sys[blockIdx.x];
   GLOBAL SysState* st = sd.st;
-  if (mode != 4 && mode != 5 && !st->active) return;
+  if (mode != 4 && mode != 5 && !sd.active) return;
   const int nb = mode == 2 ? upd_blocks(N * N) : flat_blocks(N * N);
   auto fsum = [&](int q) {
     double v = 0.0;
@@ -493,10 +496,11 @@ __global__ __launch_bounds__(256) void k_fin(const SysDev* sys, int N, int mode)
       st->snorm = sqrt(rr) / (double)N;
       sd.hist[i + 1] = rho;
       st->i = i + 1;
+      ((SysDev*)(sys + blockIdx.x))->it = i + 1;
       st->iters = i + 1;
-      if (!isfinite(rho)) deactivate(st, sd.n_active, S_BREAK, i + 1);
-      else if (rho <= st->rtol) deactivate(st, sd.n_active, S_OK, i + 1);
-      else if (i + 1 >= st->max_iter) deactivate(st, sd.n_active, S_NOTCONV, i + 1);
+      if (!isfinite(rho)) deactivate(st, sd.n_active, S_BREAK, i + 1, sys + blockIdx.x);
+      else if (rho <= st->rtol) deactivate(st, sd.n_active, S_OK, i + 1, sys + blockIdx.x);
+      else if (i + 1 >= st->max_iter) deactivate(st, sd.n_active, S_NOTCONV, i + 1, sys + blockIdx.x);
     }
   } else if (mode == 3) {
     const double rr = fsum(0), nbad = fsum(1), ff = fsum(2);
@@ -507,10 +511,10 @@ __global__ __launch_bounds__(256) void k_fin(const SysDev* sys, int N, int mode)
       st->snorm = sqrt(rr) / (double)N;
       if (nbad > 0.0 || !isfinite(rr)) {
         sd.hist[0] = __longlong_as_double(0x7ff8000000000000ll);
-        deactivate(st, sd.n_active, S_NONFINITE, 0);
+        deactivate(st, sd.n_active, S_NONFINITE, 0, sys + blockIdx.x);
       } else {
         sd.hist[0] = 1.0;
-        if (rr == 0.0) deactivate(st, sd.n_active, S_OK, 0);
+        if (rr == 0.0) deactivate(st, sd.n_active, S_OK, 0, sys + blockIdx.x);
       }
     }
   } else if (mode == 4) {
@@ -525,6 +529,7 @@ __global__ __launch_bounds__(256) void k_fin(const SysDev* sys, int N, int mode)
     if (threadIdx.x == 0) {
       st->snorm = sqrt(rr) / (double)N;
       st->active = 1;
+      ((SysDev*)(sys + blockIdx.x))->active = 1;
     }
   }
 }
@@ -570,7 +575,7 @@ __device__ __forceinline__ void offsum_diag(const GLOBAL double* __restrict__ k,
 // first: x_in = 0.  to_w: write w (else the second iterate tmp).
 __global__ __launch_bounds__(256) void k_jacobi(const SysDev* sys, int N, int to_w, int first) {
   const SysDev sd = sys[blockIdx.y];
-  if (!sd.st->active) return;
+  if (!sd.active) return;
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= N * N) return;
   const int i = p / N, j = p - i * N;
@@ -587,7 +592,7 @@ __global__ __launch_bounds__(256) void k_jacobi(const SysDev* sys, int N, int to
 // per point of the colour: row i, pair q covers columns 2q and 2q + 1.
 __global__ __launch_bounds__(256) void k_rbgs(const SysDev* sys, int N, int color, int first) {
   const SysDev sd = sys[blockIdx.y];
-  if (!sd.st->active) return;
+  if (!sd.active) return;
   const int H = (N + 1) >> 1;
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= N * H) return;
@@ -609,6 +614,18 @@ __global__ __launch_bounds__(256) void k_zero(char* p, size_t nbytes) {
   for (size_t q = (size_t)blockIdx.x * 256 + threadIdx.x; q < n16; q += stride) ((uint4*)p)[q] = uint4{0, 0, 0, 0};
   const size_t t = (n16 << 4) + (size_t)blockIdx.x * 256 + threadIdx.x;
   if (blockIdx.x == 0 && t < nbytes) p[t] = 0;
+}
+
+// Refresh the launch table's copies of the state (after the host uploaded
+// the table: the host does not know which systems stopped at set-up).
+__global__ __launch_bounds__(64) void k_sync_records(const SysDev* sys, int nsys) {
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  if (b >= nsys) return;
+  const GLOBAL SysState* st = sys[b].st;
+  SysDev* rec = (SysDev*)(sys + b);
+  rec->active = st->active;
+  rec->it = st->i;
+  rec->mmax = st->m_max;
 }
 
 // Per-system summary for the host: {active, status, iters} and the true residual.
@@ -649,6 +666,10 @@ void launch_zero(void* p, size_t nbytes, hipStream_t s) {
   const size_t n16 = (nbytes >> 4) + 1;
   const unsigned nb = (unsigned)std::min<size_t>((n16 + 255) / 256, 4096);
   hipLaunchKernelGGL(k_zero, dim3(nb), dim3(256), 0, s, (char*)p, nbytes);
+}
+
+void launch_sync_records(const SysDev* sys, int nsys, hipStream_t s) {
+  hipLaunchKernelGGL(k_sync_records, dim3((nsys + 63) / 64), dim3(64), 0, s, sys, nsys);
 }
 
 void launch_export(const SysDev* sys, int nsys, int* flags, double* tres, hipStream_t s) {

@@ -190,7 +190,7 @@ constexpr int RD_WAVES = 8;   // the combine below adds eight partials; 512 thre
 __global__ __launch_bounds__(64 * RD_WAVES) void k_rowdft_r(const SysDev* sys, int N, int M, const double* RD) {
   __shared__ double part[RD_WAVES][16][33];
   const SysDev sd = sys[blockIdx.y];
-  if (!sd.st->active) return;
+  if (!sd.active) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int n16 = lane & 15, g = lane >> 4;
   const int x0 = blockIdx.x * 16;
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void k_spec_fwd(SpecArgs a) {
   __shared__ acc_t Er_[32][SX + 1], Ei_[32][SX + 1];
   const int ky = blockIdx.x, xs = blockIdx.y;
   const SysDev sd = a.sys[blockIdx.z];
-  if (!sd.st->active) return;
+  if (!sd.active) return;
   const int N = a.N, M = a.M, twoM = 2 * M, MP = round16(twoM);
   const int x0 = xs * SX, nx = min(SX, N - x0);
   const acc_t* E = (const acc_t*)a.Eacc;
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(256) void k_spec_mix(SpecArgs a) {
   __shared__ acc_t Vr[C][KXB + 1], Vi[C][KXB + 1];
   const int ky = blockIdx.x;
   const SysDev sd = a.sys[blockIdx.z];
-  if (!sd.st->active) return;
+  if (!sd.active) return;
   const int M = a.M, twoM = 2 * M;
   const int t = threadIdx.x;
   const int ch = t % C, kl = t / C, kx = blockIdx.y * KXB + kl;
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(512) void k_spec_inv(SpecArgs a) {
   __shared__ acc_t Er_[SR][MP], Ei_[SR][MP];   // zero for kx >= 2M
   __shared__ __attribute__((aligned(16))) in_t tile[SR * C * MP];
   const SysDev sd = a.sys[blockIdx.y];
-  if (!sd.st->active) return;
+  if (!sd.active) return;
   const int N = a.N, M = a.M, twoM = 2 * M;
   const int x0 = blockIdx.x * SR;
   const int nx = min(SR, N - x0);
@@ -716,7 +716,7 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
   __shared__ float Vr_[C][NK + 1], Vi_[C][NK + 1];
   const int ky = blockIdx.x, kg = blockIdx.y * KGN;   // modes a = 16 kg .. 16 kg + NK - 1
   const SysDev sd = a.sys[blockIdx.z];
-  if (!sd.st->active) return;
+  if (!sd.active) return;
   const int N = a.N, M = a.M, twoM = 2 * M, MP = round16(twoM), NP = round16(N);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, n16 = lane & 15, g = lane >> 4;
   const int nkt = (twoM + 15) >> 4;
@@ -959,7 +959,7 @@ template <int C, int MP, int TPWV>
 __global__ __launch_bounds__(256) void k_xinv_bf(SpecArgs a, const __bf16* SA) {
   __shared__ __attribute__((aligned(16))) uint16_t tile[16 * C * MP];
   const SysDev sd = a.sys[blockIdx.z];
-  if (!sd.st->active) return;
+  if (!sd.active) return;
   const int N = a.N, M = a.M, NP = round16(N);
   const int x0 = blockIdx.x * 16;
   const int nx = min(16, N - x0);
@@ -1079,7 +1079,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
   const int lane = threadIdx.x & 63;
   const int n16 = lane & 15, g = lane >> 4;
   const SysDev sd = a.sys[blockIdx.y];
-  if (!sd.st->active) return;
+  if (!sd.active) return;
   const int N = a.N, NP = round16(N);
   // A wave takes a.spw consecutive row segments of TPW tiles each and writes
   // one partial spectrum per segment, so the results do not depend on spw.
@@ -1103,7 +1103,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == PBF
   int wm = 0;
   const double* svp[WJ] = {nullptr, nullptr};
   if (PROJ && a.wdots) {
-    const int it = sd.st->i, mmax = sd.st->m_max, ring = mmax + 1;
+    const int it = sd.it, mmax = sd.mmax, ring = mmax + 1;
     wm = window_size(it, mmax);
 #pragma unroll
     for (int j = 0; j < WJ; ++j) {

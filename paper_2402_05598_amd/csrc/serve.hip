@@ -243,6 +243,9 @@ fcgno_status upload_table(fcgno_engine* e, EngGroup& g, size_t where, const std:
   h.reserve(ids.size());
   for (int64_t id : ids) h.push_back(e->active.at(id).sd);
   HIPCHK(hipMemcpyAsync(e->pool + g.off + where, h.data(), h.size() * sizeof(SysDev), hipMemcpyHostToDevice, g.s));
+  // the records' copies of each request's state (a request may have stopped
+  // at set-up, which the host has not seen yet)
+  launch_sync_records((const SysDev*)(e->pool + g.off + where), (int)h.size(), g.s);
   return FCGNO_OK;
 }
 
