@@ -171,6 +171,8 @@ Plan make_plan(const fcgno_model* m, int N, int B, int m_max, int max_iter, int 
   p.counter = cv.take(MAX_SUB * sizeof(int));   // one active-system count per sub-batch
   p.part = cv.take((size_t)B * p.n_part_blocks * NQ * sizeof(double));
   if (kind == KIND_SOLVE) {
+    p.sysdev2 = cv.take((size_t)B * sizeof(SysDev));   // compacted launch table
+    p.idle = cv.take(sizeof(SysState));
     p.hist = cv.take((size_t)B * (max_iter + 1) * sizeof(double));
     p.r = cv.take((size_t)B * n * 8);
     p.P = cv.take((size_t)B * (m_max + 1) * n * 8);
@@ -522,8 +524,28 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
   constexpr int SUB_MIN_ACTIVE = 3;
   bool split = G > 1;
   NOLaunch NL1 = NL;
+  KrylovLaunch KL1 = KL;
   int it = 0;
   int active = B;   // active systems at the last poll
+  // Once systems stop, the single-stream launches run on a compacted table
+  // of the active systems' records (rebuilt on the device, in stream order,
+  // whenever the polled count drops), sized to the last polled count, which
+  // bounds the true one.  Not with recording, whose output is indexed by
+  // the launch slot.
+  SysDev* sysdev2 = (SysDev*)(base + p.sysdev2);
+  SysState* idle = (SysState*)(base + p.idle);
+  const bool compact = rec == nullptr;
+  int launched = B;
+  if (compact) launch_zero(idle, sizeof(SysState), s);
+  auto shrink = [&]() {
+    if (!compact || active >= launched) return;
+    launch_compact(sysdev, B, sysdev2, idle, s);
+    launched = active;
+    KL1.sys = sysdev2;
+    KL1.nsys = active;
+    NL1.sys = sysdev2;
+    NL1.nsys = active;
+  };
   // Single-stream polling overlaps the device: after queuing a chunk the host
   // reads the previous chunk's active count (copied into pinned memory behind
   // that chunk), so the device starts the next chunk while the host waits.  A
@@ -534,14 +556,15 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
   while (it < d->max_iter) {
     const int end = std::min(d->max_iter, it + K);
     if (!split && pb) {
+      shrink();
       if (is_no(op)) NL1.spw = active <= LOW_ACTIVE ? 1 : SPW_HIGH;
       for (int i = it; i < end; ++i) {
         if (is_no(op)) launch_no_apply(NL1);
-        else if (op == PJAC) launch_jacobi(KL, d->precond_steps);
-        else if (op == PSGS) launch_rbsgs(KL, d->precond_steps);
-        if (!pwd) launch_wdots(KL);
-        launch_dir(KL);
-        launch_update(KL);
+        else if (op == PJAC) launch_jacobi(KL1, d->precond_steps);
+        else if (op == PSGS) launch_rbsgs(KL1, d->precond_steps);
+        if (!pwd) launch_wdots(KL1);
+        launch_dir(KL1);
+        launch_update(KL1);
         if (rec && i < rec->m) launch_record(KL, i, rec->m, rec->rec_r, rec->rec_e, rec->ustar);
       }
       it = end;
@@ -560,16 +583,17 @@ fcgno_status solve_impl(const fcgno_model* m, const fcgno_solve_desc* d, const d
       continue;
     }
     if (!split) {
+      shrink();
       // few systems left: one row segment per wave (more, shorter waves keep
       // more of the chip busy); the same bits either way
       if (is_no(op)) NL1.spw = active <= LOW_ACTIVE ? 1 : SPW_HIGH;
       for (int i = it; i < end; ++i) {
         if (is_no(op)) launch_no_apply(NL1);
-        else if (op == PJAC) launch_jacobi(KL, d->precond_steps);
-        else if (op == PSGS) launch_rbsgs(KL, d->precond_steps);
-        if (!pwd) launch_wdots(KL);
-        launch_dir(KL);
-        launch_update(KL);
+        else if (op == PJAC) launch_jacobi(KL1, d->precond_steps);
+        else if (op == PSGS) launch_rbsgs(KL1, d->precond_steps);
+        if (!pwd) launch_wdots(KL1);
+        launch_dir(KL1);
+        launch_update(KL1);
         if (rec && i < rec->m) launch_record(KL, i, rec->m, rec->rec_r, rec->rec_e, rec->ustar);
       }
       it = end;

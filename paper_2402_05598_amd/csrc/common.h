@@ -269,6 +269,9 @@ void launch_export(const SysDev* sys, int nsys, int* flags, double* tres, hipStr
 // the launch table's copies of active flag, iteration index and window size
 // from each system's state (after a host upload of the table)
 void launch_sync_records(const SysDev* sys, int nsys, hipStream_t s);
+// out[0 .. nsys): the records of sys[0 .. nsys) whose systems are active, in
+// order, then records pointing at idle (whose active flag must be zero)
+void launch_compact(const SysDev* sys, int nsys, SysDev* out, SysState* idle, hipStream_t s);
 void launch_zero(void* p, size_t nbytes, hipStream_t s);      // bytes [0, nbytes) = 0
 
 struct NOLaunch {

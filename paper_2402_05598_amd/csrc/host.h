@@ -83,7 +83,7 @@ constexpr int MAX_SUB = 8;   // sub-batches (streams) of one solve
 
 struct Plan {
   size_t total = 0;
-  size_t sysdev = 0, state = 0, counter = 0, hist = 0, part = 0;
+  size_t sysdev = 0, state = 0, counter = 0, hist = 0, part = 0, sysdev2 = 0, idle = 0;
   size_t r = 0, w = 0, P = 0, S = 0, tmp = 0;
   size_t act = 0, logk = 0, Gr = 0, Gp = 0, Hc = 0, Vc = 0, Wh = 0, Vp = 0;
   size_t E64 = 0, Eacc = 0, T = 0, TT = 0, FA = 0, SA = 0, WT = 0, wt_bytes_per_sys = 0, RD = 0, EX = 0;

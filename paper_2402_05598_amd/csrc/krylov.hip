@@ -616,6 +616,52 @@ __global__ __launch_bounds__(256) void k_zero(char* p, size_t nbytes) {
   if (blockIdx.x == 0 && t < nbytes) p[t] = 0;
 }
 
+// Order-preserving compaction of a launch table: the records of the systems
+// still iterating first (their copies of the state refreshed from it), then,
+// up to nsys slots, records whose state is never active (the first record
+// pointing at an idle state).  Kernels find their system by block index and
+// leave at once when it has stopped, so launches sized to the active count
+// skip the stopped systems' blocks; a system's arithmetic does not depend on
+// its slot.  (Pointer parameters stay in the generic address space: the
+// host registers a kernel under the name its own signature mangles to.)
+__global__ __launch_bounds__(256) void k_compact(const SysDev* sys, int nsys, SysDev* out, SysState* idle_state) {
+  constexpr int WORDS = sizeof(SysDev) / 8;
+  static_assert(sizeof(SysDev) % 8 == 0, "records copy as 8-byte words");
+  GLOBAL SysState* idle = (GLOBAL SysState*)idle_state;
+  __shared__ int off[257];
+  const int t = threadIdx.x;
+  const int per = (nsys + 255) / 256;
+  const int b0 = min(nsys, t * per), b1 = min(nsys, b0 + per);
+  int c = 0;
+  for (int b = b0; b < b1; ++b) c += sys[b].st->active ? 1 : 0;
+  off[t + 1] = c;
+  __syncthreads();
+  if (t == 0) {
+    off[0] = 0;
+    for (int q = 1; q <= 256; ++q) off[q] += off[q - 1];
+  }
+  __syncthreads();
+  int j = off[t];
+  for (int b = b0; b < b1; ++b) {
+    const GLOBAL SysState* st = sys[b].st;
+    if (!st->active) continue;
+    const unsigned long long* src = (const unsigned long long*)(sys + b);
+    unsigned long long* dst = (unsigned long long*)(out + j);
+    for (int w = 0; w < WORDS; ++w) dst[w] = src[w];
+    out[j].active = 1;
+    out[j].it = st->i;
+    out[j].mmax = st->m_max;
+    ++j;
+  }
+  for (int q = off[256] + t; q < nsys; q += 256) {
+    const unsigned long long* src = (const unsigned long long*)sys;
+    unsigned long long* dst = (unsigned long long*)(out + q);
+    for (int w = 0; w < WORDS; ++w) dst[w] = src[w];
+    out[q].st = idle;
+    out[q].active = 0;
+  }
+}
+
 // Refresh the launch table's copies of the state (after the host uploaded
 // the table: the host does not know which systems stopped at set-up).
 __global__ __launch_bounds__(64) void k_sync_records(const SysDev* sys, int nsys) {
@@ -666,6 +712,10 @@ void launch_zero(void* p, size_t nbytes, hipStream_t s) {
   const size_t n16 = (nbytes >> 4) + 1;
   const unsigned nb = (unsigned)std::min<size_t>((n16 + 255) / 256, 4096);
   hipLaunchKernelGGL(k_zero, dim3(nb), dim3(256), 0, s, (char*)p, nbytes);
+}
+
+void launch_compact(const SysDev* sys, int nsys, SysDev* out, SysState* idle, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(256), 0, s, sys, nsys, out, idle);
 }
 
 void launch_sync_records(const SysDev* sys, int nsys, hipStream_t s) {

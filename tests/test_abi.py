@@ -181,3 +181,21 @@ def test_model_and_training_arguments_refused_on_the_host():
     lib.fcgno_train_workspace_bytes.restype = ctypes.c_size_t
     assert lib.fcgno_train_workspace_bytes(None, 32, 2, 1) == 0
     assert b"null model" in lib.fcgno_last_error()
+
+
+def test_kernel_parameters_use_generic_pointers():
+    """The host pass sees the global-address-space qualifier as empty, so a
+    kernel parameter carrying it would make the host register the kernel under
+    a name (mangled without the qualifier) that the device code object does
+    not hold, and its first launch would fail.  Qualified pointers belong in
+    kernel bodies and structs, not in kernel parameter lists."""
+    csrc = os.path.join(ROOT, "paper_2402_05598_amd", "csrc")
+    bad = []
+    for fn in sorted(os.listdir(csrc)):
+        if not fn.endswith(".hip"):
+            continue
+        text = open(os.path.join(csrc, fn)).read()
+        for m in re.finditer(r"__global__[^{;]*?\bk_\w+\s*\(([^)]*)\)", text, flags=re.S):
+            if re.search(r"\bGLOBAL\b", m.group(1)):
+                bad.append((fn, m.group(0)[:80]))
+    assert not bad, bad
