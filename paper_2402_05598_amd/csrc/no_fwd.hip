@@ -929,10 +929,12 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
         rr[c] = Rk[2 * (c * C + o)];
         rim[c] = Rk[2 * (c * C + o) + 1];
       }
+      // each term's rounding is written out (one product rounded, the other
+      // fused), so that every variant of the kernel forms the same bits
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        sr += Vr_[c][k2] * rr[c] - Vi_[c][k2] * rim[c];
-        si += Vr_[c][k2] * rim[c] + Vi_[c][k2] * rr[c];
+        sr += __builtin_fmaf(Vr_[c][k2], rr[c], -(Vi_[c][k2] * rim[c]));
+        si += __builtin_fmaf(Vi_[c][k2], rr[c], Vr_[c][k2] * rim[c]);
       }
     }
     __bf16 h, l;
