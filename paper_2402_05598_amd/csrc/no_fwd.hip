@@ -918,6 +918,9 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
   __bf16* WTl = WTh + (size_t)C * M * 64;
   // this block's modes; the last group also clears the slots 16 nkt .. 31
   const int kend = kg + KGN - 1 == nkt - 1 ? 32 : kg * 16 + NK;
+  // mixed values staged per output channel o: word k2 holds the bfloat16
+  // pair of local mode k2 (33 words per row: no bank conflicts)
+  __shared__ uint32_t wst[2][C][33];
   for (int q = t; q < (kend - kg * 16) * C; q += XFM_THREADS) {
     const int kx = kg * 16 + q / C, o = q % C, k2 = kx - kg * 16;
     float sr = 0.f, si = 0.f;
@@ -937,14 +940,26 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
         si += __builtin_fmaf(Vi_[c][k2], rr[c], Vr_[c][k2] * rim[c]);
       }
     }
-    __bf16 h, l;
-    const size_t e = wt_index(o * M + ky, 2 * kx);
-    split_bf(sr, h, l);
-    WTh[e] = h;
-    WTl[e] = l;
-    split_bf(si, h, l);
-    WTh[e + 1] = h;
-    WTl[e + 1] = l;
+    __bf16 h0, l0, h1, l1;
+    split_bf(sr, h0, l0);
+    split_bf(si, h1, l1);
+    // columns 2 kx (Re) and 2 kx + 1 (Im), one 32-bit word per part
+    wst[0][o][k2] = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+    wst[1][o][k2] = (uint32_t)__builtin_bit_cast(uint16_t, l0) | ((uint32_t)__builtin_bit_cast(uint16_t, l1) << 16);
+  }
+  __syncthreads();
+  // each (part, output channel, group of 8 columns) leaves as one 16-byte
+  // store: the 8 columns 32 kg + 8 cg .. + 7 of row o M + ky are contiguous
+  const int ncg = (kend - kg * 16) >> 2;
+  for (int q = t; q < 2 * C * ncg; q += XFM_THREADS) {
+    const int part = q / (C * ncg), o = (q / ncg) % C, cg = q % ncg;
+    const uint32_t* src = &wst[part][o][4 * cg];
+    uint4 v;
+    v.x = src[0];
+    v.y = src[1];
+    v.z = src[2];
+    v.w = src[3];
+    *(uint4*)((part ? WTl : WTh) + wt_index(o * M + ky, 32 * kg + 8 * cg)) = v;
   }
 }
 
