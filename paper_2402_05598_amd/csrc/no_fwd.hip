@@ -707,6 +707,7 @@ __device__ __forceinline__ size_t gp_index(int N, int S, int C, int ky, int x, i
 // once for both groups; used while many systems fill the chip, the same
 // sums either way).
 constexpr int XFM_THREADS = 512;
+constexpr int XFM_CUS = 256;   // compute units of the MI355X
 template <int C, int SEG, int KGN>
 __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16* FA) {
   constexpr int NW = XFM_THREADS / 64, NCT = C / 16, SPW = SEG == 4 ? 2 : 4;
@@ -1676,9 +1677,11 @@ static void apply_pc(const NOLaunch& L) {
       };
       using I1 = std::integral_constant<int, 1>;
       using I2 = std::integral_constant<int, 2>;
-      // both mode groups per block while many systems are active (the first
-      // layer transforms r's row spectrum and always takes one group)
-      if (Sx == 1 && nkt == 2 && l > 0 && L.spw > 1) xfm(I1{}, I2{});
+      // both mode groups per block once one group per block would need more
+      // blocks than the chip has compute units (measured at 512^2, M = 12:
+      // one group is faster up to 10 systems, two from 12 on); the first
+      // layer transforms r's row spectrum and always takes one group
+      if (Sx == 1 && nkt == 2 && l > 0 && L.spw > 1 && L.nsys * L.M * nkt > XFM_CUS) xfm(I1{}, I2{});
       else if (Sx == 1) xfm(I1{}, I1{});
       else if (Sx == 2) xfm(I2{}, I1{});
       else if (Sx == 4) xfm(std::integral_constant<int, 4>{}, I1{});
