@@ -964,15 +964,16 @@ __global__ __launch_bounds__(XFM_THREADS) void k_xfm_bf(SpecArgs a, const __bf16
   }
 }
 
-// x-direction synthesis, bfloat16 operator, one block per (16 rows, half of
-// the output channels when the column tiles split evenly):
+// x-direction synthesis, bfloat16 operator, one block per (16 rows, group of
+// output channels: the grid's y dimension splits the channels into equal
+// groups whose column tiles split evenly):
 // H[x][j] = sum_a W^[a][j] e^{+2 pi i kx_a x / N}, j = o*M + ky, on the matrix
 // cores, written as the rows Hc[x][o][.] = (s Re H, -s Im H) of the block's
 // channels with the inverse normalisation s of the basis (Fourier N^-2 g_ky,
 // g_0 = 1 else 2; sine (2/(N+1))^2), zero past 2M.  Column tile jt covers
-// j = 16 jt .. 16 jt + 15, so the first half of the tiles holds exactly the
-// channels o < C/2.  Waves take the block's tiles in turn; the rows pass
-// through LDS for contiguous stores.
+// j = 16 jt .. 16 jt + 15, so group y of the tiles holds exactly the
+// channels y C/nh .. (y + 1) C/nh - 1.  Waves take the block's tiles in turn;
+// the rows pass through LDS for contiguous stores.
 template <int C, int MP, int TPWV>
 __global__ __launch_bounds__(256) void k_xinv_bf(SpecArgs a, const __bf16* SA) {
   __shared__ __attribute__((aligned(16))) uint16_t tile[16 * C * MP];
@@ -983,7 +984,7 @@ __global__ __launch_bounds__(256) void k_xinv_bf(SpecArgs a, const __bf16* SA) {
   const int nx = min(16, N - x0);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, n16 = lane & 15, g = lane >> 4;
   const int ntile = C * M / 16;   // at most 32 (C, M <= 32, 16)
-  const int nh = gridDim.y;       // 1, or 2 when ntile is even
+  const int nh = gridDim.y;       // channel groups: C and ntile divisible by nh
   const int jt0 = blockIdx.y * (ntile / nh), jt1 = jt0 + ntile / nh;
   const int o0 = blockIdx.y * (C / nh), o1 = o0 + C / nh;
   for (int q = t; q < 16 * C * MP / 8; q += 256) ((uint4*)tile)[q] = uint4{0u, 0u, 0u, 0u};
@@ -1686,9 +1687,17 @@ static void apply_pc(const NOLaunch& L) {
       else if (Sx == 2) xfm(I2{}, I1{});
       else if (Sx == 4) xfm(std::integral_constant<int, 4>{}, I1{});
       else xfm(std::integral_constant<int, 0>{}, I1{});
-      const int halves = (C * L.M / 16) % 2 == 0 ? 2 : 1;   // output-channel halves per 16 rows
+      // output-channel groups per 16 rows: halves when the column tiles split
+      // evenly, then quarters and eighths while the blocks stay within four
+      // per compute unit (measured at 512^2, M = 12: eighths are fastest for
+      // one to three systems, quarters for six, halves from 16 on)
+      const int ntile = C * L.M / 16;
+      int halves = ntile % 2 == 0 ? 2 : 1;
+      while (halves < 8 && ntile % (2 * halves) == 0 && C % (2 * halves) == 0 &&
+             (long)(round16(L.N) / 16) * 2 * halves * L.nsys <= 4 * XFM_CUS)
+        halves *= 2;
       // column tiles per wave (four waves), rounded up to a power of two
-      const int tpw = (C * L.M / 16 / halves + 3) / 4;
+      const int tpw = (ntile / halves + 3) / 4;
       const dim3 xg(round16(L.N) / 16, halves, L.nsys);
       auto xinv = [&](auto mpc) {
         constexpr int MPC = decltype(mpc)::value;
