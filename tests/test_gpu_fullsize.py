@@ -9,7 +9,7 @@ configuration the benchmark times (m = 5, check every 4 iterations) and of a
 1024x1024 system: FP64 residual histories to 1e-10, the BF16 and FP32
 operator's to their operator tolerance, the returned true residual recomputed
 on the CPU, and one system solved alone equal to the same system inside the
-batch."""
+batch (16 systems, and 6 and 12, where the launches take other shapes)."""
 import numpy as np
 import pytest
 import torch
@@ -96,6 +96,32 @@ def test_fcg_full_size_first_iterations(dev, weights):
                            max_iter=its, rtol=1e-300, check_every=4)
             assert torch.equal(u1[0], u[b])
             assert np.array_equal(one["hist"][0], out["hist"][b])
+    model.close()
+
+
+@pytest.mark.parametrize("B", [6, 12])
+def test_bf16_launch_shapes_keep_the_bits(dev, weights, B):
+    """512x512, BF16 operator: the launches change shape with the number of
+    systems (row segments per wave, one or both mode groups per x-transform
+    block, two to eight output-channel groups per synthesis block), the sums
+    never do: six systems take one mode group and quarters, twelve both mode
+    groups and halves, one system alone one group and eighths.  The first
+    and last system of the batch give the bits they give alone."""
+    N, its = 512, 6
+    wb, _ = weights
+    k, f, u0, _ = synth.batch(3, B, N, (10.0, 1000.0))
+    model = fc.Model(wb, C, M, L)
+    kd, fd = torch.from_numpy(k).to(dev), torch.from_numpy(f).to(dev)
+    kw = dict(op="bf16", m_max=5, max_iter=its, rtol=1e-300, check_every=4)
+    print(f"launch shapes B={B}", flush=True)
+    u = torch.from_numpy(u0).to(dev)
+    out = fc.solve(model, kd, fd, u, **kw)
+    assert np.all(out["iters"] == its)
+    for b in (0, B - 1):
+        u1 = torch.from_numpy(u0[b:b + 1]).to(dev)
+        one = fc.solve(model, kd[b:b + 1].contiguous(), fd[b:b + 1].contiguous(), u1, **kw)
+        assert np.array_equal(one["hist"][0], out["hist"][b]), b
+        assert torch.equal(u1[0], u[b]), b
     model.close()
 
 
